@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X HOMG solver on its reference workload.
+
+One step = one pass of the whole hot path over the workload: for each of
+the two FP64 Poisson problems below, u = 0, then MFMG cycles (residual,
+restriction pyramid, fused relax+interpolate iterations, update) until the
+relative residual is <= 1e-10:
+    2D 4097 x 4097, 5-point, f ~ U[-1, 1] (seed 0)
+    3D 257 x 257 x 257, 7-point, f ~ U[-1, 1] (seed 0)
+Inputs are resident in HBM before the timed region.  `value` is grid-node
+updates per second over the whole step (sum over problems of cycles x
+iterations per cycle x nodes, divided by the wall time of the step).
+
+Extra fields: time to 1e-10 per problem, the roofline of the dominant kernel
+(the fused sweep, timed per launch with HIP events on its own stream by the
+library's profiler), and the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to 1e-10 rel. residual + grid-node updates/s, % HBM peak; mixed/learned vs FP64"
+HBM_PEAK_GBS = 8000.0
+PROBLEMS = [("2d_4097", 2, 4097), ("3d_257", 3, 257)]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(d, n, level, mode, elem=8):
+    """Algorithmic (compulsory) bytes of one whole-grid iteration at `level`:
+    the write of e_new over all N = n^d nodes, plus the reads of the previous
+    iterate at the level-m lattice and of the level-m residual (each 1/l^d of
+    N).  Level 0 reads e_old and r at every node.  The first iteration of a
+    cycle does not read e_old; the last adds into u (read + write of FP64 u
+    instead of the store of e)."""
+    N = float(n) ** d
+    l = 1 << level
+    lat = N / float(l) ** d
+    reads = (0.0 if mode & 1 else lat * elem) + lat * elem
+    if mode & 2:
+        return reads + 16.0 * N
+    return reads + N * elem
+
+
+def kernel_symbol(d, kind, level, mode):
+    if kind == "sweep":
+        base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
+        return "%s<double, %d>" % (base, mode)
+    return {"residual": "k_residual_%dd" % d, "restrict": "k_restrict_%dd" % d,
+            "norm": "k_norm2_%dd" % d, "finalize": "k_finalize"}[kind]
+
+
+def kernel_bytes(d, n, entry):
+    kind, level, mode = entry["kind"], entry["level"], entry["mode"]
+    N = float(n) ** d
+    if kind == "sweep":
+        return sweep_bytes(d, n, level, mode) * entry["launches"]
+    if kind == "residual":
+        return (8 + 8 + 8) * N * entry["launches"]  # read u, f; write r (FP64)
+    if kind == "restrict":
+        nf = (n - 1) // (1 << level) + 1
+        Nf = float(nf) ** d
+        return (8 * Nf + 8 * Nf / 2 ** d) * entry["launches"]
+    if kind == "norm":
+        return 8 * N * entry["launches"]
+    return 0.0
+
+
+def cpu_baseline():
+    """The FP64 oracle (as it stands) on a bounded sample: one MFMG cycle of
+    each problem from u = 0 (residual, restriction, all iterations, update,
+    new residual)."""
+    import ctypes
+
+    import workloads as W
+    from oracle import homg as O
+    lib = O.lib()
+    try:
+        cores = int(ctypes.CDLL(O._LIB_PATH).omp_get_max_threads())
+    except Exception:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    total_updates, total_s, parts = 0.0, 0.0, []
+    for name, d, n in PROBLEMS:
+        f = W.uniform(d, n, seed=0)
+        k = O.check_side(n)
+        sweeps = sum(it for _, it in O.default_schedule(k, 4))
+        t0 = time.perf_counter()
+        O.solve(d, n, f, fixed_cycles=1)
+        dt = time.perf_counter() - t0
+        upd = sweeps * float(n) ** d
+        total_updates += upd
+        total_s += dt
+        parts.append("%s: 1 cycle %.1f s" % (name, dt))
+        log("cpu oracle %s: one cycle in %.2f s" % (name, dt))
+    del lib
+    return {"value": total_updates / total_s, "unit": "node-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "one MFMG cycle (MaxI 4) of each problem from u = 0: " + "; ".join(parts)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--max-i", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1108_2045_amd as P
+    import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    probs = []
+    for name, d, n in PROBLEMS:
+        f = torch.from_numpy(W.uniform(d, n, seed=0)).to(dev)
+        u = torch.zeros_like(f)
+        s = P.Solver(d, n, max_i=args.max_i)
+        sweeps_per_cycle = sum(it for _, it in s.schedule())
+        probs.append({"name": name, "d": d, "n": n, "f": f, "u": u, "s": s, "spc": sweeps_per_cycle})
+    torch.cuda.synchronize()
+
+    def step(record):
+        for p in probs:
+            p["u"].zero_()
+            t0 = time.perf_counter()
+            res = p["s"].solve(p["f"], p["u"], tol=1e-10)
+            dt = time.perf_counter() - t0
+            if record is not None:
+                record.setdefault(p["name"], []).append((dt, res))
+
+    for i in range(args.warmup):
+        step(None)
+        log("warmup %d done" % (i + 1))
+    if not args.no_profile:
+        for p in probs:
+            p["s"].set_profiling(True)
+    rec = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(rec)
+        log("step %d done" % (i + 1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    updates = 0.0
+    per = {}
+    for p in probs:
+        runs = rec[p["name"]]
+        cyc = [r["cycles"] for _, r in runs]
+        updates += sum(c * p["spc"] * float(p["n"]) ** p["d"] for c in cyc)
+        times = sorted(dt for dt, _ in runs)
+        per[p["name"]] = {"time_to_1e-10_s": times[len(times) // 2], "cycles": int(np.median(cyc)),
+                          "final_relres": runs[-1][1]["final_relres"],
+                          "sweeps_per_cycle": p["spc"], "nodes": int(p["n"] ** p["d"])}
+    value = updates / elapsed
+
+    roofline, kernels = None, []
+    if not args.no_profile:
+        by_sym = {}
+        for p in probs:
+            for e in p["s"].profile():
+                sym = kernel_symbol(p["d"], e["kind"], e["level"], e["mode"])
+                k = by_sym.setdefault((p["name"], sym), {"launches": 0, "ms": 0.0, "bytes": 0.0})
+                k["launches"] += e["launches"]
+                k["ms"] += e["ms"]
+                k["bytes"] += kernel_bytes(p["d"], p["n"], e)
+        for (pname, sym), k in sorted(by_sym.items(), key=lambda kv: -kv[1]["ms"]):
+            kernels.append({"problem": pname, "kernel": sym, "launches": k["launches"],
+                            "avg_us": 1e3 * k["ms"] / max(k["launches"], 1),
+                            "total_ms": k["ms"],
+                            "alg_GBps": (k["bytes"] / 1e9) / (k["ms"] / 1e3) if k["ms"] > 0 else None})
+        dom = kernels[0]
+        k = by_sym[(dom["problem"], dom["kernel"])]
+        achieved = (k["bytes"] / k["launches"]) / (k["ms"] / k["launches"] / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": dom["kernel"], "problem": dom["problem"],
+                    "bytes_per_launch": k["bytes"] / k["launches"],
+                    "avg_launch_us": 1e3 * k["ms"] / k["launches"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline()
+
+    out = {"metric": METRIC, "value": value, "unit": "node-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "FP64 Poisson to 1e-10 relative residual: 2D 4097^2 5-point and "
+                                  "3D 257^3 7-point, f ~ U[-1,1] seed 0, u0 = 0, zero Dirichlet, "
+                                  "MaxI %d, omega 4/5 (2D) 6/7 (3D)" % args.max_i,
+                      "problems": per, "parallelism": "single GPU"},
+           "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:8]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * homg.h -- C ABI of the MI355X (gfx950) high occupancy multigrid library.
+ *
+ * The method is the high occupancy multigrid (HOMG) of Becerra-Sagredo,
+ * Malaga and Mandujano, "A novel and scalable multigrid algorithm for
+ * many-core architectures" (arXiv:1108.2045).  It solves A u = f (Sec. 2)
+ * for the discretised Poisson problem -Laplace u = f (5-point in 2D, 7-point
+ * in 3D) or the diffusion problem -div(a grad u) = f, with Dirichlet data on
+ * the boundary of the unit square/cube, on nested grids of n = 2^k + 1 nodes
+ * per side.  Every iteration is one whole-grid task: the nodes of the
+ * current level's lattice relax (damped Jacobi, Sec. 2 level-m relaxation)
+ * while every other node interpolates from that lattice (Sec. 2, fused
+ * relaxation and interpolation).  Levels follow the modified full multigrid
+ * schedule (Sec. 2, Fig. 1) and cycles restart on the residual equation
+ * until the requested relative residual (Sec. 2, last paragraph).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays passed in are DEVICE pointers (hipMalloc'd or PyTorch tensors on
+ *    the GPU), dense, C order with x fastest: 2D node (j,i) at j*n + i, 3D
+ *    node (k,j,i) at (k*n + j)*n + i, boundary nodes included.  The caller
+ *    owns them; the library never keeps them after a call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *    of a call is enqueued on it.
+ *  - Every call returns a homg_status; nothing aborts and no C++ exception
+ *    leaves the library.  Arguments are validated before any device work.
+ *    The text of the last error is available from homg_last_error.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef HOMG_H
+#define HOMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct homg_ctx *homg_handle;
+
+typedef enum homg_status {
+    HOMG_OK = 0,
+    HOMG_ERR_INVALID_ARG = 1,   /* bad size, level, pointer, tolerance, option */
+    HOMG_ERR_UNSUPPORTED = 2,   /* valid but not implemented combination */
+    HOMG_ERR_OOM = 3,           /* device allocation failed */
+    HOMG_ERR_WORKSPACE = 4,     /* caller-provided buffer too small */
+    HOMG_ERR_HIP = 5,           /* a HIP runtime call failed (text in homg_last_error) */
+    HOMG_ERR_NUMERICAL = 6,     /* NaN or Inf in the residual norm */
+    HOMG_ERR_NOT_CONVERGED = 7  /* max_cycles reached above tol; u holds the last iterate */
+} homg_status;
+
+/* Discrete operator (Sec. 2 and Sec. 4: A from the Poisson equation; the
+ * diffusion form -div(a grad) uses the harmonic mean of the nodal
+ * coefficient on each face). */
+typedef enum homg_stencil {
+    HOMG_LAPLACE_5PT_2D = 0,
+    HOMG_LAPLACE_7PT_3D = 1,
+    HOMG_DIFFUSION_5PT_2D = 2
+} homg_stencil;
+
+/* Arithmetic of the sweeps and transfers.  The residual r = f - A u, the
+ * update of u and the norms are always FP64 (iterative refinement on the
+ * residual restart of Sec. 2). */
+typedef enum homg_precision {
+    HOMG_FP64 = 0,     /* everything in FP64 */
+    HOMG_FP32_IR = 1,  /* sweeps, restriction and stored e, r in FP32 */
+    HOMG_BF16_IR = 2   /* stored e, r in BF16 (round to nearest even), FP32 arithmetic */
+} homg_precision;
+
+typedef struct homg_options {
+    size_t struct_size;    /* sizeof(homg_options); homg_options_init sets it */
+    double omega;          /* damped-Jacobi weight; <= 0 selects 4/5 (2D), 6/7 (3D) */
+    int max_i;             /* MaxI, the cap on iterations per level; <= 0 selects 4 */
+    int max_cycles;        /* cycles per solve; <= 0 selects 200 */
+    const int *schedule;   /* optional explicit schedule: schedule_len (level, iterations) pairs,
+                              visited in order; NULL selects the MFMG schedule (levels M..0,
+                              iterations min(2^(M-m+1), MaxI)) */
+    int schedule_len;
+    int precision;         /* homg_precision */
+    int temporal_block;    /* 0: one launch per whole-grid iteration; 1: several iterations of a
+                              level per launch where the kernel supports it (same results) */
+    int reserved[7];       /* must be 0 */
+} homg_options;
+
+typedef struct homg_info {
+    int cycles;            /* MFMG cycles executed */
+    int converged;         /* 1 if relres <= tol */
+    double relres0;        /* relative residual of the initial guess */
+    double final_relres;   /* ||f - A u||_2 / ||f||_2 over interior nodes after the last cycle */
+    double *history;       /* optional host array: relres after cycles 0..cycles */
+    int history_cap;       /* its capacity in doubles */
+    long long sweeps;      /* whole-grid iterations executed */
+    long long launches;    /* kernel launches enqueued */
+    int host_syncs;        /* stream synchronisations to read the residual norm */
+} homg_info;
+
+/* Fill *opt with the defaults and set struct_size. */
+void homg_options_init(homg_options *opt);
+
+/*
+ * Create a solver for one grid.  ndim in {2,3}; dims[0..ndim-1] all equal to
+ * n = 2^k + 1 with k >= 1; levels in [1, k] (0 selects k, so the coarsest
+ * lattice is 3^d with one interior unknown); stencil must match ndim.  opt
+ * may be NULL (defaults).  Allocates all device workspace on the current
+ * device (padded internal copies of e and the residual pyramid); *out is set
+ * only on success.
+ */
+homg_status homg_create(homg_handle *out, int ndim, const int64_t *dims, int levels,
+                        homg_stencil stencil, const homg_options *opt);
+
+/* Release the handle and its device memory.  NULL is accepted. */
+homg_status homg_destroy(homg_handle h);
+
+/*
+ * Nodal coefficient a > 0 (dense n^d FP64 device array) for the diffusion
+ * stencil.  Copied into the handle; required before homg_solve for
+ * HOMG_DIFFUSION_5PT_2D.
+ */
+homg_status homg_set_coefficient(homg_handle h, const double *a, void *stream);
+
+/*
+ * Solve A u = f to relative residual tol (Sec. 2: MFMG cycles restarted on
+ * the residual equation).  f: dense FP64 right-hand side (boundary entries
+ * ignored).  u: dense FP64, in = initial guess with the Dirichlet data on the
+ * boundary, out = solution; boundary entries are never written.  Returns
+ * after the first cycle whose relative residual ||f - A u||_2 / ||f||_2
+ * (interior nodes; ||f|| replaced by 1 if f = 0) is <= tol (HOMG_OK), or
+ * HOMG_ERR_NOT_CONVERGED after max_cycles, or HOMG_ERR_NUMERICAL on a
+ * non-finite norm.  tol must be > 0.  info may be NULL.
+ */
+homg_status homg_solve(homg_handle h, const double *f, double *u, double tol,
+                       void *stream, homg_info *info);
+
+/*
+ * Run exactly `cycles` MFMG cycles (no stopping test); otherwise as
+ * homg_solve.  Used to compare with a reference at equal cycle counts.
+ */
+homg_status homg_solve_cycles(homg_handle h, const double *f, double *u, int cycles,
+                              void *stream, homg_info *info);
+
+/*
+ * Residual r = f - A u in FP64 (Sec. 2, the residual equation).  r may be
+ * NULL; otherwise a dense FP64 array that receives r (0 on the boundary).
+ * *relres_out (host) receives ||r||_2 / ||f||_2 over interior nodes.
+ * Synchronises the stream.
+ */
+homg_status homg_residual(homg_handle h, const double *f, const double *u, double *r,
+                          double *relres_out, void *stream);
+
+/* The schedule in use: writes up to cap (level, iterations) pairs into
+ * pairs (host) and returns their count in *len. */
+homg_status homg_get_schedule(homg_handle h, int *pairs, int cap, int *len);
+
+/*
+ * Kernel-level entry points (the steps of one cycle, for testing and
+ * measurement).  Dense FP64 device arrays in and out; inside, the data are
+ * converted to the handle's precision and layout, the same kernels as in
+ * homg_solve run, and the result is widened back to FP64.
+ *
+ * homg_step_restrict: one full-weighting restriction (Sec. 2, restrictions
+ *   as weighted averages) from level `level` to level+1.  r_fine has side
+ *   (n-1)/2^level + 1, r_coarse side (n-1)/2^(level+1) + 1; 0 <= level < levels-1.
+ * homg_step_sweeps: `iters` whole-grid relax+interpolate iterations at level
+ *   `level` (Sec. 2, fused task) starting from e_old (side n, boundary
+ *   entries 0: the error vanishes on the Dirichlet boundary), with level
+ *   right-hand side r_level (side (n-1)/2^level + 1); writes the final iterate
+ *   to e_new (side n, boundary 0).  iters >= 1.
+ * homg_step_cycle: one MFMG cycle on A e = r0 starting from e = 0; ADDS the
+ *   resulting correction e to `acc` (side n, FP64), as the solver adds it to u.
+ */
+homg_status homg_step_restrict(homg_handle h, int level, const double *r_fine,
+                               double *r_coarse, void *stream);
+homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double *e_old,
+                             const double *r_level, double *e_new, void *stream);
+homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *stream);
+
+/*
+ * Per-launch device timing (measurement support).  With profiling enabled,
+ * every kernel the handle launches is bracketed by a pair of HIP events on
+ * the launch's stream, and the elapsed times are accumulated per kernel
+ * class (kind, level, mode) whenever the handle synchronises.  Enabling or
+ * disabling clears the accumulated times.
+ *   kind: 0 norm of f, 1 residual, 2 norm finalisation, 3 restriction from
+ *   `level` to level+1, 4 whole-grid iteration at `level`.
+ *   mode (kind 4): bit 0 = first iteration of a cycle (starts from e = 0),
+ *   bit 1 = last iteration of a cycle (adds e into u).
+ * homg_get_profile synchronises outstanding events, then writes up to cap
+ * entries and their count in *len.
+ */
+typedef struct homg_kernel_time {
+    int kind;
+    int level;
+    int mode;
+    int reserved;
+    long long launches;
+    double ms;
+} homg_kernel_time;
+
+homg_status homg_set_profiling(homg_handle h, int enable);
+homg_status homg_get_profile(homg_handle h, homg_kernel_time *out, int cap, int *len);
+
+/* Text of the last error on h (or of the calling thread if h is NULL). */
+const char *homg_last_error(homg_handle h);
+
+/* Library version string. */
+const char *homg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HOMG_H */

@@ -1,0 +1,613 @@
+// homg_capi.cpp -- C ABI, planner and cycle driver of the MI355X HOMG library.
+//
+// The driver sequences the steps of the method (arXiv:1108.2045, Sec. 2) on
+// one HIP stream:
+//   residual r_0 = f - A u and its norm           (residual equation)
+//   restriction pyramid r_1 .. r_M                (nested partial reductions)
+//   the MFMG schedule of whole-grid iterations    (fused relax+interpolate)
+//   u += e, fused into the last iteration; next residual
+// and restarts cycles until the relative residual reaches the tolerance.
+//
+// Control stays on the device: every kernel of a cycle first reads a
+// device-side `done` flag that the norm kernel sets when the tolerance is
+// met, so the host can enqueue several cycles ahead without a round trip;
+// it synchronises only to read the residual history, sizing each batch of
+// cycles from the contraction observed so far.  Cycles enqueued past
+// convergence do no work and leave u untouched.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/homg.h"
+#include "homg_internal.h"
+
+using namespace homg;
+
+namespace {
+
+thread_local std::string g_err;
+
+}  // namespace
+
+namespace {
+
+enum Kind { K_NORM = 0, K_RESIDUAL = 1, K_FINALIZE = 2, K_RESTRICT = 3, K_SWEEP = 4 };
+
+// Event-pair timing of individual launches, harvested at synchronisation.
+struct Profiler {
+  using Key = std::tuple<int, int, int>;  // kind, level, mode
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<Key, size_t>> pending;  // key, index of the start event
+  std::map<Key, std::pair<long long, double>> acc;
+};
+
+}  // namespace
+
+struct homg_ctx {
+  int d = 0, n = 0, k = 0, levels = 0;
+  int stencil = 0, prec = 0;
+  double omega = 0.8;
+  int max_i = 4, max_cycles = 200, temporal = 0;
+  std::vector<int> sched;  // (level, iterations) pairs
+  int top_level = 0;       // coarsest level the schedule visits
+  int total_sweeps = 0;
+  Lay dl;                  // caller's dense FP64 arrays (side n)
+  Lay el;                  // internal e arrays
+  std::vector<Lay> rl;     // internal residual pyramid, per level
+  std::vector<Lay> al;     // internal coefficient pyramid (FP64), per level
+  std::vector<Lay> cdl;    // dense layouts of the compact levels (step entry points)
+  void* e[2] = {nullptr, nullptr};
+  std::vector<void*> r;
+  std::vector<double*> a;
+  bool has_coef = false;
+  double* partials = nullptr;
+  int npart = 0;
+  DevState* st = nullptr;
+  double* hist = nullptr;
+  int* zero_flag = nullptr;
+  DevState* h_st = nullptr;  // pinned mirrors
+  double* h_hist = nullptr;
+  int device = 0;
+  std::string err;
+  long long launches = 0;
+  Profiler prof;
+};
+
+namespace {
+
+homg_status fail(homg_ctx* h, homg_status s, const std::string& msg) {
+  g_err = msg;
+  if (h) h->err = msg;
+  return s;
+}
+
+#define HIPCHK(h, call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(h, HOMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// Launch with optional event-pair timing under the class (kind, level, mode).
+#define LAUNCH_K(h, s, kind, level, mode, call)                                 \
+  do {                                                                          \
+    size_t ev_ = 0;                                                             \
+    if ((h)->prof.on) {                                                         \
+      if (homg_status pe_ = prof_begin(h, s, &ev_)) return pe_;                 \
+    }                                                                           \
+    HIPCHK(h, call);                                                            \
+    ++(h)->launches;                                                            \
+    if ((h)->prof.on) {                                                         \
+      HIPCHK(h, hipEventRecord((h)->prof.pool[ev_ + 1], s));                    \
+      (h)->prof.pending.push_back({Profiler::Key(kind, level, mode), ev_});     \
+    }                                                                           \
+  } while (0)
+
+#define LAUNCH(h, call)          \
+  do {                           \
+    HIPCHK(h, call);             \
+    ++(h)->launches;             \
+  } while (0)
+
+homg_status prof_begin(homg_ctx* h, hipStream_t s, size_t* ev) {
+  Profiler& p = h->prof;
+  while (p.pool.size() < p.used + 2) {
+    hipEvent_t e;
+    HIPCHK(h, hipEventCreate(&e));
+    p.pool.push_back(e);
+  }
+  *ev = p.used;
+  p.used += 2;
+  HIPCHK(h, hipEventRecord(p.pool[*ev], s));
+  return HOMG_OK;
+}
+
+// Accumulate the elapsed times of all recorded pairs (waits for them).
+homg_status prof_harvest(homg_ctx* h) {
+  Profiler& p = h->prof;
+  for (auto& kv : p.pending) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventSynchronize(p.pool[kv.second + 1]));
+    HIPCHK(h, hipEventElapsedTime(&ms, p.pool[kv.second], p.pool[kv.second + 1]));
+    auto& a = p.acc[kv.first];
+    a.first += 1;
+    a.second += double(ms);
+  }
+  p.pending.clear();
+  p.used = 0;
+  return HOMG_OK;
+}
+
+// Keeps the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int side_exponent(int64_t n) {
+  if (n < 3) return -1;
+  int k = 0;
+  while ((int64_t(1) << (k + 1)) + 1 <= n) ++k;
+  return ((int64_t(1) << k) + 1 == n) ? k : -1;
+}
+
+void free_ctx(homg_ctx* h) {
+  if (!h) return;
+  (void)hipFree(h->e[0]);
+  (void)hipFree(h->e[1]);
+  for (void* p : h->r) (void)hipFree(p);
+  for (double* p : h->a) (void)hipFree(p);
+  (void)hipFree(h->partials);
+  (void)hipFree(h->st);
+  (void)hipFree(h->hist);
+  (void)hipFree(h->zero_flag);
+  if (h->h_st) (void)hipHostFree(h->h_st);
+  if (h->h_hist) (void)hipHostFree(h->h_hist);
+  for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
+  delete h;
+}
+
+homg_status dev_alloc(homg_ctx* h, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(h, HOMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return HOMG_OK;
+}
+
+// Enqueue one MFMG cycle (Sec. 2): restriction pyramid of r_0, the
+// schedule's whole-grid iterations with the last one adding e into acc,
+// then (if f != null) the new residual and its norm as history[cycle].
+homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, const int* done,
+                          hipStream_t s) {
+  for (int m = 0; m < h->top_level; ++m)
+    LAUNCH_K(h, s, K_RESTRICT, m, 0,
+             launch_restrict(h->prec, h->d, h->r[m], h->rl[m], h->r[m + 1], h->rl[m + 1], done, s));
+  int cur = 0, idx = 0;
+  const Lay none;
+  for (size_t p = 0; p < h->sched.size(); p += 2) {
+    const int m = h->sched[p], it = h->sched[p + 1];
+    for (int t = 0; t < it; ++t, ++idx) {
+      int mode = 0;
+      if (idx == 0) mode |= SW_ZERO_OLD;
+      if (idx == h->total_sweeps - 1) mode |= SW_ACCUM;
+      const double* am = h->has_coef ? h->a[m] : nullptr;
+      LAUNCH_K(h, s, K_SWEEP, m, mode,
+               launch_sweep(h->prec, h->d, h->n, m, h->omega, h->e[cur], h->e[1 - cur], h->el,
+                            h->r[m], h->rl[m], am, am ? h->al[m] : none, acc, h->dl, mode, done, s));
+      cur = 1 - cur;
+    }
+  }
+  if (f) {
+    int count = 0;
+    const double* a0 = h->has_coef ? h->a[0] : nullptr;
+    LAUNCH_K(h, s, K_RESIDUAL, 0, 0,
+             launch_residual(h->prec, h->d, h->n, acc, h->dl, f, h->dl, a0, a0 ? h->al[0] : none,
+                             h->r[0], h->rl[0], h->partials, &count, done, s));
+    LAUNCH_K(h, s, K_FINALIZE, 0, 1, launch_finalize(h->partials, count, h->st, h->hist, cycle, 1, s));
+  }
+  return HOMG_OK;
+}
+
+homg_status check_ready(homg_ctx* h) {
+  if (h->stencil == HOMG_DIFFUSION_5PT_2D && !h->has_coef)
+    return fail(h, HOMG_ERR_INVALID_ARG, "diffusion stencil needs homg_set_coefficient first");
+  return HOMG_OK;
+}
+
+homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int fixed_cycles,
+                       void* stream, homg_info* info) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!f || !u) return fail(h, HOMG_ERR_INVALID_ARG, "null f or u");
+  const bool stop_on_tol = fixed_cycles < 0;
+  if (stop_on_tol && !(tol > 0.0)) return fail(h, HOMG_ERR_INVALID_ARG, "tol must be > 0");
+  if (!stop_on_tol && fixed_cycles > h->max_cycles)
+    return fail(h, HOMG_ERR_INVALID_ARG, "cycles exceeds max_cycles of the handle");
+  if (homg_status c = check_ready(h)) return c;
+  DeviceGuard guard(h->device);
+  if (!guard.ok) return fail(h, HOMG_ERR_HIP, "cannot select the handle's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long launches0 = h->launches;
+  const int* done = &h->st->done;
+
+  LAUNCH(h, launch_init_state(h->st, stop_on_tol ? tol : 0.0, stop_on_tol ? 1 : 0, s));
+  int count = 0;
+  LAUNCH_K(h, s, K_NORM, 0, 0, launch_norm2(h->d, h->n, f, h->dl, h->partials, &count, s));
+  LAUNCH_K(h, s, K_FINALIZE, 0, 0, launch_finalize(h->partials, count, h->st, h->hist, 0, 0, s));
+  const double* a0 = h->has_coef ? h->a[0] : nullptr;
+  const Lay none;
+  LAUNCH_K(h, s, K_RESIDUAL, 0, 0,
+           launch_residual(h->prec, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none,
+                           h->r[0], h->rl[0], h->partials, &count, done, s));
+  LAUNCH_K(h, s, K_FINALIZE, 0, 1, launch_finalize(h->partials, count, h->st, h->hist, 0, 1, s));
+
+  const int limit = stop_on_tol ? h->max_cycles : fixed_cycles;
+  int enqueued = 0, syncs = 0;
+  int batch = stop_on_tol ? 2 : limit;
+  for (;;) {
+    const int upto = std::min(limit, enqueued + std::max(batch, 0));
+    for (int c = enqueued + 1; c <= upto; ++c)
+      if (homg_status e = enqueue_cycle(h, f, u, c, done, s)) return e;
+    enqueued = upto;
+    HIPCHK(h, hipMemcpyAsync(h->h_st, h->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(h->h_hist, h->hist, sizeof(double) * (enqueued + 1),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    ++syncs;
+    if (h->prof.on)
+      if (homg_status pe = prof_harvest(h)) return pe;
+    if (h->h_st->done || enqueued >= limit) break;
+    // size the next batch from the observed contraction
+    const int c = h->h_st->cycles;
+    double q = 0.5;
+    if (c >= 2 && h->h_hist[c - 1] > 0) q = h->h_hist[c] / h->h_hist[c - 1];
+    q = std::min(std::max(q, 1e-3), 0.95);
+    const double need = std::log(tol / h->h_hist[c]) / std::log(q);
+    batch = int(std::ceil(std::max(1.0, std::min(need, 16.0))));
+  }
+  const int cycles = std::max(h->h_st->cycles, 0);
+  const double final_rel = h->h_hist[cycles];
+  if (info) {
+    info->cycles = cycles;
+    info->relres0 = h->h_hist[0];
+    info->final_relres = final_rel;
+    info->converged = (h->h_st->done == 1) ? 1 : 0;
+    if (info->history && info->history_cap > 0) {
+      const int nh = std::min(info->history_cap, cycles + 1);
+      std::memcpy(info->history, h->h_hist, sizeof(double) * nh);
+    }
+    info->sweeps = (long long)cycles * h->total_sweeps;
+    info->launches = h->launches - launches0;
+    info->host_syncs = syncs;
+  }
+  if (h->h_st->done == 2) return fail(h, HOMG_ERR_NUMERICAL, "non-finite residual norm");
+  if (stop_on_tol && h->h_st->done != 1)
+    return fail(h, HOMG_ERR_NOT_CONVERGED, "max_cycles reached above tol");
+  return HOMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void homg_options_init(homg_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->struct_size = sizeof(homg_options);
+  opt->omega = 0.0;
+  opt->max_i = 4;
+  opt->max_cycles = 200;
+  opt->precision = HOMG_FP64;
+  opt->temporal_block = 0;
+}
+
+homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int levels,
+                        homg_stencil stencil, const homg_options* opt) {
+  if (!out) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (ndim != 2 && ndim != 3) return fail(nullptr, HOMG_ERR_INVALID_ARG, "ndim must be 2 or 3");
+  if (!dims) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null dims");
+  for (int i = 1; i < ndim; ++i)
+    if (dims[i] != dims[0]) return fail(nullptr, HOMG_ERR_UNSUPPORTED, "all sides must be equal");
+  const int k = side_exponent(dims[0]);
+  if (k < 1) return fail(nullptr, HOMG_ERR_INVALID_ARG, "side must be 2^k + 1 with k >= 1");
+  if ((ndim == 2 && k > 15) || (ndim == 3 && k > 10))
+    return fail(nullptr, HOMG_ERR_UNSUPPORTED, "grid too large");
+  if (levels == 0) levels = k;
+  if (levels < 1 || levels > k) return fail(nullptr, HOMG_ERR_INVALID_ARG, "levels must be in [1, k]");
+  const bool st_ok = (stencil == HOMG_LAPLACE_5PT_2D && ndim == 2) ||
+                     (stencil == HOMG_LAPLACE_7PT_3D && ndim == 3) ||
+                     (stencil == HOMG_DIFFUSION_5PT_2D && ndim == 2);
+  if (!st_ok) {
+    if (stencil == HOMG_LAPLACE_5PT_2D || stencil == HOMG_LAPLACE_7PT_3D || stencil == HOMG_DIFFUSION_5PT_2D)
+      return fail(nullptr, HOMG_ERR_UNSUPPORTED, "stencil does not match ndim");
+    return fail(nullptr, HOMG_ERR_INVALID_ARG, "unknown stencil");
+  }
+  homg_options o;
+  homg_options_init(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(homg_options))
+      return fail(nullptr, HOMG_ERR_INVALID_ARG, "homg_options.struct_size mismatch");
+    o = *opt;
+    for (int i = 0; i < 7; ++i)
+      if (o.reserved[i] != 0) return fail(nullptr, HOMG_ERR_INVALID_ARG, "reserved options must be 0");
+  }
+  double omega = o.omega > 0 ? o.omega : (ndim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
+  if (!(omega > 0.0 && omega <= 1.0)) return fail(nullptr, HOMG_ERR_INVALID_ARG, "omega must be in (0, 1]");
+  const int max_i = o.max_i > 0 ? o.max_i : 4;
+  const int max_cycles = o.max_cycles > 0 ? o.max_cycles : 200;
+  if (max_cycles > 100000) return fail(nullptr, HOMG_ERR_INVALID_ARG, "max_cycles too large");
+  if (o.precision < HOMG_FP64 || o.precision > HOMG_BF16_IR)
+    return fail(nullptr, HOMG_ERR_INVALID_ARG, "unknown precision");
+  if (o.temporal_block < 0) return fail(nullptr, HOMG_ERR_INVALID_ARG, "temporal_block must be >= 0");
+
+  std::vector<int> sched;
+  if (o.schedule) {
+    if (o.schedule_len < 1 || o.schedule_len > 4096)
+      return fail(nullptr, HOMG_ERR_INVALID_ARG, "schedule_len must be in [1, 4096]");
+    for (int i = 0; i < o.schedule_len; ++i) {
+      const int m = o.schedule[2 * i], it = o.schedule[2 * i + 1];
+      if (m < 0 || m >= levels) return fail(nullptr, HOMG_ERR_INVALID_ARG, "schedule level out of range");
+      if (it < 1 || it > 1 << 20) return fail(nullptr, HOMG_ERR_INVALID_ARG, "schedule iterations must be >= 1");
+      sched.push_back(m);
+      sched.push_back(it);
+    }
+  } else {
+    // MFMG (Sec. 2, Fig. 1): two iterations on the coarsest level, doubling
+    // per finer level, capped at MaxI.
+    const int M = levels - 1;
+    for (int m = M; m >= 0; --m) {
+      const int64_t want = int64_t(1) << std::min(M - m + 1, 30);
+      sched.push_back(m);
+      sched.push_back(int(std::min<int64_t>(want, max_i)));
+    }
+  }
+
+  homg_ctx* h = new (std::nothrow) homg_ctx;
+  if (!h) return fail(nullptr, HOMG_ERR_OOM, "host allocation failed");
+  h->d = ndim;
+  h->n = int(dims[0]);
+  h->k = k;
+  h->levels = levels;
+  h->stencil = stencil;
+  h->prec = o.precision;
+  h->omega = omega;
+  h->max_i = max_i;
+  h->max_cycles = max_cycles;
+  h->temporal = o.temporal_block;
+  h->sched = sched;
+  h->top_level = 0;
+  h->total_sweeps = 0;
+  for (size_t p = 0; p < sched.size(); p += 2) {
+    h->top_level = std::max(h->top_level, sched[p]);
+    h->total_sweeps += sched[p + 1];
+  }
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, HOMG_ERR_HIP, "hipGetDevice failed");
+  }
+  const int eb = prec_bytes(h->prec);
+  h->dl = dense_layout(ndim, h->n);
+  h->el = padded_layout(ndim, h->n, eb);
+  for (int m = 0; m < levels; ++m) {
+    const int side = (h->n - 1) / (1 << m) + 1;
+    h->rl.push_back(padded_layout(ndim, side, eb));
+    h->al.push_back(padded_layout(ndim, side, 8));
+    h->cdl.push_back(dense_layout(ndim, side));
+  }
+  homg_status stt = HOMG_OK;
+  for (int b = 0; b < 2 && !stt; ++b) stt = dev_alloc(h, &h->e[b], size_t(h->el.alloc) * eb);
+  h->r.assign(levels, nullptr);
+  for (int m = 0; m < levels && !stt; ++m) stt = dev_alloc(h, &h->r[m], size_t(h->rl[m].alloc) * eb);
+  h->npart = partials_bound(ndim, h->n);
+  if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->partials), sizeof(double) * h->npart);
+  if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->st), sizeof(DevState));
+  if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->hist), sizeof(double) * (max_cycles + 1));
+  if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->zero_flag), sizeof(int) * 64);
+  if (stt) {
+    std::string msg = h->err;
+    free_ctx(h);
+    return fail(nullptr, stt, msg);
+  }
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&h->h_st), sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&h->h_hist), sizeof(double) * (max_cycles + 1), hipHostMallocDefault) == hipSuccess;
+  // e's boundary nodes are never written: zero both buffers once.
+  ok = ok && hipMemset(h->e[0], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
+       hipMemset(h->e[1], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
+       hipMemset(h->zero_flag, 0, sizeof(int) * 64) == hipSuccess;
+  for (int m = 0; m < levels && ok; ++m) ok = hipMemset(h->r[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    free_ctx(h);
+    return fail(nullptr, HOMG_ERR_HIP, "workspace initialisation failed");
+  }
+  *out = h;
+  return HOMG_OK;
+}
+
+homg_status homg_destroy(homg_handle h) {
+  if (!h) return HOMG_OK;
+  DeviceGuard guard(h->device);
+  (void)hipDeviceSynchronize();
+  free_ctx(h);
+  return HOMG_OK;
+}
+
+homg_status homg_set_coefficient(homg_handle h, const double* a, void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!a) return fail(h, HOMG_ERR_INVALID_ARG, "null coefficient");
+  if (h->stencil != HOMG_DIFFUSION_5PT_2D)
+    return fail(h, HOMG_ERR_INVALID_ARG, "coefficient only applies to the diffusion stencil");
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->a.empty()) {
+    h->a.assign(h->levels, nullptr);
+    for (int m = 0; m < h->levels; ++m)
+      if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->a[m]), sizeof(double) * h->al[m].alloc))
+        return e;
+    for (int m = 0; m < h->levels; ++m)
+      HIPCHK(h, hipMemsetAsync(h->a[m], 0, sizeof(double) * h->al[m].alloc, s));
+  }
+  // level-m lattice coefficients: the nodal values sampled every 2^m nodes
+  for (int m = 0; m < h->levels; ++m)
+    LAUNCH(h, launch_sample(h->d, a, h->dl, 1 << m, h->a[m], h->al[m], s));
+  h->has_coef = true;
+  return HOMG_OK;
+}
+
+homg_status homg_solve(homg_handle h, const double* f, double* u, double tol, void* stream,
+                       homg_info* info) {
+  return solve_impl(h, f, u, tol, -1, stream, info);
+}
+
+homg_status homg_solve_cycles(homg_handle h, const double* f, double* u, int cycles, void* stream,
+                              homg_info* info) {
+  if (cycles < 0) return fail(h, HOMG_ERR_INVALID_ARG, "cycles must be >= 0");
+  return solve_impl(h, f, u, 1.0, cycles, stream, info);
+}
+
+homg_status homg_residual(homg_handle h, const double* f, const double* u, double* r,
+                          double* relres_out, void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!f || !u) return fail(h, HOMG_ERR_INVALID_ARG, "null f or u");
+  if (homg_status c = check_ready(h)) return c;
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int count = 0;
+  LAUNCH(h, launch_init_state(h->st, 0.0, 0, s));
+  LAUNCH(h, launch_norm2(h->d, h->n, f, h->dl, h->partials, &count, s));
+  LAUNCH(h, launch_finalize(h->partials, count, h->st, h->hist, 0, 0, s));
+  const double* a0 = h->has_coef ? h->a[0] : nullptr;
+  const Lay none;
+  if (r)
+    LAUNCH(h, launch_residual(PREC_F64, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none,
+                              r, h->dl, h->partials, &count, h->zero_flag, s));
+  else
+    LAUNCH(h, launch_residual(h->prec, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none,
+                              h->r[0], h->rl[0], h->partials, &count, h->zero_flag, s));
+  LAUNCH(h, launch_finalize(h->partials, count, h->st, h->hist, 0, 1, s));
+  HIPCHK(h, hipMemcpyAsync(h->h_hist, h->hist, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (relres_out) *relres_out = h->h_hist[0];
+  return HOMG_OK;
+}
+
+homg_status homg_get_schedule(homg_handle h, int* pairs, int cap, int* len) {
+  if (!h || !len) return fail(h, HOMG_ERR_INVALID_ARG, "null argument");
+  const int np = int(h->sched.size() / 2);
+  *len = np;
+  if (pairs) {
+    if (cap < np) return fail(h, HOMG_ERR_WORKSPACE, "schedule buffer too small");
+    for (int i = 0; i < 2 * np; ++i) pairs[i] = h->sched[i];
+  }
+  return HOMG_OK;
+}
+
+homg_status homg_step_restrict(homg_handle h, int level, const double* r_fine, double* r_coarse,
+                               void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!r_fine || !r_coarse) return fail(h, HOMG_ERR_INVALID_ARG, "null array");
+  if (level < 0 || level >= h->levels - 1) return fail(h, HOMG_ERR_INVALID_ARG, "level out of range");
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LAUNCH(h, launch_pack(h->prec, h->d, r_fine, h->cdl[level], h->r[level], h->rl[level], s));
+  LAUNCH(h, launch_restrict(h->prec, h->d, h->r[level], h->rl[level], h->r[level + 1], h->rl[level + 1],
+                            h->zero_flag, s));
+  LAUNCH(h, launch_unpack(h->prec, h->d, h->r[level + 1], h->rl[level + 1], r_coarse, h->cdl[level + 1], s));
+  return HOMG_OK;
+}
+
+homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* e_old,
+                             const double* r_level, double* e_new, void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!e_old || !r_level || !e_new) return fail(h, HOMG_ERR_INVALID_ARG, "null array");
+  if (level < 0 || level >= h->levels) return fail(h, HOMG_ERR_INVALID_ARG, "level out of range");
+  if (iters < 1) return fail(h, HOMG_ERR_INVALID_ARG, "iters must be >= 1");
+  if (homg_status c = check_ready(h)) return c;
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LAUNCH(h, launch_pack(h->prec, h->d, e_old, h->dl, h->e[0], h->el, s));
+  LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
+  int cur = 0;
+  const double* am = h->has_coef ? h->a[level] : nullptr;
+  const Lay none;
+  for (int t = 0; t < iters; ++t) {
+    LAUNCH_K(h, s, K_SWEEP, level, 0,
+             launch_sweep(h->prec, h->d, h->n, level, h->omega, h->e[cur], h->e[1 - cur], h->el,
+                           h->r[level], h->rl[level], am, am ? h->al[level] : none, nullptr, h->dl, 0,
+                           h->zero_flag, s));
+    cur = 1 - cur;
+  }
+  LAUNCH(h, launch_unpack(h->prec, h->d, h->e[cur], h->el, e_new, h->dl, s));
+  // the solver relies on zero boundaries in both e buffers
+  const size_t eb = size_t(prec_bytes(h->prec));
+  HIPCHK(h, hipMemsetAsync(h->e[0], 0, size_t(h->el.alloc) * eb, s));
+  HIPCHK(h, hipMemsetAsync(h->e[1], 0, size_t(h->el.alloc) * eb, s));
+  return HOMG_OK;
+}
+
+homg_status homg_step_cycle(homg_handle h, const double* r0, double* acc, void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!r0 || !acc) return fail(h, HOMG_ERR_INVALID_ARG, "null array");
+  if (homg_status c = check_ready(h)) return c;
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LAUNCH(h, launch_pack(h->prec, h->d, r0, h->dl, h->r[0], h->rl[0], s));
+  return enqueue_cycle(h, nullptr, acc, 1, h->zero_flag, s);
+}
+
+homg_status homg_set_profiling(homg_handle h, int enable) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  DeviceGuard guard(h->device);
+  if (homg_status e = prof_harvest(h)) return e;
+  h->prof.acc.clear();
+  h->prof.on = enable != 0;
+  return HOMG_OK;
+}
+
+homg_status homg_get_profile(homg_handle h, homg_kernel_time* out, int cap, int* len) {
+  if (!h || !len) return fail(h, HOMG_ERR_INVALID_ARG, "null argument");
+  DeviceGuard guard(h->device);
+  if (homg_status e = prof_harvest(h)) return e;
+  *len = int(h->prof.acc.size());
+  if (out) {
+    if (cap < *len) return fail(h, HOMG_ERR_WORKSPACE, "profile buffer too small");
+    int i = 0;
+    for (auto& kv : h->prof.acc) {
+      out[i].kind = std::get<0>(kv.first);
+      out[i].level = std::get<1>(kv.first);
+      out[i].mode = std::get<2>(kv.first);
+      out[i].reserved = 0;
+      out[i].launches = kv.second.first;
+      out[i].ms = kv.second.second;
+      ++i;
+    }
+  }
+  return HOMG_OK;
+}
+
+const char* homg_last_error(homg_handle h) {
+  if (h) return h->err.c_str();
+  return g_err.c_str();
+}
+
+const char* homg_version(void) { return "homg-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

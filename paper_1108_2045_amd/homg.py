@@ -1,0 +1,227 @@
+"""Thin ctypes binding of libhomg.so (the C ABI declared in include/homg.h).
+
+Argument marshalling only: tensors are passed as device pointers, the
+current torch stream as the hipStream_t, and every step of the method runs
+in the library's HIP kernels.  There is no fallback: if the library is
+missing or fails to load, importing this module raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhomg.so")
+
+HOMG_OK = 0
+STATUS_NAMES = {
+    0: "HOMG_OK", 1: "HOMG_ERR_INVALID_ARG", 2: "HOMG_ERR_UNSUPPORTED", 3: "HOMG_ERR_OOM",
+    4: "HOMG_ERR_WORKSPACE", 5: "HOMG_ERR_HIP", 6: "HOMG_ERR_NUMERICAL", 7: "HOMG_ERR_NOT_CONVERGED",
+}
+LAPLACE_5PT_2D, LAPLACE_7PT_3D, DIFFUSION_5PT_2D = 0, 1, 2
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class HomgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("omega", ctypes.c_double),
+                ("max_i", ctypes.c_int), ("max_cycles", ctypes.c_int),
+                ("schedule", ctypes.POINTER(ctypes.c_int)), ("schedule_len", ctypes.c_int),
+                ("precision", ctypes.c_int), ("temporal_block", ctypes.c_int),
+                ("reserved", ctypes.c_int * 7)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("converged", ctypes.c_int),
+                ("relres0", ctypes.c_double), ("final_relres", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+                ("sweeps", ctypes.c_longlong), ("launches", ctypes.c_longlong),
+                ("host_syncs", ctypes.c_int)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("level", ctypes.c_int), ("mode", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double)]
+
+
+KIND_NAMES = {0: "norm", 1: "residual", 2: "finalize", 3: "restrict", 4: "sweep"}
+
+
+def load_library(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("libhomg.so not built (run __graft_entry__.build() or "
+                          "python -m paper_1108_2045_amd.build): " + path)
+    L = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)
+    H = ctypes.c_void_p
+    L.homg_options_init.argtypes = [ctypes.POINTER(Options)]
+    L.homg_options_init.restype = None
+    L.homg_create.argtypes = [ctypes.POINTER(H), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]
+    L.homg_destroy.argtypes = [H]
+    L.homg_set_coefficient.argtypes = [H, dp, vp]
+    L.homg_solve.argtypes = [H, dp, dp, ctypes.c_double, vp, ctypes.POINTER(Info)]
+    L.homg_solve_cycles.argtypes = [H, dp, dp, ctypes.c_int, vp, ctypes.POINTER(Info)]
+    L.homg_residual.argtypes = [H, dp, dp, dp, ctypes.POINTER(ctypes.c_double), vp]
+    L.homg_get_schedule.argtypes = [H, ip, ctypes.c_int, ip]
+    L.homg_step_restrict.argtypes = [H, ctypes.c_int, dp, dp, vp]
+    L.homg_step_sweeps.argtypes = [H, ctypes.c_int, ctypes.c_int, dp, dp, dp, vp]
+    L.homg_step_cycle.argtypes = [H, dp, dp, vp]
+    L.homg_set_profiling.argtypes = [H, ctypes.c_int]
+    L.homg_get_profile.argtypes = [H, ctypes.POINTER(KernelTime), ctypes.c_int, ip]
+    L.homg_last_error.argtypes = [H]
+    L.homg_last_error.restype = ctypes.c_char_p
+    L.homg_version.argtypes = []
+    L.homg_version.restype = ctypes.c_char_p
+    for name in ("homg_create", "homg_destroy", "homg_set_coefficient", "homg_solve",
+                 "homg_solve_cycles", "homg_residual", "homg_get_schedule", "homg_step_restrict",
+                 "homg_step_sweeps", "homg_step_cycle", "homg_set_profiling", "homg_get_profile"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _ptr(t, dtype=None):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("arrays must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("arrays must be contiguous (C order, x fastest)")
+    if t.dtype != (dtype or torch.float64):
+        raise ValueError("arrays must be float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One HOMG solver for a d-dimensional grid of side n = 2^k + 1."""
+
+    def __init__(self, ndim, n, levels=0, stencil=None, omega=0.0, max_i=4, max_cycles=200,
+                 schedule=None, precision="fp64", temporal_block=0):
+        L = lib()
+        if stencil is None:
+            stencil = LAPLACE_5PT_2D if ndim == 2 else LAPLACE_7PT_3D
+        opt = Options()
+        L.homg_options_init(ctypes.byref(opt))
+        opt.omega = omega
+        opt.max_i = max_i
+        opt.max_cycles = max_cycles
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opt.temporal_block = temporal_block
+        self._sched_buf = None
+        if schedule is not None:
+            flat = [int(v) for pair in schedule for v in pair]
+            self._sched_buf = (ctypes.c_int * len(flat))(*flat)
+            opt.schedule = self._sched_buf
+            opt.schedule_len = len(schedule)
+        dims = (ctypes.c_int64 * ndim)(*([n] * ndim))
+        h = ctypes.c_void_p()
+        st = L.homg_create(ctypes.byref(h), ndim, dims, levels, stencil, ctypes.byref(opt))
+        if st != HOMG_OK:
+            raise HomgError(st, L.homg_last_error(None).decode())
+        self._h = h
+        self.ndim, self.n, self.max_cycles = ndim, n, max_cycles
+        self.precision = precision
+
+    def _check(self, st):
+        if st != HOMG_OK:
+            raise HomgError(st, lib().homg_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().homg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_coefficient(self, a, stream=None):
+        self._check(lib().homg_set_coefficient(self._h, _ptr(a), _stream(stream)))
+
+    def _info(self):
+        info = Info()
+        hist = (ctypes.c_double * (self.max_cycles + 1))()
+        info.history = hist
+        info.history_cap = self.max_cycles + 1
+        return info, hist
+
+    @staticmethod
+    def _result(info, hist):
+        return {"cycles": info.cycles, "converged": bool(info.converged), "relres0": info.relres0,
+                "final_relres": info.final_relres, "history": list(hist[:info.cycles + 1]),
+                "sweeps": info.sweeps, "launches": info.launches, "host_syncs": info.host_syncs}
+
+    def solve(self, f, u, tol=1e-10, stream=None, raise_on_status=True):
+        info, hist = self._info()
+        st = lib().homg_solve(self._h, _ptr(f), _ptr(u), tol, _stream(stream), ctypes.byref(info))
+        out = self._result(info, hist)
+        out["status"] = st
+        if raise_on_status:
+            self._check(st)
+        return out
+
+    def solve_cycles(self, f, u, cycles, stream=None):
+        info, hist = self._info()
+        st = lib().homg_solve_cycles(self._h, _ptr(f), _ptr(u), cycles, _stream(stream), ctypes.byref(info))
+        self._check(st)
+        return self._result(info, hist)
+
+    def residual(self, f, u, r=None, stream=None):
+        rel = ctypes.c_double()
+        self._check(lib().homg_residual(self._h, _ptr(f), _ptr(u), _ptr(r), ctypes.byref(rel), _stream(stream)))
+        return rel.value
+
+    def schedule(self):
+        n = ctypes.c_int()
+        self._check(lib().homg_get_schedule(self._h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_int * (2 * n.value))()
+        self._check(lib().homg_get_schedule(self._h, buf, n.value, ctypes.byref(n)))
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+
+    def set_profiling(self, enable=True):
+        self._check(lib().homg_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self):
+        """[{kind, level, mode, launches, ms}] accumulated since profiling was enabled."""
+        n = ctypes.c_int()
+        self._check(lib().homg_get_profile(self._h, None, 0, ctypes.byref(n)))
+        buf = (KernelTime * max(n.value, 1))()
+        self._check(lib().homg_get_profile(self._h, buf, n.value, ctypes.byref(n)))
+        return [{"kind": KIND_NAMES.get(b.kind, b.kind), "level": b.level, "mode": b.mode,
+                 "launches": b.launches, "ms": b.ms} for b in buf[:n.value]]
+
+    def step_restrict(self, level, r_fine, r_coarse, stream=None):
+        self._check(lib().homg_step_restrict(self._h, level, _ptr(r_fine), _ptr(r_coarse), _stream(stream)))
+
+    def step_sweeps(self, level, iters, e_old, r_level, e_new, stream=None):
+        self._check(lib().homg_step_sweeps(self._h, level, iters, _ptr(e_old), _ptr(r_level),
+                                           _ptr(e_new), _stream(stream)))
+
+    def step_cycle(self, r0, acc, stream=None):
+        self._check(lib().homg_step_cycle(self._h, _ptr(r0), _ptr(acc), _stream(stream)))
+
+
+def version():
+    return lib().homg_version().decode()

@@ -1,0 +1,406 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Element by element on the same seeded inputs.  Tolerances, derived from the
+arithmetic:
+  * FP64 kernels: a few ulp per node formula; single steps within
+    1e-12 * max|expected|, whole solves within 1e-11 relative in u at the
+    same cycle count (the benchmark spec's bound).
+  * FP32 steps: within 1e-5 * max|expected| (a few FP32 ulp, 2^-24 each).
+  * BF16 steps: inputs are made exactly representable in BF16; the GPU
+    rounds its FP32 result to BF16 and the expectation is the FP64 result
+    rounded to BF16, so the two may sit one BF16 ulp apart (at most 2^-7
+    relative): within 2^-7 * |expected| + 1e-5 * max|expected| per node.
+  * Residual history: within 1e-6 relative plus the rounding floor of the
+    residual itself, 16 eps || |A| |u| ||_2 / ||f||_2, since two correct
+    FP64 residuals of nearly the same u differ by that much.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import homg as O
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def B(torch_cuda):
+    import paper_1108_2045_amd as P
+    return P
+
+
+def dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rand_interior(rng, d, n):
+    x = np.zeros((n,) * d)
+    x[(slice(1, -1),) * d] = rng.standard_normal((n - 2,) * d)
+    return x
+
+
+def representable(torch, x, prec):
+    """Round test inputs so the GPU's conversion to `prec` is exact."""
+    if prec == "fp64":
+        return x
+    dt = torch.float32 if prec == "fp32" else torch.bfloat16
+    return torch.from_numpy(x).to(dt).to(torch.float64).numpy()
+
+
+def step_tol(prec, want):
+    mx = np.max(np.abs(want)) if want.size else 0.0
+    if prec == "fp64":
+        return 1e-12 * mx + 1e-300
+    if prec == "fp32":
+        return 1e-5 * mx + 1e-300
+    return 2.0 ** -7 * np.abs(want) + 1e-5 * mx + 1e-300
+
+
+def abs_A_u(d, n, u):
+    """|A| |u|: (2d|u_p| + sum |u_q|) / h^2 on interior nodes."""
+    h = 1.0 / (n - 1)
+    au = np.abs(u)
+    inn = (slice(1, -1),) * d
+    out = 2 * d * au[inn]
+    for axis in range(d):
+        for s in (-1, 1):
+            sl = [slice(1, -1)] * d
+            sl[axis] = slice(1 + s, n - 1 + s)
+            out = out + au[tuple(sl)]
+    return out / (h * h)
+
+
+def relres_floor(d, n, u, f):
+    fn = np.linalg.norm(f[(slice(1, -1),) * d])
+    return 16 * EPS * np.linalg.norm(abs_A_u(d, n, u)) / (fn if fn > 0 else 1.0)
+
+
+# ------------------------------------------------------------- single steps
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d,n", [(2, 257), (2, 1025), (3, 33), (3, 129)])
+def test_step_restrict(B, torch_cuda, d, n, prec):
+    torch = torch_cuda
+    rng = np.random.default_rng(100 + n + d)
+    k = O.check_side(n)
+    s = B.Solver(d, n, precision=prec)
+    for level in sorted({0, 1, k - 2}):
+        nf = (n - 1) // (1 << level) + 1
+        nc = (nf - 1) // 2 + 1
+        say("restrict d=%d n=%d level=%d prec=%s" % (d, n, level, prec))
+        rf = representable(torch, rand_interior(rng, d, nf), prec)
+        out = torch.zeros((nc,) * d, dtype=torch.float64, device="cuda")
+        s.step_restrict(level, dev(torch, rf), out)
+        torch.cuda.synchronize()
+        want = O.restrict(d, rf)
+        got = host(out)
+        inn = (slice(1, -1),) * d
+        tol = np.broadcast_to(step_tol(prec, want), want.shape)
+        assert np.all(np.abs(got[inn] - want[inn]) <= tol[inn])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d,n", [(2, 257), (2, 1025), (3, 33), (3, 65)])
+def test_step_sweeps_every_level(B, torch_cuda, d, n, prec):
+    torch = torch_cuda
+    rng = np.random.default_rng(200 + n + d)
+    k = O.check_side(n)
+    s = B.Solver(d, n, precision=prec)
+    omega = O.default_omega(d)
+    for level in range(k):
+        nm = (n - 1) // (1 << level) + 1
+        for iters in (1, 3):
+            say("sweeps d=%d n=%d level=%d iters=%d prec=%s" % (d, n, level, iters, prec))
+            e0 = representable(torch, rand_interior(rng, d, n), prec)
+            rm = representable(torch, rand_interior(rng, d, nm), prec)
+            out = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+            s.step_sweeps(level, iters, dev(torch, e0), dev(torch, rm), out)
+            torch.cuda.synchronize()
+            want = e0
+            for _ in range(iters):
+                want = O.sweep(d, n, level, omega, rm, want)
+                if prec != "fp64":
+                    # the GPU stores every iterate in the working precision
+                    want = representable(torch, want, prec)
+            got = host(out)
+            tol = step_tol(prec, want)
+            if iters > 1 and prec == "fp32":
+                tol = tol * 4
+            if iters > 1 and prec == "bf16":
+                # a one-ulp difference in an intermediate BF16 rounding propagates
+                tol = 2.0 ** -7 * iters * np.max(np.abs(want))
+            assert np.all(np.abs(got - want) <= tol), (level, iters, np.max(np.abs(got - want)))
+
+
+@pytest.mark.parametrize("d,n,max_i", [(2, 129, 4), (2, 513, 2), (2, 257, 32), (3, 33, 4), (3, 65, 8)])
+def test_step_cycle_fp64(B, torch_cuda, d, n, max_i):
+    torch = torch_cuda
+    say("cycle d=%d n=%d max_i=%d" % (d, n, max_i))
+    rng = np.random.default_rng(300 + n)
+    r0 = rand_interior(rng, d, n)
+    s = B.Solver(d, n, max_i=max_i)
+    acc = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+    s.step_cycle(dev(torch, r0), acc)
+    torch.cuda.synchronize()
+    k = O.check_side(n)
+    want = O.mfmg_cycle(d, n, r0, O.default_schedule(k, max_i), O.default_omega(d))
+    got = host(acc)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_schedule_matches_oracle(B, torch_cuda):
+    for d, n, max_i in ((2, 129, 4), (2, 4097, 4), (3, 257, 32), (2, 1025, 2)):
+        k = O.check_side(n)
+        if d == 3 and n > 257:
+            continue
+        s = B.Solver(d, n, max_i=max_i)
+        assert s.schedule() == O.default_schedule(k, max_i)
+
+
+# ------------------------------------------------------------- whole solves
+
+def solve_and_compare(B, torch, d, n, f, *, a=None, max_i=4, tol=1e-10, schedule=None, levels=0,
+                      stencil=None):
+    say("solve d=%d n=%d max_i=%d levels=%d var=%s" % (d, n, max_i, levels, a is not None))
+    s = B.Solver(d, n, max_i=max_i, schedule=schedule, levels=levels, stencil=stencil)
+    if a is not None:
+        s.set_coefficient(dev(torch, a))
+    u = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+    res = s.solve(dev(torch, f), u, tol=tol)
+    torch.cuda.synchronize()
+    ug = host(u)
+    lv = levels if levels else None
+    uo, ho = O.solve(d, n, f, a=a, max_i=max_i, fixed_cycles=res["cycles"], schedule=schedule, levels=lv)
+    # u parity at the same cycle count
+    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    assert rel <= 1e-11, rel
+    # residual history
+    floor = relres_floor(d, n, uo, f)
+    hg = np.array(res["history"])
+    assert len(hg) == len(ho)
+    assert np.all(np.abs(hg - np.array(ho)) <= 1e-6 * np.array(ho) + floor), (hg, ho, floor)
+    # final residual recomputed by the oracle from the GPU's u
+    _, s2 = O.residual(d, n, f, ug, a)
+    fn = np.sqrt(O.norm2_interior(d, n, f))
+    assert np.sqrt(s2) / fn <= tol * (1 + 1e-6) + floor
+    assert res["converged"]
+    return ug, res
+
+
+def test_sine_problem_129_fp64(B, torch_cuda):
+    """2D -Lap u = 2 pi^2 sin sin on 129^2, omega 4/5, down to the 3x3 lattice."""
+    torch = torch_cuda
+    n = 129
+    f = W.sine2d(n)
+    ug, res = solve_and_compare(B, torch, 2, n, f)
+    from oracle import textbook as T
+    lam = T.laplace_eigenvalue(2, n, (1, 1))
+    uh = (2 * np.pi ** 2 / lam) * W.sine2d_exact(n)
+    assert np.linalg.norm(ug - uh) / np.linalg.norm(uh) <= 1e-9
+    assert res["final_relres"] <= 1e-10
+
+
+@pytest.mark.parametrize("d,n,seed,max_i", [(2, 257, 1, 4), (2, 1025, 2, 4), (2, 513, 3, 32),
+                                            (3, 33, 4, 4), (3, 65, 5, 4), (3, 129, 6, 8)])
+def test_uniform_solves_fp64(B, torch_cuda, d, n, seed, max_i):
+    solve_and_compare(B, torch_cuda, d, n, W.uniform(d, n, seed=seed), max_i=max_i)
+
+
+def test_normal_source_and_partial_levels(B, torch_cuda):
+    f = W.normal(3, 65, seed=7)
+    solve_and_compare(B, torch_cuda, 3, 65, f, levels=4)
+
+
+def test_explicit_zigzag_schedule(B, torch_cuda):
+    n = 129
+    sched = [(6, 2), (5, 2), (6, 1), (5, 2), (4, 2), (3, 2), (4, 1), (3, 2), (2, 2), (1, 2), (0, 2)]
+    solve_and_compare(B, torch_cuda, 2, n, W.uniform(2, n, seed=8), schedule=sched)
+
+
+@pytest.mark.parametrize("n", [129, 257])
+def test_variable_coefficient_fp64(B, torch_cuda, n):
+    a, f = W.grf_problem(n, seed=9)
+    solve_and_compare(B, torch_cuda, 2, n, f, a=a, stencil=B.DIFFUSION_5PT_2D)
+
+
+def test_golden_histories(B, torch_cuda):
+    torch = torch_cuda
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_histories.json")) as fh:
+        cases = json.load(fh)["cases"]
+    for c in cases:
+        say("golden " + c["name"])
+        d, n = c["d"], c["n"]
+        f = W.sine2d(n) if c["input"] == "sine2d" else W.uniform(d, n, seed=c["seed"])
+        s = B.Solver(d, n, max_i=c["max_i"])
+        u = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+        res = s.solve(dev(torch, f), u, tol=c["tol"])
+        ho = np.array(c["history"])
+        assert res["cycles"] == len(ho) - 1
+        np.testing.assert_allclose(res["history"], ho, rtol=1e-5, atol=1e-12)
+
+
+def test_tiny_grids(B, torch_cuda):
+    torch = torch_cuda
+    for d, n in ((2, 3), (2, 5), (3, 3), (3, 5)):
+        say("tiny d=%d n=%d" % (d, n))
+        f = W.uniform(d, n, seed=10)
+        solve_and_compare(B, torch, d, n, f, tol=1e-12)
+
+
+def test_nonzero_initial_guess_and_boundary_data(B, torch_cuda):
+    """u0 carries Dirichlet data on the boundary and a guess inside; the
+    boundary is never written."""
+    torch = torch_cuda
+    d, n = 2, 129
+    rng = np.random.default_rng(11)
+    f = W.uniform(d, n, seed=11)
+    u0 = rng.standard_normal((n, n))
+    s = B.Solver(d, n)
+    u = dev(torch, u0)
+    res = s.solve(dev(torch, f), u, tol=1e-10)
+    ug = host(u)
+    assert np.array_equal(ug[0], u0[0]) and np.array_equal(ug[-1], u0[-1])
+    assert np.array_equal(ug[:, 0], u0[:, 0]) and np.array_equal(ug[:, -1], u0[:, -1])
+    uo, ho = O.solve(d, n, f, u0=u0, fixed_cycles=res["cycles"])
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) <= 1e-11
+
+
+def test_repeat_solves_bitwise_identical(B, torch_cuda):
+    torch = torch_cuda
+    for d, n in ((2, 1025), (3, 65)):
+        f = dev(torch, W.uniform(d, n, seed=12))
+        s = B.Solver(d, n)
+        outs = []
+        for _ in range(2):
+            u = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+            s.solve(f, u, tol=1e-10)
+            outs.append(host(u))
+        assert np.array_equal(outs[0], outs[1])
+
+
+def test_residual_entry_point(B, torch_cuda):
+    torch = torch_cuda
+    for d, n in ((2, 257), (3, 33)):
+        rng = np.random.default_rng(13)
+        f = W.uniform(d, n, seed=13)
+        u = rand_interior(rng, d, n)
+        s = B.Solver(d, n)
+        r = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+        rel = s.residual(dev(torch, f), dev(torch, u), r)
+        ro, so = O.residual(d, n, f, u)
+        fn = np.sqrt(O.norm2_interior(d, n, f))
+        assert rel == pytest.approx(np.sqrt(so) / fn, rel=1e-12)
+        assert np.max(np.abs(host(r) - ro)) <= 1e-12 * np.max(np.abs(ro))
+        rel2 = s.residual(dev(torch, f), dev(torch, u))
+        assert rel2 == pytest.approx(rel, rel=1e-12)
+
+
+# ------------------------------------------------------------- error paths
+
+def test_not_converged_leaves_last_iterate(B, torch_cuda):
+    torch = torch_cuda
+    n = 65
+    f = W.uniform(2, n, seed=14)
+    s = B.Solver(2, n, max_cycles=3)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    res = s.solve(dev(torch, f), u, tol=1e-300, raise_on_status=False)
+    assert res["status"] == 7 and res["cycles"] == 3 and not res["converged"]
+    uo, _ = O.solve(2, n, f, fixed_cycles=3)
+    assert np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= 1e-11
+
+
+def test_non_finite_source_is_reported(B, torch_cuda):
+    torch = torch_cuda
+    n = 65
+    f = W.uniform(2, n, seed=15)
+    f[10, 10] = np.nan
+    s = B.Solver(2, n)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    res = s.solve(dev(torch, f), u, tol=1e-10, raise_on_status=False)
+    assert res["status"] == 6
+
+
+def test_diffusion_needs_coefficient(B, torch_cuda):
+    torch = torch_cuda
+    s = B.Solver(2, 33, stencil=B.DIFFUSION_5PT_2D)
+    u = torch.zeros((33, 33), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.HomgError):
+        s.solve(dev(torch, W.uniform(2, 33)), u)
+
+
+# ------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d,n", [(2, 257), (3, 65)])
+def test_mixed_precision_refinement(B, torch_cuda, d, n, prec):
+    """FP32 / BF16 sweeps under FP64 residual and update: the final FP64
+    relative residual (recomputed by the oracle) reaches the tolerance and u
+    lies within the rigorous bound of the FP64 oracle's u."""
+    torch = torch_cuda
+    say("mixed d=%d n=%d prec=%s" % (d, n, prec))
+    f = W.normal(d, n, seed=16)
+    s = B.Solver(d, n, precision=prec, max_cycles=200)
+    u = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+    res = s.solve(dev(torch, f), u, tol=1e-10, raise_on_status=False)
+    ug = host(u)
+    say("  status %d cycles %d final %.3e" % (res["status"], res["cycles"], res["final_relres"]))
+    assert res["status"] == 0
+    _, s2 = O.residual(d, n, f, ug)
+    fn = np.sqrt(O.norm2_interior(d, n, f))
+    assert np.sqrt(s2) / fn <= 1e-10 * (1 + 1e-6) + relres_floor(d, n, ug, f)
+    uo, ho = O.solve(d, n, f, tol=1e-10)
+    h = 1.0 / (n - 1)
+    lam_min = (4 * d / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    _, so = O.residual(d, n, f, uo)
+    bound = (np.sqrt(s2) + np.sqrt(so)) / lam_min
+    assert np.linalg.norm(ug - uo) <= bound * (1 + 1e-6)
+
+
+# ------------------------------------------------------------- full sizes
+
+@pytest.mark.parametrize("d,n", [(2, 4097), (3, 257)])
+def test_full_size_fp64(B, torch_cuda, d, n):
+    """The bench workloads at full size: one whole cycle element by element
+    against the oracle, then the full solve with its final residual
+    recomputed by the oracle."""
+    torch = torch_cuda
+    f = W.uniform(d, n, seed=0)
+    fd = dev(torch, f)
+    s = B.Solver(d, n)
+    say("full size d=%d n=%d: one cycle" % (d, n))
+    u = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+    res1 = s.solve_cycles(fd, u, 1)
+    ug = host(u)
+    uo, ho = O.solve(d, n, f, fixed_cycles=1)
+    assert np.linalg.norm(ug - uo) / np.linalg.norm(uo) <= 1e-11
+    assert abs(res1["history"][1] - ho[1]) <= 1e-6 * ho[1] + relres_floor(d, n, uo, f)
+    say("full size d=%d n=%d: solve to 1e-10" % (d, n))
+    u.zero_()
+    res = s.solve(fd, u, tol=1e-10)
+    ug = host(u)
+    _, s2 = O.residual(d, n, f, ug)
+    fn = np.sqrt(O.norm2_interior(d, n, f))
+    assert np.sqrt(s2) / fn <= 1e-10 * (1 + 1e-6) + relres_floor(d, n, ug, f)
+    say("  cycles %d final %.3e" % (res["cycles"], res["final_relres"]))
