@@ -57,8 +57,14 @@ def kernel_symbol(d, kind, level, mode):
     if kind == "sweep":
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
         return "%s<double, %d>" % (base, mode)
+    if kind == "lattice":
+        if mode & 4:
+            return "k_lattice_small_%dd<double, %s>" % (d, "true" if mode & 1 else "false")
+        return "k_sweep_%dd_l0<double, %d> (compact lattice)" % (d, mode & 3)
+    if kind == "level_write":
+        return "k_level_write_%dd<double, %d>" % (d, mode)
     return {"residual": "k_residual_%dd" % d, "restrict": "k_restrict_%dd" % d,
-            "norm": "k_norm2_%dd" % d, "finalize": "k_finalize"}[kind]
+            "norm": "k_norm2_%dd" % d, "finalize": "k_finalize", "gather": "k_gather<double>"}[kind]
 
 
 def kernel_bytes(d, n, entry):
@@ -74,6 +80,16 @@ def kernel_bytes(d, n, entry):
         return (8 * Nf + 8 * Nf / 2 ** d) * entry["launches"]
     if kind == "norm":
         return 8 * N * entry["launches"]
+    lat = N / float(1 << level) ** d
+    if kind == "gather":
+        return 16 * lat * entry["launches"]
+    if kind == "lattice":
+        if mode & 4:  # whole lattice in one workgroup: read x_0, r; write two iterates
+            return ((0 if mode & 1 else 8) + 8 + 16) * lat * entry["launches"]
+        return ((0 if mode & 1 else 8) + 16) * lat * entry["launches"]
+    if kind == "level_write":
+        reads = (0 if mode & 1 else 8) * lat + 8 * lat
+        return (reads + (16 * N if mode & 2 else 8 * N)) * entry["launches"]
     return 0.0
 
 
@@ -109,6 +125,50 @@ def cpu_baseline():
             "sample": "one MFMG cycle (MaxI 4) of each problem from u = 0: " + "; ".join(parts)}
 
 
+def mixed_precision_section(P, W, torch, dev, reps=3):
+    """3D 513^3 7-point Poisson, f ~ N(0,1) seed 0: time to 1e-10 (FP64
+    relative residual) with FP64, FP32-storage and BF16-storage sweeps under
+    the FP64 residual/update, the speedup over FP64 and the error of u
+    against the FP64 solve, with the rigorous bound (||r_a|| + ||r_b||) /
+    lambda_min that both solutions satisfy."""
+    d, n = 3, 513
+    f = torch.from_numpy(W.normal(d, n, seed=0)).to(dev)
+    h = 1.0 / (n - 1)
+    lam_min = (4 * d / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    fn = float(torch.linalg.vector_norm(f[1:-1, 1:-1, 1:-1]))
+    out, ref = {}, None
+    for prec in ("fp64", "fp32", "bf16"):
+        s = P.Solver(d, n, precision=prec, max_cycles=100)
+        u = torch.zeros_like(f)
+        times, res = [], None
+        for _ in range(reps + 1):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = s.solve(f, u, tol=1e-10, raise_on_status=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = sorted(times[1:])[len(times[1:]) // 2]
+        entry = {"status": res["status"], "converged": res["converged"], "cycles": res["cycles"],
+                 "time_to_1e-10_s": t if res["converged"] else None,
+                 "final_relres_fp64": res["final_relres"]}
+        if prec == "fp64":
+            ref = u.clone()
+            ref_res = res["final_relres"]
+        else:
+            diff = float(torch.linalg.vector_norm(u - ref))
+            entry["rel_err_vs_fp64"] = diff / float(torch.linalg.vector_norm(ref))
+            entry["abs_err_bound"] = (res["final_relres"] + ref_res) * fn / lam_min
+            entry["abs_err"] = diff
+            if res["converged"] and out["fp64"]["time_to_1e-10_s"]:
+                entry["speedup_vs_fp64"] = out["fp64"]["time_to_1e-10_s"] / t
+        out[prec] = entry
+        log("mixed %s: %s" % (prec, entry))
+        del s
+    return {"workload": "3D 513^3 7-point Poisson, f ~ N(0,1) seed 0, tol 1e-10 (FP64 residual), MaxI 4",
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +177,7 @@ def main():
     ap.add_argument("--max-i", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 precision comparison")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -201,6 +262,12 @@ def main():
                     "bytes_per_launch": k["bytes"] / k["launches"],
                     "avg_launch_us": 1e3 * k["ms"] / k["launches"]}
 
+    for p in probs:
+        p["s"].close()
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_precision_section(P, W, torch, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline()
@@ -213,7 +280,8 @@ def main():
                                   "3D 257^3 7-point, f ~ U[-1,1] seed 0, u0 = 0, zero Dirichlet, "
                                   "MaxI %d, omega 4/5 (2D) 6/7 (3D)" % args.max_i,
                       "problems": per, "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:8]}
+           "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:10],
+           "mixed_precision": mixed}
     print(json.dumps(out), flush=True)
 
 

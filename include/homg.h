@@ -77,8 +77,9 @@ typedef struct homg_options {
                               iterations min(2^(M-m+1), MaxI)) */
     int schedule_len;
     int precision;         /* homg_precision */
-    int temporal_block;    /* 0: one launch per whole-grid iteration; 1: several iterations of a
-                              level per launch where the kernel supports it (same results) */
+    int temporal_block;    /* 1 (default): level-blocked -- the iterations of a coarse level run on
+                              its compact lattice and the whole grid is written once per level;
+                              0: one whole-grid launch per iteration.  Same results bit for bit. */
     int reserved[7];       /* must be 0 */
 } homg_options;
 
@@ -181,9 +182,11 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  * class (kind, level, mode) whenever the handle synchronises.  Enabling or
  * disabling clears the accumulated times.
  *   kind: 0 norm of f, 1 residual, 2 norm finalisation, 3 restriction from
- *   `level` to level+1, 4 whole-grid iteration at `level`.
- *   mode (kind 4): bit 0 = first iteration of a cycle (starts from e = 0),
- *   bit 1 = last iteration of a cycle (adds e into u).
+ *   `level` to level+1, 4 whole-grid iteration at `level`, 5 sampling of the
+ *   grid on the level lattice, 6 iterations on the compact lattice, 7
+ *   whole-grid pass of a blocked level.
+ *   mode (kinds 4, 6, 7): bit 0 = starts from e = 0, bit 1 = adds into u;
+ *   bit 2 (kind 6) = the whole lattice held by one workgroup.
  * homg_get_profile synchronises outstanding events, then writes up to cap
  * entries and their count in *len.
  */
@@ -198,6 +201,44 @@ typedef struct homg_kernel_time {
 
 homg_status homg_set_profiling(homg_handle h, int enable);
 homg_status homg_get_profile(homg_handle h, homg_kernel_time *out, int cap, int *len);
+
+/*
+ * Batched solver: many independent 2D Poisson problems (5-point, zero
+ * Dirichlet) of uneven sides, solved in ONE persistent kernel launch
+ * (captured once in a HIP graph and replayed).  All problems advance in
+ * lockstep steps of their own MFMG sequence (Sec. 2); each retires when
+ * its relative residual reaches tol.  Precision, omega, MaxI and
+ * max_cycles come from opt (schedule and temporal_block are ignored: one
+ * whole-grid kernel tile per iteration).
+ *
+ * homg_batch_create: count >= 1 problems with sides[i] = 2^k + 1, 3 <= side
+ *   <= 32769 and at most 16 levels; allocates one device arena for all of
+ *   them.  *out set only on success.
+ * homg_batch_solve: f[i], u[i] are host arrays of `count` device pointers to
+ *   dense FP64 side^2 arrays (u: initial guess in, solution out; boundary
+ *   entries never written).  relres_out / cycles_out / status_out (host,
+ *   `count` entries each, may be NULL) receive each problem's final relative
+ *   residual, cycles and homg_status.  Returns HOMG_OK if every problem
+ *   converged, HOMG_ERR_NOT_CONVERGED / HOMG_ERR_NUMERICAL if any did not,
+ *   HOMG_ERR_HIP if the persistent launch had to abort (a grid barrier
+ *   outwaited its time limit).  Synchronises the stream.
+ * homg_batch_set_tile_rows: rows per tile (the tile shape of the
+ *   fine-grid stages) for all problems of side `side`; 0 restores the
+ *   default.  homg_batch_tune picks them by timing candidate shapes on the
+ *   given inputs (u is overwritten; coordinate descent over the sides,
+ *   largest first) and reads/appends the choice in the text file cache_path
+ *   (lines "<arch/CUs/precision/MaxI key> <side> <rows>"; NULL: no cache).
+ */
+typedef struct homg_batch_ctx *homg_batch;
+
+homg_status homg_batch_create(homg_batch *out, int count, const int64_t *sides,
+                              const homg_options *opt);
+homg_status homg_batch_solve(homg_batch b, const double *const *f, double *const *u, double tol,
+                             void *stream, double *relres_out, int *cycles_out, int *status_out);
+homg_status homg_batch_set_tile_rows(homg_batch b, int64_t side, int rows);
+homg_status homg_batch_tune(homg_batch b, const double *const *f, double *const *u, double tol,
+                            void *stream, const char *cache_path);
+homg_status homg_batch_destroy(homg_batch b);
 
 /* Text of the last error on h (or of the calling thread if h is NULL). */
 const char *homg_last_error(homg_handle h);

@@ -1,0 +1,396 @@
+// homg_batch.cpp -- batched persistent HOMG solver: C ABI, arena, graph.
+//
+// Many independent 2D problems of uneven size are solved by one persistent
+// kernel (k_batched_2d): every problem walks its own MFMG sequence (Sec. 2
+// of arXiv:1108.2045: residual, restriction pyramid, fused relax+interpolate
+// iterations, restart) in lockstep steps separated by a grid barrier.  The
+// launch (state reset + persistent kernel) is captured once into a HIP
+// graph on an internal stream and replayed on the caller's stream; the
+// per-call inputs (array pointers, tolerance) live in device descriptors
+// uploaded before each replay, so the graph never changes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/homg.h"
+#include "homg_internal.h"
+
+using namespace homg;
+
+struct homg_batch_ctx {
+  int count = 0, prec = 0, max_i = 4, max_cycles = 200;
+  double omega = 0.8;
+  std::vector<int> sides, levels;
+  std::vector<int> sweep_levels;  // concatenated per-problem iteration levels
+  std::map<int, int> tile_rows;   // side -> rows per tile (absent: default)
+  BatchProblem* h_probs = nullptr;
+  BatchProblem* d_probs = nullptr;
+  BatchRun* h_run = nullptr;
+  BatchRun* d_run = nullptr;
+  BatchState* h_state = nullptr;
+  BatchState* d_state = nullptr;
+  int* h_done = nullptr;
+  int* d_done = nullptr;
+  int* d_sweep_levels = nullptr;
+  BatchSync* h_sync = nullptr;
+  BatchSync* d_sync = nullptr;
+  void* arena = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int grid = 0, device = 0;
+  uint64_t barrier_ticks = 0;
+  int max_steps = 0;
+  std::string err;
+};
+
+namespace {
+
+homg_status bfail(homg_batch_ctx* b, homg_status s, const std::string& msg) {
+  set_last_error(msg.c_str());
+  if (b) b->err = msg;
+  return s;
+}
+
+#define BHIP(b, call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return bfail(b, HOMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+int side_k(int64_t n) {
+  if (n < 3) return -1;
+  int k = 0;
+  while ((int64_t(1) << (k + 1)) + 1 <= n) ++k;
+  return ((int64_t(1) << k) + 1 == n) ? k : -1;
+}
+
+void free_batch(homg_batch_ctx* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  (void)hipFree(b->arena);
+  (void)hipFree(b->d_probs);
+  (void)hipFree(b->d_run);
+  (void)hipFree(b->d_state);
+  (void)hipFree(b->d_done);
+  (void)hipFree(b->d_sweep_levels);
+  (void)hipFree(b->d_sync);
+  if (b->h_probs) (void)hipHostFree(b->h_probs);
+  if (b->h_run) (void)hipHostFree(b->h_run);
+  if (b->h_state) (void)hipHostFree(b->h_state);
+  if (b->h_done) (void)hipHostFree(b->h_done);
+  if (b->h_sync) (void)hipHostFree(b->h_sync);
+  delete b;
+}
+
+// Tile rows (the walked length of a tile) of the fine-grid stages.
+int rows_for(const homg_batch_ctx* b, int side) {
+  auto it = b->tile_rows.find(side);
+  if (it != b->tile_rows.end() && it->second > 0) return std::min(it->second, side - 2);
+  return default_walk_len(2, side);
+}
+
+void apply_tiles(homg_batch_ctx* b) {
+  for (int i = 0; i < b->count; ++i) b->h_probs[i].len[0] = rows_for(b, b->sides[i]);
+}
+
+homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u, double tol,
+                     hipStream_t s) {
+  for (int i = 0; i < b->count; ++i) {
+    if (!f[i] || !u[i]) return bfail(b, HOMG_ERR_INVALID_ARG, "null f or u pointer");
+    b->h_probs[i].f = f[i];
+    b->h_probs[i].u = u[i];
+  }
+  *b->h_run = BatchRun{tol, b->omega, b->count, b->max_cycles, b->max_steps, 0, b->barrier_ticks};
+  BHIP(b, hipMemcpyAsync(b->d_probs, b->h_probs, sizeof(BatchProblem) * b->count,
+                         hipMemcpyHostToDevice, s));
+  BHIP(b, hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
+  if (!b->exec) {
+    BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batch(b->prec, b->count, b->grid, b->d_probs, b->d_state, b->d_done,
+                                 b->d_sweep_levels, b->d_run, b->d_sync, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(b->cap, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return bfail(b, HOMG_ERR_HIP, std::string("graph capture failed: ") +
+                                        hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    b->graph = g;
+    BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  BHIP(b, hipGraphLaunch(b->exec, s));
+  BHIP(b, hipMemcpyAsync(b->h_state, b->d_state, sizeof(BatchState) * b->count, hipMemcpyDeviceToHost, s));
+  BHIP(b, hipMemcpyAsync(b->h_done, b->d_done, sizeof(int) * b->count, hipMemcpyDeviceToHost, s));
+  BHIP(b, hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, s));
+  BHIP(b, hipStreamSynchronize(s));
+  if (b->h_sync->abort)
+    return bfail(b, HOMG_ERR_HIP, "persistent batched launch aborted: a grid barrier exceeded its time limit");
+  return HOMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, const homg_options* opt) {
+  if (!out) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (count < 1 || count > 16000) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "count must be in [1, 16000]");
+  if (!sides) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null sides");
+  homg_options o;
+  homg_options_init(&o);
+  if (opt) {
+    if (opt->struct_size != sizeof(homg_options))
+      return bfail(nullptr, HOMG_ERR_INVALID_ARG, "homg_options.struct_size mismatch");
+    o = *opt;
+  }
+  for (int i = 0; i < count; ++i) {
+    const int k = side_k(sides[i]);
+    if (k < 1 || k > 15) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "every side must be 2^k + 1, 1 <= k <= 15");
+  }
+  const double omega = o.omega > 0 ? o.omega : 0.8;
+  if (!(omega > 0.0 && omega <= 1.0)) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "omega must be in (0, 1]");
+  if (o.precision < HOMG_FP64 || o.precision > HOMG_BF16_IR)
+    return bfail(nullptr, HOMG_ERR_INVALID_ARG, "unknown precision");
+  homg_batch_ctx* b = new (std::nothrow) homg_batch_ctx;
+  if (!b) return bfail(nullptr, HOMG_ERR_OOM, "host allocation failed");
+  b->count = count;
+  b->prec = o.precision;
+  b->omega = omega;
+  b->max_i = o.max_i > 0 ? o.max_i : 4;
+  b->max_cycles = o.max_cycles > 0 ? o.max_cycles : 200;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return bfail(nullptr, HOMG_ERR_HIP, "hipGetDevice failed");
+  }
+  const int eb = prec_bytes(b->prec);
+  // arena layout: per problem e0, e1, r_0..r_M (storage type), partials, history
+  std::vector<size_t> off;
+  size_t total = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = total;
+    total += (bytes + 255) & ~size_t(255);
+    return o2;
+  };
+  struct Plan { size_t e[2], r[BATCH_MAX_LEVELS], part, hist; Lay el, rl[BATCH_MAX_LEVELS]; };
+  std::vector<Plan> plans(count);
+  int max_cycle_len = 0;
+  for (int i = 0; i < count; ++i) {
+    const int n = int(sides[i]);
+    const int L = side_k(n);
+    b->sides.push_back(n);
+    b->levels.push_back(L);
+    Plan& p = plans[i];
+    p.el = padded_layout(2, n, eb);
+    p.e[0] = take(size_t(p.el.alloc) * eb);
+    p.e[1] = take(size_t(p.el.alloc) * eb);
+    for (int m = 0; m < L; ++m) {
+      p.rl[m] = padded_layout(2, (n - 1) / (1 << m) + 1, eb);
+      p.r[m] = take(size_t(p.rl[m].alloc) * eb);
+    }
+    p.part = take(sizeof(double) * size_t(batch_tiles(n, 1)));
+    p.hist = take(sizeof(double) * size_t(b->max_cycles + 1));
+    const int M = L - 1;
+    int sweeps = 0;
+    for (int m = M; m >= 0; --m) sweeps += std::min(1 << std::min(M - m + 1, 30), b->max_i);
+    max_cycle_len = std::max(max_cycle_len, M + sweeps + 2);
+  }
+  b->max_steps = 4 + (b->max_cycles + 1) * max_cycle_len;
+  homg_status st = HOMG_OK;
+  if (hipMalloc(&b->arena, total) != hipSuccess) {
+    (void)hipGetLastError();
+    free_batch(b);
+    return bfail(nullptr, HOMG_ERR_OOM, "batch arena allocation of " + std::to_string(total) + " bytes failed");
+  }
+  bool ok = hipMemset(b->arena, 0, total) == hipSuccess;  // e boundaries stay 0 forever
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_probs), sizeof(BatchProblem) * count) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_run), sizeof(BatchRun)) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_state), sizeof(BatchState) * count) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_done), sizeof(int) * count) == hipSuccess;
+  ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_sync), sizeof(BatchSync)) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_probs), sizeof(BatchProblem) * count, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_run), sizeof(BatchRun), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_state), sizeof(BatchState) * count, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_done), sizeof(int) * count, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_sync), sizeof(BatchSync), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_batch(b);
+    return bfail(nullptr, HOMG_ERR_OOM, "batch workspace allocation failed");
+  }
+  char* base = static_cast<char*>(b->arena);
+  for (int i = 0; i < count; ++i) {
+    BatchProblem& q = b->h_probs[i];
+    std::memset(&q, 0, sizeof(q));
+    const Plan& p = plans[i];
+    const int n = b->sides[i], L = b->levels[i];
+    q.e[0] = base + p.e[0] + size_t(p.el.off) * eb;
+    q.e[1] = base + p.e[1] + size_t(p.el.off) * eb;
+    q.ep = p.el.pitch;
+    for (int m = 0; m < L; ++m) {
+      q.r[m] = base + p.r[m] + size_t(p.rl[m].off) * eb;
+      q.rp[m] = p.rl[m].pitch;
+      q.len[m] = default_walk_len(2, (n - 1) / (1 << m) + 1);
+    }
+    q.partials = reinterpret_cast<double*>(base + p.part);
+    q.history = reinterpret_cast<double*>(base + p.hist);
+    q.n = n;
+    q.levels = L;
+    q.top = L - 1;
+    q.sched_off = int(b->sweep_levels.size());
+    const int M = L - 1;
+    int sw = 0;
+    for (int m = M; m >= 0; --m) {
+      const int it = std::min(1 << std::min(M - m + 1, 30), b->max_i);
+      for (int t = 0; t < it; ++t) b->sweep_levels.push_back(m);
+      sw += it;
+    }
+    q.sweeps = sw;
+    q.id = i;
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&b->d_sweep_levels), sizeof(int) * b->sweep_levels.size()) != hipSuccess ||
+      hipMemcpy(b->d_sweep_levels, b->sweep_levels.data(), sizeof(int) * b->sweep_levels.size(),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    free_batch(b);
+    return bfail(nullptr, HOMG_ERR_OOM, "schedule table allocation failed");
+  }
+  int per_cu = 0, cus = 0, clock_khz = 0;
+  size_t lds = 0;
+  if (batch_occupancy(b->prec, count, &per_cu, &lds) != hipSuccess || per_cu < 1 ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
+      hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    free_batch(b);
+    return bfail(nullptr, HOMG_ERR_HIP, "cannot size the persistent launch");
+  }
+  b->grid = per_cu * cus;
+  // one barrier wait may not exceed 5 s of wall clock
+  b->barrier_ticks = uint64_t(std::max(clock_khz, 1)) * 1000ull * 5ull;
+  (void)st;
+  if (hipDeviceSynchronize() != hipSuccess) {
+    free_batch(b);
+    return bfail(nullptr, HOMG_ERR_HIP, "batch initialisation failed");
+  }
+  *out = b;
+  return HOMG_OK;
+}
+
+homg_status homg_batch_destroy(homg_batch b) {
+  if (!b) return HOMG_OK;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+  return HOMG_OK;
+}
+
+homg_status homg_batch_set_tile_rows(homg_batch b, int64_t side, int rows) {
+  if (!b) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null batch handle");
+  if (rows < 0 || rows > 4096) return bfail(b, HOMG_ERR_INVALID_ARG, "rows must be in [0, 4096]");
+  if (rows == 0) b->tile_rows.erase(int(side));
+  else b->tile_rows[int(side)] = rows;
+  return HOMG_OK;
+}
+
+homg_status homg_batch_solve(homg_batch b, const double* const* f, double* const* u, double tol,
+                             void* stream, double* relres_out, int* cycles_out, int* status_out) {
+  if (!b) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null batch handle");
+  if (!f || !u) return bfail(b, HOMG_ERR_INVALID_ARG, "null f or u array");
+  if (!(tol > 0.0)) return bfail(b, HOMG_ERR_INVALID_ARG, "tol must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  apply_tiles(b);
+  if (homg_status e = run_once(b, f, u, tol, s)) return e;
+  homg_status worst = HOMG_OK;
+  for (int i = 0; i < b->count; ++i) {
+    const int dn = b->h_done[i];
+    homg_status si = dn == 1 ? HOMG_OK : (dn == 2 ? HOMG_ERR_NUMERICAL : HOMG_ERR_NOT_CONVERGED);
+    if (relres_out) relres_out[i] = b->h_state[i].final_rel;
+    if (cycles_out) cycles_out[i] = b->h_state[i].cycles;
+    if (status_out) status_out[i] = si;
+    if (si == HOMG_ERR_NUMERICAL) worst = si;
+    else if (si != HOMG_OK && worst == HOMG_OK) worst = si;
+  }
+  if (worst != HOMG_OK) return bfail(b, worst, "some problems did not converge");
+  return HOMG_OK;
+}
+
+homg_status homg_batch_tune(homg_batch b, const double* const* f, double* const* u, double tol,
+                            void* stream, const char* cache_path) {
+  if (!b) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null batch handle");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int> distinct = b->sides;
+  std::sort(distinct.begin(), distinct.end());
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  const char* pname = b->prec == PREC_F64 ? "fp64" : (b->prec == PREC_F32 ? "fp32" : "bf16");
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  char key[128];
+  std::snprintf(key, sizeof key, "gfx950/cu%d/%s/maxi%d", cus, pname, b->max_i);
+  // cache: lines of the form   <key> <side> <rows>
+  if (cache_path) {
+    if (FILE* fp = std::fopen(cache_path, "r")) {
+      char k2[128];
+      int side = 0, rows = 0, hits = 0;
+      while (std::fscanf(fp, "%127s %d %d", k2, &side, &rows) == 3)
+        if (std::strcmp(k2, key) == 0 && std::find(distinct.begin(), distinct.end(), side) != distinct.end()) {
+          b->tile_rows[side] = rows;
+          ++hits;
+        }
+      std::fclose(fp);
+      if (hits == int(distinct.size())) return HOMG_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  auto timed = [&](float* ms) -> homg_status {
+    apply_tiles(b);
+    BHIP(b, hipEventRecord(e0, s));
+    if (homg_status e = run_once(b, f, u, tol, s)) return e;
+    BHIP(b, hipEventRecord(e1, s));
+    BHIP(b, hipEventSynchronize(e1));
+    BHIP(b, hipEventElapsedTime(ms, e0, e1));
+    return HOMG_OK;
+  };
+  float best = 0.f;
+  if (homg_status e = timed(&best)) return e;  // warm-up
+  if (homg_status e = timed(&best)) return e;
+  // coordinate descent over the sides, largest first
+  for (auto it = distinct.rbegin(); it != distinct.rend(); ++it) {
+    const int side = *it;
+    const int keep = rows_for(b, side);
+    int best_rows = keep;
+    for (int rows : {4, 8, 16, 32, 64}) {
+      if (rows == keep || rows > side - 2) continue;
+      b->tile_rows[side] = rows;
+      float ms = 0.f;
+      if (homg_status e = timed(&ms)) return e;
+      if (ms < best) {
+        best = ms;
+        best_rows = rows;
+      }
+    }
+    b->tile_rows[side] = best_rows;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (cache_path) {
+    if (FILE* fp = std::fopen(cache_path, "a")) {
+      for (int side : distinct) std::fprintf(fp, "%s %d %d\n", key, side, rows_for(b, side));
+      std::fclose(fp);
+    }
+  }
+  return HOMG_OK;
+}
+
+}  // extern "C"

@@ -35,9 +35,14 @@ thread_local std::string g_err;
 
 }  // namespace
 
+void homg::set_last_error(const char* msg) { g_err = msg; }
+
 namespace {
 
-enum Kind { K_NORM = 0, K_RESIDUAL = 1, K_FINALIZE = 2, K_RESTRICT = 3, K_SWEEP = 4 };
+enum Kind {
+  K_NORM = 0, K_RESIDUAL = 1, K_FINALIZE = 2, K_RESTRICT = 3, K_SWEEP = 4,
+  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7
+};
 
 // Event-pair timing of individual launches, harvested at synchronisation.
 struct Profiler {
@@ -67,6 +72,8 @@ struct homg_ctx {
   void* e[2] = {nullptr, nullptr};
   std::vector<void*> r;
   std::vector<double*> a;
+  std::vector<void*> xc;   // level-blocked path: compact x_{t-1}, x_t pairs per level (2m, 2m+1)
+  size_t lds_limit = 65536;
   bool has_coef = false;
   double* partials = nullptr;
   int npart = 0;
@@ -101,14 +108,14 @@ homg_status fail(homg_ctx* h, homg_status s, const std::string& msg) {
   do {                                                                          \
     size_t ev_ = 0;                                                             \
     if ((h)->prof.on) {                                                         \
-      if (homg_status pe_ = prof_begin(h, s, &ev_)) return pe_;                 \
+      if (homg_status pe_ = prof_begin(h, &ev_)) return pe_;                    \
     }                                                                           \
-    HIPCHK(h, call);                                                            \
+    hipError_t le_ = (call);                                                    \
+    set_launch_events(nullptr, nullptr);                                        \
+    HIPCHK(h, le_);                                                             \
     ++(h)->launches;                                                            \
-    if ((h)->prof.on) {                                                         \
-      HIPCHK(h, hipEventRecord((h)->prof.pool[ev_ + 1], s));                    \
+    if ((h)->prof.on)                                                           \
       (h)->prof.pending.push_back({Profiler::Key(kind, level, mode), ev_});     \
-    }                                                                           \
   } while (0)
 
 #define LAUNCH(h, call)          \
@@ -117,7 +124,10 @@ homg_status fail(homg_ctx* h, homg_status s, const std::string& msg) {
     ++(h)->launches;             \
   } while (0)
 
-homg_status prof_begin(homg_ctx* h, hipStream_t s, size_t* ev) {
+// Reserve an event pair and arm it for the next launch: the launch stamps
+// the pair with its own start and end (hipExtLaunchKernelGGL), so the
+// elapsed time is the kernel's execution alone.
+homg_status prof_begin(homg_ctx* h, size_t* ev) {
   Profiler& p = h->prof;
   while (p.pool.size() < p.used + 2) {
     hipEvent_t e;
@@ -126,7 +136,7 @@ homg_status prof_begin(homg_ctx* h, hipStream_t s, size_t* ev) {
   }
   *ev = p.used;
   p.used += 2;
-  HIPCHK(h, hipEventRecord(p.pool[*ev], s));
+  set_launch_events(p.pool[*ev], p.pool[*ev + 1]);
   return HOMG_OK;
 }
 
@@ -173,6 +183,7 @@ void free_ctx(homg_ctx* h) {
   (void)hipFree(h->e[1]);
   for (void* p : h->r) (void)hipFree(p);
   for (double* p : h->a) (void)hipFree(p);
+  for (void* p : h->xc) (void)hipFree(p);
   (void)hipFree(h->partials);
   (void)hipFree(h->st);
   (void)hipFree(h->hist);
@@ -192,6 +203,66 @@ homg_status dev_alloc(homg_ctx* h, void** p, size_t bytes) {
   return HOMG_OK;
 }
 
+// `it` iterations of level m on the whole-grid state e[*cur] (Sec. 2, fused
+// relax+interpolate task), leaving the result in e[*cur] (or added into acc
+// when `last`).  `first`: the state is e = 0 (first level of a cycle).
+homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cur, double* acc,
+                      const int* done, hipStream_t s) {
+  const Lay none;
+  const double* am = h->has_coef ? h->a[m] : nullptr;
+  const Lay& alm = am ? h->al[m] : none;
+  // One launch per iteration: level 0 always (every node is a lattice
+  // node), every level when blocking is off, and a coarse last level in
+  // reduced precision (its iterate goes into u unrounded).
+  if (m == 0 || !h->temporal || (last && h->prec != PREC_F64)) {
+    for (int t = 0; t < it; ++t) {
+      int mode = 0;
+      if (first && t == 0) mode |= SW_ZERO_OLD;
+      if (last && t == it - 1) mode |= SW_ACCUM;
+      LAUNCH_K(h, s, K_SWEEP, m, mode,
+               launch_sweep(h->prec, h->d, h->n, m, h->omega, h->e[*cur], h->e[1 - *cur], h->el,
+                            h->r[m], h->rl[m], am, alm, acc, h->dl, mode, done, s));
+      *cur = 1 - *cur;
+    }
+    return HOMG_OK;
+  }
+  // Level-blocked: iterations on the compact lattice, one whole-grid pass.
+  const int l = 1 << m, nm = (h->n - 1) / l + 1;
+  const Lay& cl = h->rl[m];
+  void* X0 = h->xc[2 * m];
+  void* X1 = h->xc[2 * m + 1];
+  void* xprev;
+  void* xcur;
+  int wmode = last ? SW_ACCUM : 0;
+  if (lattice_small_lds(h->prec, h->d, nm, am != nullptr) <= h->lds_limit) {
+    LAUNCH_K(h, s, K_LATTICE, m, 4 | (first ? 1 : 0),
+             launch_lattice_small(h->prec, h->d, nm, l, it, h->omega, first, h->e[*cur], h->el,
+                                  h->r[m], h->rl[m], am, alm, X0, X1, cl, done, s));
+    xprev = X0;
+    xcur = X1;
+  } else {
+    if (!first)
+      LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X0, cl, done, s));
+    void* X[2] = {X0, X1};
+    int src = 0;
+    for (int t = 1; t <= it; ++t) {
+      const int mode = (first && t == 1) ? SW_ZERO_OLD : 0;
+      LAUNCH_K(h, s, K_LATTICE, m, mode,
+               launch_sweep(h->prec, h->d, nm, 0, h->omega, X[src], X[1 - src], cl, h->r[m],
+                            h->rl[m], am, alm, nullptr, none, mode, done, s));
+      src = 1 - src;
+    }
+    xcur = X[src];
+    xprev = X[1 - src];
+    if (first && it == 1) wmode |= SW_ZERO_OLD;  // x_0 = 0 was never stored
+  }
+  LAUNCH_K(h, s, K_LEVEL_WRITE, m, wmode,
+           launch_level_write(h->prec, h->d, h->n, m, xprev, xcur, cl, h->e[1 - *cur], h->el, acc,
+                              h->dl, wmode, done, s));
+  *cur = 1 - *cur;
+  return HOMG_OK;
+}
+
 // Enqueue one MFMG cycle (Sec. 2): restriction pyramid of r_0, the
 // schedule's whole-grid iterations with the last one adding e into acc,
 // then (if f != null) the new residual and its norm as history[cycle].
@@ -200,20 +271,12 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   for (int m = 0; m < h->top_level; ++m)
     LAUNCH_K(h, s, K_RESTRICT, m, 0,
              launch_restrict(h->prec, h->d, h->r[m], h->rl[m], h->r[m + 1], h->rl[m + 1], done, s));
-  int cur = 0, idx = 0;
+  int cur = 0;
   const Lay none;
-  for (size_t p = 0; p < h->sched.size(); p += 2) {
-    const int m = h->sched[p], it = h->sched[p + 1];
-    for (int t = 0; t < it; ++t, ++idx) {
-      int mode = 0;
-      if (idx == 0) mode |= SW_ZERO_OLD;
-      if (idx == h->total_sweeps - 1) mode |= SW_ACCUM;
-      const double* am = h->has_coef ? h->a[m] : nullptr;
-      LAUNCH_K(h, s, K_SWEEP, m, mode,
-               launch_sweep(h->prec, h->d, h->n, m, h->omega, h->e[cur], h->e[1 - cur], h->el,
-                            h->r[m], h->rl[m], am, am ? h->al[m] : none, acc, h->dl, mode, done, s));
-      cur = 1 - cur;
-    }
+  const size_t np = h->sched.size() / 2;
+  for (size_t p = 0; p < np; ++p) {
+    const int m = h->sched[2 * p], it = h->sched[2 * p + 1];
+    if (homg_status e = run_level(h, m, it, p == 0, p + 1 == np, &cur, acc, done, s)) return e;
   }
   if (f) {
     int count = 0;
@@ -315,7 +378,7 @@ void homg_options_init(homg_options* opt) {
   opt->max_i = 4;
   opt->max_cycles = 200;
   opt->precision = HOMG_FP64;
-  opt->temporal_block = 0;
+  opt->temporal_block = 1;
 }
 
 homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int levels,
@@ -416,6 +479,12 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   for (int b = 0; b < 2 && !stt; ++b) stt = dev_alloc(h, &h->e[b], size_t(h->el.alloc) * eb);
   h->r.assign(levels, nullptr);
   for (int m = 0; m < levels && !stt; ++m) stt = dev_alloc(h, &h->r[m], size_t(h->rl[m].alloc) * eb);
+  if (h->temporal) {
+    h->xc.assign(2 * levels, nullptr);
+    for (int m = 1; m < levels && !stt; ++m)
+      for (int b = 0; b < 2 && !stt; ++b)
+        stt = dev_alloc(h, &h->xc[2 * m + b], size_t(h->rl[m].alloc) * eb);
+  }
   h->npart = partials_bound(ndim, h->n);
   if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->partials), sizeof(double) * h->npart);
   if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->st), sizeof(DevState));
@@ -433,6 +502,15 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
        hipMemset(h->e[1], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
        hipMemset(h->zero_flag, 0, sizeof(int) * 64) == hipSuccess;
   for (int m = 0; m < levels && ok; ++m) ok = hipMemset(h->r[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  // compact lattices: boundary nodes are read as 0 and never written
+  for (int m = 1; m < levels && ok && h->temporal; ++m)
+    for (int b = 0; b < 2 && ok; ++b) ok = hipMemset(h->xc[2 * m + b], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  if (ok) {
+    int optin = 0, base = 0;
+    (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, h->device);
+    (void)hipDeviceGetAttribute(&base, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+    h->lds_limit = size_t(std::max(std::max(optin, base), 16384));
+  }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     free_ctx(h);
@@ -546,15 +624,7 @@ homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* 
   LAUNCH(h, launch_pack(h->prec, h->d, e_old, h->dl, h->e[0], h->el, s));
   LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
   int cur = 0;
-  const double* am = h->has_coef ? h->a[level] : nullptr;
-  const Lay none;
-  for (int t = 0; t < iters; ++t) {
-    LAUNCH_K(h, s, K_SWEEP, level, 0,
-             launch_sweep(h->prec, h->d, h->n, level, h->omega, h->e[cur], h->e[1 - cur], h->el,
-                           h->r[level], h->rl[level], am, am ? h->al[level] : none, nullptr, h->dl, 0,
-                           h->zero_flag, s));
-    cur = 1 - cur;
-  }
+  if (homg_status e = run_level(h, level, iters, false, false, &cur, nullptr, h->zero_flag, s)) return e;
   LAUNCH(h, launch_unpack(h->prec, h->d, h->e[cur], h->el, e_new, h->dl, s));
   // the solver relies on zero boundaries in both e buffers
   const size_t eb = size_t(prec_bytes(h->prec));

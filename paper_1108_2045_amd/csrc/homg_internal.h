@@ -77,4 +77,67 @@ hipError_t launch_unpack(int prec, int d, const void* src, const Lay& sl, double
 hipError_t launch_sample(int d, const double* src, const Lay& sl, int stride, double* dst,
                          const Lay& dl, hipStream_t s);
 
+// Level-blocked path (same results as one launch per iteration):
+// x_0 = the whole grid sampled on the level-l lattice (all compact nodes).
+hipError_t launch_gather(int prec, int d, const void* src, const Lay& sl, int l, void* dst,
+                         const Lay& dl, const int* done, hipStream_t s);
+// LDS bytes the single-workgroup lattice kernel needs for a compact side nm.
+size_t lattice_small_lds(int prec, int d, int nm, bool var);
+// All `it` iterations of a level on a compact lattice of side nm held by one
+// workgroup; x_0 gathered from e (layout el, stride l) unless zero; writes
+// x_{it-1} to xprev and x_it to xcur (compact layout cl).
+hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double omega, bool zero,
+                                const void* e, const Lay& el, const void* rm, const Lay& rl,
+                                const double* am, const Lay& al, void* xprev, void* xcur,
+                                const Lay& cl, const int* done, hipStream_t s);
+// LDS bytes of the whole-grid pass of level m.
+size_t level_write_lds(int prec, int d, int n, int m);
+// Whole-grid pass of level m from compact x_{it-1} (xprev) and x_it (xcur):
+// mode SW_ZERO_OLD = x_{it-1} is 0, SW_ACCUM = add into u instead of storing.
+hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, const void* xcur,
+                              const Lay& cl, void* en, const Lay& el, double* u, const Lay& ul,
+                              int mode, const int* done, hipStream_t s);
+// ---- batched persistent solver (2D, constant coefficient)
+constexpr int BATCH_MAX_LEVELS = 16;
+struct BatchProblem {         // one problem, read by the persistent kernel
+  const double* f;            // caller arrays, dense side n
+  double* u;
+  void* e[2];                 // internal e ping-pong, pointer at node (0,0)
+  void* r[BATCH_MAX_LEVELS];  // residual pyramid, pointer at node (0,0) of each level
+  int64_t ep;                 // pitch of e
+  int64_t rp[BATCH_MAX_LEVELS];
+  int len[BATCH_MAX_LEVELS];  // rows walked per tile on level-m grids (tile shape)
+  double* partials;           // per-tile norm sums
+  double* history;            // relres after cycles 0..max_cycles
+  int n, levels, top, sweeps; // side, levels, coarsest level visited, iterations per cycle
+  int sched_off, id, pad0, pad1;
+};
+struct BatchState {
+  int cycles;
+  int pad;
+  double fnorm;
+  double final_rel;
+};
+struct BatchRun {
+  double tol, omega;
+  int count, max_cycles, max_steps, pad;
+  uint64_t barrier_ticks;     // wall-clock limit of one barrier wait (100 MHz ticks)
+};
+struct BatchSync {
+  unsigned count, gen;
+  int abort, steps;
+};
+hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds);
+int default_walk_len(int d, int n);
+int batch_tiles(int side, int len);
+hipError_t launch_batch(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs, int* done,
+                        const int* levels_of_sweep, const BatchRun* run, BatchSync* sync,
+                        hipStream_t s);
+
+// Record the text of the calling thread's last error (homg_last_error(NULL)).
+void set_last_error(const char* msg);
+
+// Start/stop events stamped on the next launch of this thread (null: none).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+
 }  // namespace homg

@@ -16,6 +16,7 @@
 // Arithmetic is written with explicit fused multiply-adds and the file is
 // compiled with -ffp-contract=off, so every kernel that evaluates the same
 // node formula produces the same bits.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -50,6 +51,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ void st(bf16* p, float v) { p->bits = f2bf(v); }
 
+// Value as it reads back after a store in storage type T.
+template <typename T> __device__ __forceinline__ typename Tr<T>::C rnd(typename Tr<T>::C v) { return v; }
+template <> __device__ __forceinline__ float rnd<bf16>(float v) {
+  return __uint_as_float(uint32_t(f2bf(v)) << 16);
+}
+
 __device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -68,6 +75,19 @@ __device__ __forceinline__ C relax_const(C c, C q, C r, C w, C hl2, C two_d) {
 
 // Harmonic mean of two nodal coefficients (the face coefficient).
 __device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// Damped Jacobi for -div(a grad) at a lattice node: c + w (h_l^2 r - flux) / sum_a
+// with face coefficients the harmonic means of the nodal coefficient
+// (w = omega here).  Neighbours in the order -x, +x, -y, +y.
+template <typename C>
+__device__ __forceinline__ C relax_var(C c, C xm, C xp, C ym, C yp, double ac, double axm,
+                                       double axp, double aym, double ayp, C r, C w, C hl2) {
+  const C cxm = C(harm(ac, axm)), cxp = C(harm(ac, axp));
+  const C cym = C(harm(ac, aym)), cyp = C(harm(ac, ayp));
+  const C sa = (cxm + cxp) + (cym + cyp);
+  const C flux = fmac(cxm, c - xm, cxp * (c - xp)) + fmac(cym, c - ym, cyp * (c - yp));
+  return fmac(w / sa, fmac(hl2, r, -flux), c);
+}
 
 // Linear interpolation a + t (b - a), t in [0, 1).
 template <typename C>
@@ -155,10 +175,10 @@ Lay padded_layout(int d, int side, int elem_bytes) {
 
 // ------------------------------------------------------------ norm of f
 
-__global__ __launch_bounds__(256) void k_norm2_2d(const double* __restrict__ f, int64_t fp, int n,
-                                                  int len, double* __restrict__ partials) {
-  const int x = 1 + blockIdx.x * BX2 + threadIdx.x;
-  const int y0 = 1 + blockIdx.y * len;
+__device__ __forceinline__ void tile_norm2_2d(const double* __restrict__ f, int64_t fp, int n,
+                                                  int len, double* __restrict__ partials, int bx, int by, int pidx) {
+  const int x = 1 + bx * BX2 + threadIdx.x;
+  const int y0 = 1 + by * len;
   const int y1 = min(n - 1, y0 + len);
   double s = 0.0;
   if (x <= n - 2)
@@ -167,7 +187,12 @@ __global__ __launch_bounds__(256) void k_norm2_2d(const double* __restrict__ f, 
       s = fmac(v, v, s);
     }
   s = block_sum<256>(s);
-  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[pidx] = s;
+}
+
+__global__ __launch_bounds__(256) void k_norm2_2d(const double* __restrict__ f, int64_t fp, int n,
+                                                  int len, double* __restrict__ partials) {
+  tile_norm2_2d(f, fp, n, len, partials, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_norm2_3d(const double* __restrict__ f, int64_t fp,
@@ -194,13 +219,12 @@ __global__ __launch_bounds__(256) void k_norm2_3d(const double* __restrict__ f, 
 // FP64 values.
 
 template <typename T, bool VAR>
-__global__ __launch_bounds__(256) void k_residual_2d(
+__device__ __forceinline__ void tile_residual_2d(
     const double* __restrict__ u, int64_t up, const double* __restrict__ f, int64_t fp,
     const double* __restrict__ a, int64_t ap, T* __restrict__ r, int64_t rp, int n, int len,
-    double inv_h2, double* __restrict__ partials, const int* __restrict__ done) {
-  if (*done) return;
-  const int x = 1 + blockIdx.x * BX2 + threadIdx.x;
-  const int y0 = 1 + blockIdx.y * len;
+    double inv_h2, double* __restrict__ partials, int bx, int by, int pidx) {
+  const int x = 1 + bx * BX2 + threadIdx.x;
+  const int y0 = 1 + by * len;
   const int y1 = min(n - 1, y0 + len);
   double s = 0.0;
   if (x <= n - 2) {
@@ -236,7 +260,16 @@ __global__ __launch_bounds__(256) void k_residual_2d(
     }
   }
   s = block_sum<256>(s);
-  if (threadIdx.x == 0) partials[blockIdx.y * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[pidx] = s;
+}
+
+template <typename T, bool VAR>
+__global__ __launch_bounds__(256) void k_residual_2d(
+    const double* __restrict__ u, int64_t up, const double* __restrict__ f, int64_t fp,
+    const double* __restrict__ a, int64_t ap, T* __restrict__ r, int64_t rp, int n, int len,
+    double inv_h2, double* __restrict__ partials, const int* __restrict__ done) {
+  if (*done) return;
+  tile_residual_2d<T, VAR>(u, up, f, fp, a, ap, r, rp, n, len, inv_h2, partials, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 template <typename T>
@@ -309,14 +342,13 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 // reductions): coarse node = (1/4)[1 2 1] per axis of the fine neighbours.
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_2d(const T* __restrict__ rf, int64_t fp,
+__device__ __forceinline__ void tile_restrict_2d(const T* __restrict__ rf, int64_t fp,
                                                      T* __restrict__ rc, int64_t cp, int nc,
-                                                     int len, const int* __restrict__ done) {
+                                                     int len, int bx, int by) {
   using C = typename Tr<T>::C;
-  if (*done) return;
-  const int I = 1 + blockIdx.x * BX2 + threadIdx.x;
+  const int I = 1 + bx * BX2 + threadIdx.x;
   if (I > nc - 2) return;
-  const int J0 = 1 + blockIdx.y * len;
+  const int J0 = 1 + by * len;
   const int J1 = min(nc - 1, J0 + len);
   const int xi = 2 * I;
   auto rowsum = [&](int yf) {
@@ -330,6 +362,14 @@ __global__ __launch_bounds__(256) void k_restrict_2d(const T* __restrict__ rf, i
     st(rc + int64_t(J) * cp + I, fmac(C(2), mid, top + bot) * C(0.0625));
     top = bot;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_2d(const T* __restrict__ rf, int64_t fp,
+                                                     T* __restrict__ rc, int64_t cp, int nc,
+                                                     int len, const int* __restrict__ done) {
+  if (*done) return;
+  tile_restrict_2d<T>(rf, fp, rc, cp, nc, len, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -381,15 +421,14 @@ __device__ __forceinline__ void emit_2d(T* en, int64_t eoff, double* u, int64_t 
 
 // Level 0: every interior node relaxes (plain damped Jacobi).
 template <typename T, int MODE, bool VAR>
-__global__ __launch_bounds__(256) void k_sweep_2d_l0(
+__device__ __forceinline__ void tile_sweep_2d_l0(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r,
     int64_t rp, const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up,
-    int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done) {
+    int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2, int bx, int by) {
   using C = typename Tr<T>::C;
-  if (*done) return;
-  const int x = 1 + blockIdx.x * BX2 + threadIdx.x;
+  const int x = 1 + bx * BX2 + threadIdx.x;
   if (x > n - 2) return;
-  const int y0 = 1 + blockIdx.y * len;
+  const int y0 = 1 + by * len;
   const int y1 = min(n - 1, y0 + len);
   C ym = C(0), c = C(0);
   if (!(MODE & SW_ZERO_OLD)) {
@@ -414,11 +453,7 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
     if (VAR) {
       const double* arow = a + int64_t(y) * ap;
       const double ayp = arow[ap + x];
-      const C cxm = C(harm(ac, arow[x - 1])), cxp = C(harm(ac, arow[x + 1]));
-      const C cym = C(harm(ac, aym)), cyp = C(harm(ac, ayp));
-      const C sa = (cxm + cxp) + (cym + cyp);
-      const C flux = fmac(cxm, c - xm, cxp * (c - xp)) + fmac(cym, c - ym, cyp * (c - yp));
-      v = fmac(w / sa, fmac(hl2, rv, -flux), c);
+      v = relax_var<C>(c, xm, xp, ym, yp, ac, arow[x - 1], arow[x + 1], aym, ayp, rv, w, hl2);
       aym = ac;
       ac = ayp;
     } else {
@@ -430,22 +465,29 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
   }
 }
 
+template <typename T, int MODE, bool VAR>
+__global__ __launch_bounds__(256) void k_sweep_2d_l0(
+    const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r,
+    int64_t rp, const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up,
+    int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done) {
+  if (*done) return;
+  tile_sweep_2d_l0<T, MODE, VAR>(eo, en, ep, r, rp, a, ap, u, up, n, len, w, hl2, blockIdx.x, blockIdx.y);
+}
+
 // Levels m >= 1: lattice nodes relax, the rest interpolate.  The lane keeps
 // the four corners of its current level-m cell; they change every l rows.
 template <typename T, int MODE, bool VAR>
-__global__ __launch_bounds__(256) void k_sweep_2d_coarse(
+__device__ __forceinline__ void tile_sweep_2d_coarse(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ rm,
     int64_t rp, const double* __restrict__ am, int64_t ap, double* __restrict__ u, int64_t up,
-    int n, int len, int m, typename Tr<T>::C w, typename Tr<T>::C hl2,
-    const int* __restrict__ done) {
+    int n, int len, int m, typename Tr<T>::C w, typename Tr<T>::C hl2, int bx, int by) {
   using C = typename Tr<T>::C;
-  if (*done) return;
-  const int x = 1 + blockIdx.x * BX2 + threadIdx.x;
+  const int x = 1 + bx * BX2 + threadIdx.x;
   if (x > n - 2) return;
   const int l = 1 << m;
   const int mask = l - 1;
   const C inv_l = C(1) / C(l);
-  const int y0 = 1 + blockIdx.y * len;
+  const int y0 = 1 + by * len;
   const int y1 = min(n - 1, y0 + len);
   const int xa = x & ~mask, xb = xa + l;
   const C tx = C(x - xa) * inv_l;
@@ -482,12 +524,8 @@ __global__ __launch_bounds__(256) void k_sweep_2d_coarse(
       if (VAR) {
         const int I = xa >> m, J = ya >> m;
         const double* arow = am + int64_t(J) * ap + I;
-        const double ac = arow[0];
-        const C cxm = C(harm(ac, arow[-1])), cxp = C(harm(ac, arow[1]));
-        const C cym = C(harm(ac, arow[-ap])), cyp = C(harm(ac, arow[ap]));
-        const C sa = (cxm + cxp) + (cym + cyp);
-        const C flux = fmac(cxm, t0 - xm, cxp * (t0 - t1)) + fmac(cym, t0 - ym, cyp * (t0 - b0));
-        v = fmac(w / sa, fmac(hl2, rv, -flux), t0);
+        v = relax_var<C>(t0, xm, t1, ym, b0, arow[0], arow[-1], arow[1], arow[-ap], arow[ap], rv,
+                         w, hl2);
       } else {
         v = relax_const<C>(t0, (xm + t1) + (ym + b0), rv, w, hl2, C(4));
       }
@@ -496,6 +534,16 @@ __global__ __launch_bounds__(256) void k_sweep_2d_coarse(
     }
     emit_2d<T, MODE, VAR>(en, int64_t(y) * ep + x, u, int64_t(y) * up + x, v);
   }
+}
+
+template <typename T, int MODE, bool VAR>
+__global__ __launch_bounds__(256) void k_sweep_2d_coarse(
+    const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ rm,
+    int64_t rp, const double* __restrict__ am, int64_t ap, double* __restrict__ u, int64_t up,
+    int n, int len, int m, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    const int* __restrict__ done) {
+  if (*done) return;
+  tile_sweep_2d_coarse<T, MODE, VAR>(eo, en, ep, rm, rp, am, ap, u, up, n, len, m, w, hl2, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, int MODE>
@@ -604,6 +652,238 @@ __global__ __launch_bounds__(256) void k_sweep_3d_coarse(
   }
 }
 
+// ------------------------------------------------------------ level-blocked path
+// The n_m iterations of level m read only lattice values, so they run on the
+// compact level-m lattice (x_0 = the whole grid sampled on the lattice,
+// x_t = one damped-Jacobi step of x_{t-1}); afterwards one whole-grid pass
+// writes the level's final state: interior lattice nodes take x_{n_m}, every
+// other interior node the multilinear interpolant of x_{n_m - 1} (the
+// one-iteration delay of the fused task).  The node formulas are the ones
+// of the one-launch-per-iteration kernels above, and every iterate is
+// rounded to the storage type at the same points, so both paths produce the
+// same bits.
+
+// x_0 on the compact lattice: dst[K][J][I] = src[K l][J l][I l] (all nodes).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ src, int64_t sp,
+                                                int64_t spl, int l, T* __restrict__ dst,
+                                                int64_t dp, int64_t dpl, int side, int nz) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= side || z >= nz) return;
+  dst[int64_t(z) * dpl + int64_t(y) * dp + x] =
+      src[int64_t(z) * l * spl + int64_t(y) * l * sp + int64_t(x) * l];
+}
+
+// Small lattices: one workgroup holds the whole compact level-m lattice in
+// LDS and runs all `it` iterations there; writes x_{it-1} and x_it.
+// ZERO: x_0 = 0 (first level of a cycle).
+constexpr int SMALL_NT = 1024;
+
+template <typename T, bool ZERO, bool VAR>
+__global__ __launch_bounds__(SMALL_NT) void k_lattice_small_2d(
+    const T* __restrict__ e, int64_t ep, int l, const T* __restrict__ rm, int64_t rp,
+    const double* __restrict__ am, int64_t ap, T* __restrict__ xprev, T* __restrict__ xcur,
+    int64_t cp, int nm, int it, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int cnt = nm * nm;
+  C* xa = reinterpret_cast<C*>(smem);
+  C* xb = xa + cnt;
+  C* rr = xb + cnt;
+  double* aa = reinterpret_cast<double*>(smem + ((3 * cnt * sizeof(C) + 15) & ~size_t(15)));
+  for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+    const int J = i / nm, I = i - J * nm;
+    const bool inner = I > 0 && I < nm - 1 && J > 0 && J < nm - 1;
+    xa[i] = ZERO ? C(0) : ld(e + int64_t(J) * l * ep + int64_t(I) * l);
+    xb[i] = xa[i];
+    rr[i] = inner ? ld(rm + int64_t(J) * rp + I) : C(0);
+    if (VAR) aa[i] = am[int64_t(J) * ap + I];
+  }
+  __syncthreads();
+  for (int t = 1; t <= it; ++t) {
+    const C* src = (t & 1) ? xa : xb;
+    C* dst = (t & 1) ? xb : xa;
+    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+      const int J = i / nm, I = i - J * nm;
+      if (I > 0 && I < nm - 1 && J > 0 && J < nm - 1) {
+        const C c = src[i], xm = src[i - 1], xp = src[i + 1], ym = src[i - nm], yp = src[i + nm];
+        C v;
+        if (VAR)
+          v = relax_var<C>(c, xm, xp, ym, yp, aa[i], aa[i - 1], aa[i + 1], aa[i - nm], aa[i + nm],
+                           rr[i], w, hl2);
+        else
+          v = relax_const<C>(c, (xm + xp) + (ym + yp), rr[i], w, hl2, C(4));
+        dst[i] = rnd<T>(v);
+      }
+    }
+    __syncthreads();
+  }
+  const C* cur = (it & 1) ? xb : xa;
+  const C* prv = (it & 1) ? xa : xb;
+  for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+    const int J = i / nm, I = i - J * nm;
+    st(xprev + int64_t(J) * cp + I, prv[i]);
+    st(xcur + int64_t(J) * cp + I, cur[i]);
+  }
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(SMALL_NT) void k_lattice_small_3d(
+    const T* __restrict__ e, int64_t ep, int64_t epl, int l, const T* __restrict__ rm,
+    int64_t rp, int64_t rpl, T* __restrict__ xprev, T* __restrict__ xcur, int64_t cp,
+    int64_t cpl, int nm, int it, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int pl = nm * nm, cnt = pl * nm;
+  C* xa = reinterpret_cast<C*>(smem);
+  C* xb = xa + cnt;
+  C* rr = xb + cnt;
+  for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+    const int K = i / pl, rem = i - K * pl, J = rem / nm, I = rem - J * nm;
+    const bool inner = I > 0 && I < nm - 1 && J > 0 && J < nm - 1 && K > 0 && K < nm - 1;
+    xa[i] = ZERO ? C(0) : ld(e + int64_t(K) * l * epl + int64_t(J) * l * ep + int64_t(I) * l);
+    xb[i] = xa[i];
+    rr[i] = inner ? ld(rm + int64_t(K) * rpl + int64_t(J) * rp + I) : C(0);
+  }
+  __syncthreads();
+  for (int t = 1; t <= it; ++t) {
+    const C* src = (t & 1) ? xa : xb;
+    C* dst = (t & 1) ? xb : xa;
+    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+      const int K = i / pl, rem = i - K * pl, J = rem / nm, I = rem - J * nm;
+      if (I > 0 && I < nm - 1 && J > 0 && J < nm - 1 && K > 0 && K < nm - 1) {
+        const C c = src[i];
+        const C q = ((src[i - 1] + src[i + 1]) + (src[i - nm] + src[i + nm])) + (src[i - pl] + src[i + pl]);
+        dst[i] = rnd<T>(relax_const<C>(c, q, rr[i], w, hl2, C(6)));
+      }
+    }
+    __syncthreads();
+  }
+  const C* cur = (it & 1) ? xb : xa;
+  const C* prv = (it & 1) ? xa : xb;
+  for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+    const int K = i / pl, rem = i - K * pl, J = rem / nm, I = rem - J * nm;
+    st(xprev + int64_t(K) * cpl + int64_t(J) * cp + I, prv[i]);
+    st(xcur + int64_t(K) * cpl + int64_t(J) * cp + I, cur[i]);
+  }
+}
+
+// The whole-grid pass of a level: stages the compact x_{it-1} / x_it values
+// under the block's tile in LDS, then every lane walks its column writing
+// lattice nodes from x_it and the rest by multilinear interpolation of
+// x_{it-1}.  MODE bits: SW_ZERO_OLD (x_{it-1} = 0), SW_ACCUM (add into u).
+constexpr int LW_ROWS2 = 32;  // rows per 2D tile
+constexpr int LW_PLANES3 = 16;  // planes per 3D tile
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_level_write_2d(
+    const T* __restrict__ xprev, const T* __restrict__ xcur, int64_t cp, T* __restrict__ en,
+    int64_t ep, double* __restrict__ u, int64_t up, int n, int m, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int l = 1 << m, mask = l - 1;
+  const int X0 = 1 + blockIdx.x * BX2, X1 = min(n - 2, X0 + BX2 - 1);
+  const int Y0 = 1 + blockIdx.y * LW_ROWS2, Y1 = min(n - 2, Y0 + LW_ROWS2 - 1);
+  const int I0 = X0 >> m, J0 = Y0 >> m;
+  const int CW = (X1 >> m) - I0 + 2, CH = (Y1 >> m) - J0 + 2;
+  C* P = reinterpret_cast<C*>(smem);
+  C* Q = P + CW * CH;
+  for (int i = threadIdx.x; i < CW * CH; i += BX2) {
+    const int j = i / CW, c = i - j * CW;
+    const int64_t g = int64_t(J0 + j) * cp + (I0 + c);
+    P[i] = (MODE & SW_ZERO_OLD) ? C(0) : ld(xprev + g);
+    Q[i] = ld(xcur + g);
+  }
+  __syncthreads();
+  const int x = X0 + threadIdx.x;
+  if (x > X1) return;
+  const C inv_l = C(1) / C(l);
+  const int xi = (x >> m) - I0;
+  const C tx = C(x & mask) * inv_l;
+  const bool latc = (x & mask) == 0;
+  int band = -1;
+  C top = C(0), bot = C(0);
+  for (int y = Y0; y <= Y1; ++y) {
+    const int yj = (y >> m) - J0;
+    if (yj != band) {
+      band = yj;
+      const C* p = P + yj * CW + xi;
+      top = lerp(p[0], p[1], tx);
+      bot = lerp(p[CW], p[CW + 1], tx);
+    }
+    C v;
+    if (latc && (y & mask) == 0)
+      v = Q[yj * CW + xi];
+    else
+      v = lerp(top, bot, C(y & mask) * inv_l);
+    if (MODE & SW_ACCUM)
+      u[int64_t(y) * up + x] += double(v);
+    else
+      st(en + int64_t(y) * ep + x, v);
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_level_write_3d(
+    const T* __restrict__ xprev, const T* __restrict__ xcur, int64_t cp, int64_t cpl,
+    T* __restrict__ en, int64_t ep, int64_t epl, double* __restrict__ u, int64_t up, int64_t upl,
+    int n, int m, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int l = 1 << m, mask = l - 1;
+  const int X0 = 1 + blockIdx.x * BX3, X1 = min(n - 2, X0 + BX3 - 1);
+  const int Y0 = 1 + blockIdx.y * BY3, Y1 = min(n - 2, Y0 + BY3 - 1);
+  const int Z0 = 1 + blockIdx.z * LW_PLANES3, Z1 = min(n - 2, Z0 + LW_PLANES3 - 1);
+  const int I0 = X0 >> m, J0 = Y0 >> m, K0 = Z0 >> m;
+  const int CW = (X1 >> m) - I0 + 2, CH = (Y1 >> m) - J0 + 2, CD = (Z1 >> m) - K0 + 2;
+  const int CP = CW * CH;
+  C* P = reinterpret_cast<C*>(smem);
+  C* Q = P + CP * CD;
+  const int tid = threadIdx.y * BX3 + threadIdx.x;
+  for (int i = tid; i < CP * CD; i += BX3 * BY3) {
+    const int k = i / CP, rem = i - k * CP, j = rem / CW, c = rem - j * CW;
+    const int64_t g = int64_t(K0 + k) * cpl + int64_t(J0 + j) * cp + (I0 + c);
+    P[i] = (MODE & SW_ZERO_OLD) ? C(0) : ld(xprev + g);
+    Q[i] = ld(xcur + g);
+  }
+  __syncthreads();
+  const int x = X0 + threadIdx.x, y = Y0 + threadIdx.y;
+  if (x > X1 || y > Y1) return;
+  const C inv_l = C(1) / C(l);
+  const int xi = (x >> m) - I0, yj = (y >> m) - J0;
+  const C tx = C(x & mask) * inv_l, ty = C(y & mask) * inv_l;
+  const bool latxy = (x & mask) == 0 && (y & mask) == 0;
+  int band = -1;
+  C top = C(0), bot = C(0);
+  for (int z = Z0; z <= Z1; ++z) {
+    const int zk = (z >> m) - K0;
+    if (zk != band) {
+      band = zk;
+      const C* p = P + zk * CP + yj * CW + xi;
+      top = lerp(lerp(p[0], p[1], tx), lerp(p[CW], p[CW + 1], tx), ty);
+      const C* q = p + CP;
+      bot = lerp(lerp(q[0], q[1], tx), lerp(q[CW], q[CW + 1], tx), ty);
+    }
+    C v;
+    if (latxy && (z & mask) == 0)
+      v = Q[zk * CP + yj * CW + xi];
+    else
+      v = lerp(top, bot, C(z & mask) * inv_l);
+    if (MODE & SW_ACCUM)
+      u[int64_t(z) * upl + int64_t(y) * up + x] += double(v);
+    else
+      st(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
+  }
+}
+
 // ------------------------------------------------------------ pack / unpack
 
 template <typename T>
@@ -642,11 +922,26 @@ __global__ __launch_bounds__(256) void k_sample(const double* __restrict__ src, 
 
 // ------------------------------------------------------------ launchers
 
-#define HOMG_LAUNCH(kernel, grid, block, stream, ...)               \
-  do {                                                              \
-    hipLaunchKernelGGL(kernel, grid, block, 0, stream, __VA_ARGS__); \
-    return hipGetLastError();                                       \
+// Start/stop events of the next launch (set by the profiler, else null):
+// hipExtLaunchKernelGGL stamps them with the dispatch's own start and end.
+namespace {
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+}
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+#define HOMG_LAUNCH_SMEM(kernel, grid, block, smem, stream, ...)                              \
+  do {                                                                                        \
+    hipExtLaunchKernelGGL(kernel, grid, block, smem, stream, g_ev_start, g_ev_stop, 0,        \
+                          __VA_ARGS__);                                                       \
+    return hipGetLastError();                                                                 \
   } while (0)
+
+#define HOMG_LAUNCH(kernel, grid, block, stream, ...) \
+  HOMG_LAUNCH_SMEM(kernel, grid, block, 0, stream, __VA_ARGS__)
 
 hipError_t launch_norm2(int d, int n, const double* f, const Lay& fl, double* partials,
                         int* count, hipStream_t s) {
@@ -829,6 +1124,425 @@ hipError_t launch_sample(int d, const double* src, const Lay& sl, int stride, do
   const int side = dl.side, nz = d == 3 ? side : 1;
   HOMG_LAUNCH(k_sample, copy_grid(d, side), dim3(256), s, src + sl.off, sl.pitch, sl.plane,
               stride, dst + dl.off, dl.pitch, dl.plane, side, nz);
+}
+
+// ------------------------------------------------------------ level-blocked launchers
+
+hipError_t launch_gather(int prec, int d, const void* src, const Lay& sl, int l, void* dst,
+                         const Lay& dl, const int* done, hipStream_t s) {
+  (void)done;
+  const int side = dl.side, nz = d == 3 ? side : 1;
+  const dim3 g = copy_grid(d, side);
+  switch (prec) {
+    case PREC_F64:
+      HOMG_LAUNCH((k_gather<double>), g, dim3(256), s, static_cast<const double*>(src) + sl.off,
+                  sl.pitch, sl.plane, l, static_cast<double*>(dst) + dl.off, dl.pitch, dl.plane, side, nz);
+    case PREC_F32:
+      HOMG_LAUNCH((k_gather<float>), g, dim3(256), s, static_cast<const float*>(src) + sl.off,
+                  sl.pitch, sl.plane, l, static_cast<float*>(dst) + dl.off, dl.pitch, dl.plane, side, nz);
+    default:
+      HOMG_LAUNCH((k_gather<bf16>), g, dim3(256), s, static_cast<const bf16*>(src) + sl.off,
+                  sl.pitch, sl.plane, l, static_cast<bf16*>(dst) + dl.off, dl.pitch, dl.plane, side, nz);
+  }
+}
+
+size_t lattice_small_lds(int prec, int d, int nm, bool var) {
+  const size_t cs = prec == PREC_F64 ? 8 : 4;
+  const size_t cnt = d == 2 ? size_t(nm) * nm : size_t(nm) * nm * nm;
+  size_t b = 3 * cnt * cs;
+  if (var) b = ((b + 15) & ~size_t(15)) + cnt * 8;
+  return b;
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <typename T, bool ZERO>
+static hipError_t small_tz(int d, int nm, int l, int it, double omega, const void* e, const Lay& el,
+                           const void* rm, const Lay& rl, const double* am, const Lay& al,
+                           void* xprev, void* xcur, const Lay& cl, const int* done, hipStream_t s) {
+  using C = typename Tr<T>::C;
+  const double hl = 1.0 / double(nm - 1);
+  const C hl2 = C(hl * hl);
+  const size_t lds = lattice_small_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, nm, am != nullptr);
+  const T* ee = static_cast<const T*>(e) + el.off;
+  const T* r = static_cast<const T*>(rm) + rl.off;
+  T* xp = static_cast<T*>(xprev) + cl.off;
+  T* xc = static_cast<T*>(xcur) + cl.off;
+  if (d == 2) {
+    if (am) {
+      hipError_t a = allow_lds(k_lattice_small_2d<T, ZERO, true>, lds);
+      if (a != hipSuccess) return a;
+      HOMG_LAUNCH_SMEM((k_lattice_small_2d<T, ZERO, true>), dim3(1), dim3(SMALL_NT), lds, s, ee,
+                       el.pitch, l, r, rl.pitch, am + al.off, al.pitch, xp, xc, cl.pitch, nm, it,
+                       C(omega), hl2, done);
+    }
+    hipError_t a = allow_lds(k_lattice_small_2d<T, ZERO, false>, lds);
+    if (a != hipSuccess) return a;
+    HOMG_LAUNCH_SMEM((k_lattice_small_2d<T, ZERO, false>), dim3(1), dim3(SMALL_NT), lds, s, ee,
+                     el.pitch, l, r, rl.pitch, (const double*)nullptr, int64_t(0), xp, xc, cl.pitch,
+                     nm, it, C(omega / 4.0), hl2, done);
+  }
+  hipError_t a = allow_lds(k_lattice_small_3d<T, ZERO>, lds);
+  if (a != hipSuccess) return a;
+  HOMG_LAUNCH_SMEM((k_lattice_small_3d<T, ZERO>), dim3(1), dim3(SMALL_NT), lds, s, ee, el.pitch,
+                   el.plane, l, r, rl.pitch, rl.plane, xp, xc, cl.pitch, cl.plane, nm, it,
+                   C(omega / 6.0), hl2, done);
+}
+
+hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double omega, bool zero,
+                                const void* e, const Lay& el, const void* rm, const Lay& rl,
+                                const double* am, const Lay& al, void* xprev, void* xcur,
+                                const Lay& cl, const int* done, hipStream_t s) {
+#define SMALL_CASE(T)                                                                          \
+  return zero ? small_tz<T, true>(d, nm, l, it, omega, e, el, rm, rl, am, al, xprev, xcur, cl, done, s) \
+              : small_tz<T, false>(d, nm, l, it, omega, e, el, rm, rl, am, al, xprev, xcur, cl, done, s)
+  switch (prec) {
+    case PREC_F64: SMALL_CASE(double);
+    case PREC_F32: SMALL_CASE(float);
+    default: SMALL_CASE(bf16);
+  }
+#undef SMALL_CASE
+}
+
+size_t level_write_lds(int prec, int d, int n, int m) {
+  const size_t cs = prec == PREC_F64 ? 8 : 4;
+  if (d == 2) {
+    const size_t cw = size_t(BX2 >> m) + 3, ch = size_t(LW_ROWS2 >> m) + 3;
+    return 2 * cw * ch * cs;
+  }
+  const size_t cw = size_t(BX3 >> m) + 3, ch = size_t(BY3 >> m) + 3, cd = size_t(LW_PLANES3 >> m) + 3;
+  (void)n;
+  return 2 * cw * ch * cd * cs;
+}
+
+template <typename T, int MODE>
+static hipError_t level_write_tm(int d, int n, int m, const void* xprev, const void* xcur,
+                                 const Lay& cl, void* en, const Lay& el, double* u, const Lay& ul,
+                                 const int* done, hipStream_t s) {
+  const size_t lds = level_write_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, n, m);
+  const T* xp = static_cast<const T*>(xprev) + cl.off;
+  const T* xc = static_cast<const T*>(xcur) + cl.off;
+  T* e = en ? static_cast<T*>(en) + el.off : nullptr;
+  double* uu = u ? u + ul.off : nullptr;
+  const int inner = n - 2;
+  if (d == 2) {
+    const dim3 g((inner + BX2 - 1) / BX2, (inner + LW_ROWS2 - 1) / LW_ROWS2);
+    HOMG_LAUNCH_SMEM((k_level_write_2d<T, MODE>), g, dim3(BX2), lds, s, xp, xc, cl.pitch, e,
+                     el.pitch, uu, ul.pitch, n, m, done);
+  }
+  const dim3 g((inner + BX3 - 1) / BX3, (inner + BY3 - 1) / BY3, (inner + LW_PLANES3 - 1) / LW_PLANES3);
+  HOMG_LAUNCH_SMEM((k_level_write_3d<T, MODE>), g, dim3(BX3, BY3), lds, s, xp, xc, cl.pitch,
+                   cl.plane, e, el.pitch, el.plane, uu, ul.pitch, ul.plane, n, m, done);
+}
+
+template <typename T>
+static hipError_t level_write_t(int d, int n, int m, const void* xprev, const void* xcur,
+                                const Lay& cl, void* en, const Lay& el, double* u, const Lay& ul,
+                                int mode, const int* done, hipStream_t s) {
+  switch (mode & 3) {
+    case 0: return level_write_tm<T, 0>(d, n, m, xprev, xcur, cl, en, el, u, ul, done, s);
+    case 1: return level_write_tm<T, 1>(d, n, m, xprev, xcur, cl, en, el, u, ul, done, s);
+    case 2: return level_write_tm<T, 2>(d, n, m, xprev, xcur, cl, en, el, u, ul, done, s);
+    default: return level_write_tm<T, 3>(d, n, m, xprev, xcur, cl, en, el, u, ul, done, s);
+  }
+}
+
+hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, const void* xcur,
+                              const Lay& cl, void* en, const Lay& el, double* u, const Lay& ul,
+                              int mode, const int* done, hipStream_t s) {
+  switch (prec) {
+    case PREC_F64: return level_write_t<double>(d, n, m, xprev, xcur, cl, en, el, u, ul, mode, done, s);
+    case PREC_F32: return level_write_t<float>(d, n, m, xprev, xcur, cl, en, el, u, ul, mode, done, s);
+    default: return level_write_t<bf16>(d, n, m, xprev, xcur, cl, en, el, u, ul, mode, done, s);
+  }
+}
+
+// ------------------------------------------------------------ batched solver
+// Many independent 2D problems of uneven size in ONE persistent launch.  All
+// problems advance in lockstep global steps; at step k every unfinished
+// problem runs the next stage of its own sequence
+//     norm(f), ||f||, residual, norm      (cycle 0)
+//     restriction 0..M-1, the schedule's iterations, residual, norm   (cycles 1, 2, ...)
+// The step's tiles (the same tiles, and the same tile code, as the
+// one-problem kernels) are spread over the co-resident workgroups, and a
+// grid barrier separates steps.  The norm stage of a cycle retires its
+// problem once the relative residual reaches the tolerance.  A barrier
+// that waits longer than its time limit raises an abort flag that every
+// workgroup checks, so the launch always terminates.
+
+__device__ __forceinline__ int tiles_of(int side, int len) {
+  const int inner = side - 2;
+  return ((inner + BX2 - 1) / BX2) * ((inner + len - 1) / len);
+}
+
+struct StageInfo {
+  int kind;   // BK_* below
+  int level;  // restriction: fine level; sweep: level
+  int mode;   // sweep mode bits
+  int sweep;  // sweep index within the cycle
+  int cycle;
+};
+enum { BK_NONE = 0, BK_NORM = 1, BK_FNORM = 2, BK_RES = 3, BK_FIN = 4, BK_RESTRICT = 5, BK_SWEEP = 6 };
+
+__device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* __restrict__ levels_of_sweep, int k) {
+  StageInfo si{BK_NONE, 0, 0, 0, 0};
+  if (k == 0) { si.kind = BK_NORM; return si; }
+  if (k == 1) { si.kind = BK_FNORM; return si; }
+  if (k == 2) { si.kind = BK_RES; return si; }
+  if (k == 3) { si.kind = BK_FIN; si.cycle = 0; return si; }
+  const int L = p.top + p.sweeps + 2;
+  const int j = (k - 4) % L;
+  si.cycle = (k - 4) / L + 1;
+  if (j < p.top) { si.kind = BK_RESTRICT; si.level = j; return si; }
+  if (j < p.top + p.sweeps) {
+    si.kind = BK_SWEEP;
+    si.sweep = j - p.top;
+    si.level = levels_of_sweep[p.sched_off + si.sweep];
+    si.mode = (si.sweep == 0 ? SW_ZERO_OLD : 0) | (si.sweep == p.sweeps - 1 ? SW_ACCUM : 0);
+    return si;
+  }
+  si.kind = (j == p.top + p.sweeps) ? BK_RES : BK_FIN;
+  return si;
+}
+
+__device__ __forceinline__ int stage_tiles(const BatchProblem& p, const StageInfo& si) {
+  switch (si.kind) {
+    case BK_NORM:
+    case BK_RES:
+    case BK_SWEEP: return tiles_of(p.n, p.len[0]);
+    case BK_RESTRICT: {
+      const int nc = (p.n - 1) / (2 << si.level) + 1;
+      return nc >= 3 ? tiles_of(nc, p.len[si.level + 1]) : 0;
+    }
+    case BK_FNORM:
+    case BK_FIN: return 1;
+    default: return 0;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __restrict__ bs,
+                                           int* __restrict__ done, const StageInfo& si, int t,
+                                           const BatchRun& run) {
+  using C = typename Tr<T>::C;
+  const int n = p.n;
+  const int gx = (n - 2 + BX2 - 1) / BX2;
+  const int bx = t % gx, by = t / gx;
+  T* e0 = static_cast<T*>(p.e[0]);
+  T* e1 = static_cast<T*>(p.e[1]);
+  switch (si.kind) {
+    case BK_NORM:
+      tile_norm2_2d(p.f, n, n, p.len[0], p.partials, bx, by, t);
+      break;
+    case BK_RES: {
+      const double h = 1.0 / double(n - 1);
+      tile_residual_2d<T, false>(p.u, n, p.f, n, nullptr, 0, static_cast<T*>(p.r[0]), p.rp[0], n,
+                                 p.len[0], 1.0 / (h * h), p.partials, bx, by, t);
+      break;
+    }
+    case BK_FNORM:
+    case BK_FIN: {
+      const int count = tiles_of(n, p.len[0]);
+      double s = 0.0;
+      for (int i = threadIdx.x; i < count; i += 256) s += p.partials[i];
+      s = block_sum<256>(s);
+      if (threadIdx.x == 0) {
+        BatchState& b = bs[p.id];
+        if (si.kind == BK_FNORM) {
+          const double fn = sqrt(s);
+          b.fnorm = fn > 0.0 ? fn : 1.0;
+        } else {
+          const double rel = sqrt(s) / b.fnorm;
+          p.history[si.cycle] = rel;
+          b.cycles = si.cycle;
+          b.final_rel = rel;
+          int dn = 0;
+          if (!(rel <= 1.7976931348623157e308)) dn = 2;
+          else if (rel <= run.tol) dn = 1;
+          else if (si.cycle >= run.max_cycles) dn = 3;
+          if (dn) done[p.id] = dn;
+        }
+      }
+      break;
+    }
+    case BK_RESTRICT: {
+      const int nc = (n - 1) / (2 << si.level) + 1;
+      const int gxc = (nc - 2 + BX2 - 1) / BX2;
+      tile_restrict_2d<T>(static_cast<const T*>(p.r[si.level]), p.rp[si.level],
+                          static_cast<T*>(p.r[si.level + 1]), p.rp[si.level + 1], nc,
+                          p.len[si.level + 1], t % gxc, t / gxc);
+      break;
+    }
+    case BK_SWEEP: {
+      const T* eo = (si.sweep & 1) ? e1 : e0;
+      T* en = (si.sweep & 1) ? e0 : e1;
+      const int m = si.level;
+      const double hl = double(1 << m) / double(n - 1);
+      const C hl2 = C(hl * hl), w = C(run.omega / 4.0);
+      const T* rm = static_cast<const T*>(p.r[m]);
+#define BATCH_SWEEP(MODE)                                                                          \
+  if (m == 0)                                                                                      \
+    tile_sweep_2d_l0<T, MODE, false>(eo, en, p.ep, rm, p.rp[m], nullptr, 0, p.u, n, n, p.len[0], w, \
+                                     hl2, bx, by);                                                 \
+  else                                                                                             \
+    tile_sweep_2d_coarse<T, MODE, false>(eo, en, p.ep, rm, p.rp[m], nullptr, 0, p.u, n, n,          \
+                                         p.len[0], m, w, hl2, bx, by);
+      switch (si.mode) {
+        case 0: BATCH_SWEEP(0); break;
+        case 1: BATCH_SWEEP(1); break;
+        case 2: BATCH_SWEEP(2); break;
+        default: BATCH_SWEEP(3); break;
+      }
+#undef BATCH_SWEEP
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Grid-wide barrier for co-resident workgroups (sense by generation count).
+// Returns false if the launch was aborted (a wait exceeded its time limit).
+__device__ bool grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks, int* abort,
+                             uint64_t limit_ticks) {
+  __shared__ int ok;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (wall_clock64() - t0 > limit_ticks) {
+          __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+      }
+    }
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+  }
+  __syncthreads();
+  __threadfence();
+  return ok != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_batched_2d(const BatchProblem* __restrict__ probs,
+                                                    BatchState* __restrict__ bs,
+                                                    int* __restrict__ done,
+                                                    const int* __restrict__ levels_of_sweep,
+                                                    const BatchRun* __restrict__ runp,
+                                                    BatchSync* __restrict__ sync) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BatchRun run = *runp;
+  const int P = run.count;
+  int* pref = reinterpret_cast<int*>(smem);  // P + 1 prefix sums of tile counts
+  for (int k = 0; k < run.max_steps; ++k) {
+    // tile counts of this step, then an inclusive scan (fixed order)
+    for (int i = threadIdx.x; i < P; i += 256) {
+      const BatchProblem& p = probs[i];
+      pref[i + 1] = done[i] ? 0 : stage_tiles(p, stage_of(p, levels_of_sweep, k));
+    }
+    if (threadIdx.x == 0) pref[0] = 0;
+    __syncthreads();
+    // serial scan by chunks: each thread scans its chunk, then offsets
+    const int chunk = (P + 255) / 256;
+    const int lo = threadIdx.x * chunk + 1, hi = min(P, lo + chunk - 1);
+    int acc = 0;
+    for (int i = lo; i <= hi; ++i) { acc += pref[i]; pref[i] = acc; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int off = 0;
+      for (int c = 0; c < 256; ++c) {
+        const int clo = c * chunk + 1, chi = min(P, clo + chunk - 1);
+        if (clo > P) break;
+        const int last = pref[chi];
+        for (int i = clo; i <= chi; ++i) pref[i] += off;
+        off += last;
+      }
+    }
+    __syncthreads();
+    const int total = pref[P];
+    if (total == 0) break;
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+      // problem owning global tile g: last i with pref[i] <= g
+      int a = 0, b = P;
+      while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (pref[mid] <= g) a = mid; else b = mid;
+      }
+      const BatchProblem& p = probs[a];
+      batch_tile<T>(p, bs, done, stage_of(p, levels_of_sweep, k), g - pref[a], run);
+      __syncthreads();
+    }
+    if (!grid_barrier(&sync->count, &sync->gen, gridDim.x, &sync->abort, run.barrier_ticks)) break;
+    if (threadIdx.x == 0 && blockIdx.x == 0) sync->steps = k + 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_init(BatchState* bs, int* done, int P, BatchSync* sync) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < P) {
+    bs[i].cycles = -1;
+    bs[i].fnorm = 1.0;
+    bs[i].final_rel = 0.0;
+    done[i] = 0;
+  }
+  if (i == 0) {
+    sync->count = 0;
+    sync->gen = 0;
+    sync->abort = 0;
+    sync->steps = 0;
+  }
+}
+
+int default_walk_len(int d, int n) { return walk_len(d, n); }
+
+int batch_tiles(int side, int len) {
+  const int inner = side - 2;
+  return ((inner + BX2 - 1) / BX2) * ((inner + len - 1) / len);
+}
+
+hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds) {
+  *lds = size_t(P + 1) * sizeof(int);
+  switch (prec) {
+    case PREC_F64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_2d<double>, 256, *lds);
+    case PREC_F32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_2d<float>, 256, *lds);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_2d<bf16>, 256, *lds);
+  }
+}
+
+hipError_t launch_batch(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs, int* done,
+                        const int* levels_of_sweep, const BatchRun* run, BatchSync* sync,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init, dim3((P + 255) / 256), dim3(256), 0, s, bs, done, P, sync);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = size_t(P + 1) * sizeof(int);
+  switch (prec) {
+    case PREC_F64:
+      hipLaunchKernelGGL((k_batched_2d<double>), dim3(grid), dim3(256), lds, s, probs, bs, done, levels_of_sweep, run, sync);
+      break;
+    case PREC_F32:
+      hipLaunchKernelGGL((k_batched_2d<float>), dim3(grid), dim3(256), lds, s, probs, bs, done, levels_of_sweep, run, sync);
+      break;
+    default:
+      hipLaunchKernelGGL((k_batched_2d<bf16>), dim3(grid), dim3(256), lds, s, probs, bs, done, levels_of_sweep, run, sync);
+      break;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace homg

@@ -47,7 +47,8 @@ class KernelTime(ctypes.Structure):
                 ("reserved", ctypes.c_int), ("launches", ctypes.c_longlong), ("ms", ctypes.c_double)]
 
 
-KIND_NAMES = {0: "norm", 1: "residual", 2: "finalize", 3: "restrict", 4: "sweep"}
+KIND_NAMES = {0: "norm", 1: "residual", 2: "finalize", 3: "restrict", 4: "sweep",
+              5: "gather", 6: "lattice", 7: "level_write"}
 
 
 def load_library(path=LIB_PATH):
@@ -72,13 +73,23 @@ def load_library(path=LIB_PATH):
     L.homg_step_cycle.argtypes = [H, dp, dp, vp]
     L.homg_set_profiling.argtypes = [H, ctypes.c_int]
     L.homg_get_profile.argtypes = [H, ctypes.POINTER(KernelTime), ctypes.c_int, ip]
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.homg_batch_create.argtypes = [ctypes.POINTER(H), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(Options)]
+    L.homg_batch_solve.argtypes = [H, PP, PP, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double),
+                                   ip, ip]
+    L.homg_batch_set_tile_rows.argtypes = [H, ctypes.c_int64, ctypes.c_int]
+    L.homg_batch_tune.argtypes = [H, PP, PP, ctypes.c_double, vp, ctypes.c_char_p]
+    L.homg_batch_destroy.argtypes = [H]
     L.homg_last_error.argtypes = [H]
     L.homg_last_error.restype = ctypes.c_char_p
     L.homg_version.argtypes = []
     L.homg_version.restype = ctypes.c_char_p
     for name in ("homg_create", "homg_destroy", "homg_set_coefficient", "homg_solve",
                  "homg_solve_cycles", "homg_residual", "homg_get_schedule", "homg_step_restrict",
-                 "homg_step_sweeps", "homg_step_cycle", "homg_set_profiling", "homg_get_profile"):
+                 "homg_step_sweeps", "homg_step_cycle", "homg_set_profiling", "homg_get_profile",
+                 "homg_batch_create", "homg_batch_solve", "homg_batch_set_tile_rows", "homg_batch_tune",
+                 "homg_batch_destroy"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -116,7 +127,7 @@ class Solver:
     """One HOMG solver for a d-dimensional grid of side n = 2^k + 1."""
 
     def __init__(self, ndim, n, levels=0, stencil=None, omega=0.0, max_i=4, max_cycles=200,
-                 schedule=None, precision="fp64", temporal_block=0):
+                 schedule=None, precision="fp64", temporal_block=1):
         L = lib()
         if stencil is None:
             stencil = LAPLACE_5PT_2D if ndim == 2 else LAPLACE_7PT_3D
@@ -221,6 +232,68 @@ class Solver:
 
     def step_cycle(self, r0, acc, stream=None):
         self._check(lib().homg_step_cycle(self._h, _ptr(r0), _ptr(acc), _stream(stream)))
+
+
+class BatchSolver:
+    """Many independent 2D Poisson problems solved in one persistent launch."""
+
+    def __init__(self, sides, precision="fp32", omega=0.0, max_i=4, max_cycles=200):
+        L = lib()
+        opt = Options()
+        L.homg_options_init(ctypes.byref(opt))
+        opt.omega = omega
+        opt.max_i = max_i
+        opt.max_cycles = max_cycles
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.sides = [int(v) for v in sides]
+        arr = (ctypes.c_int64 * len(self.sides))(*self.sides)
+        h = ctypes.c_void_p()
+        st = L.homg_batch_create(ctypes.byref(h), len(self.sides), arr, ctypes.byref(opt))
+        if st != HOMG_OK:
+            raise HomgError(st, L.homg_last_error(None).decode())
+        self._h = h
+
+    def _check(self, st):
+        if st != HOMG_OK:
+            raise HomgError(st, lib().homg_last_error(None).decode())
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ctypes.c_void_p * len(ts))(*[_ptr(t).value for t in ts])
+
+    def solve(self, fs, us, tol=1e-10, stream=None, raise_on_status=True):
+        n = len(self.sides)
+        if len(fs) != n or len(us) != n:
+            raise ValueError("need one f and one u per problem")
+        for t, s in zip(fs, self.sides):
+            if tuple(t.shape) != (s, s):
+                raise ValueError("array shape does not match its side")
+        rel = (ctypes.c_double * n)()
+        cyc = (ctypes.c_int * n)()
+        sts = (ctypes.c_int * n)()
+        st = lib().homg_batch_solve(self._h, self._ptrs(fs), self._ptrs(us), tol, _stream(stream), rel, cyc, sts)
+        out = {"status": st, "relres": list(rel), "cycles": list(cyc), "statuses": list(sts)}
+        if raise_on_status:
+            self._check(st)
+        return out
+
+    def set_tile_rows(self, side, rows):
+        self._check(lib().homg_batch_set_tile_rows(self._h, side, rows))
+
+    def tune(self, fs, us, tol=1e-10, cache_path=None, stream=None):
+        self._check(lib().homg_batch_tune(self._h, self._ptrs(fs), self._ptrs(us), tol, _stream(stream),
+                                          cache_path.encode() if cache_path else None))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().homg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version():

@@ -121,18 +121,19 @@ def test_step_restrict(B, torch_cuda, d, n, prec):
         assert np.all(np.abs(got[inn] - want[inn]) <= tol[inn])
 
 
+@pytest.mark.parametrize("blocked", [0, 1])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("d,n", [(2, 257), (2, 1025), (3, 33), (3, 65)])
-def test_step_sweeps_every_level(B, torch_cuda, d, n, prec):
+def test_step_sweeps_every_level(B, torch_cuda, d, n, prec, blocked):
     torch = torch_cuda
     rng = np.random.default_rng(200 + n + d)
     k = O.check_side(n)
-    s = B.Solver(d, n, precision=prec)
+    s = B.Solver(d, n, precision=prec, temporal_block=blocked)
     omega = O.default_omega(d)
     for level in range(k):
         nm = (n - 1) // (1 << level) + 1
         for iters in (1, 3):
-            say("sweeps d=%d n=%d level=%d iters=%d prec=%s" % (d, n, level, iters, prec))
+            say("sweeps d=%d n=%d level=%d iters=%d prec=%s blocked=%d" % (d, n, level, iters, prec, blocked))
             e0 = representable(torch, rand_interior(rng, d, n), prec)
             rm = representable(torch, rand_interior(rng, d, nm), prec)
             out = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
@@ -168,6 +169,33 @@ def test_step_cycle_fp64(B, torch_cuda, d, n, max_i):
     want = O.mfmg_cycle(d, n, r0, O.default_schedule(k, max_i), O.default_omega(d))
     got = host(acc)
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("d,n,max_i,var", [(2, 1025, 4, False), (2, 257, 32, False), (2, 129, 4, True),
+                                           (3, 129, 4, False), (3, 65, 8, False)])
+def test_level_blocked_path_is_bitwise_identical(B, torch_cuda, d, n, max_i, var, prec):
+    """The level-blocked path (compact-lattice iterations, one whole-grid pass
+    per level) and the one-launch-per-iteration path give the same bits."""
+    torch = torch_cuda
+    if var and prec != "fp64":
+        pytest.skip("variable coefficient covered in FP64")
+    say("blocked vs per-iteration d=%d n=%d max_i=%d var=%s prec=%s" % (d, n, max_i, var, prec))
+    f = dev(torch, W.uniform(d, n, seed=17))
+    a = None
+    if var:
+        a_np, _ = W.grf_problem(n, seed=17)
+        a = dev(torch, a_np)
+    outs = []
+    for blocked in (0, 1):
+        s = B.Solver(d, n, max_i=max_i, precision=prec, temporal_block=blocked,
+                     stencil=B.DIFFUSION_5PT_2D if var else None)
+        if var:
+            s.set_coefficient(a)
+        u = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+        s.solve_cycles(f, u, 3)
+        outs.append(host(u))
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_schedule_matches_oracle(B, torch_cuda):
