@@ -93,6 +93,8 @@ typedef struct homg_info {
     long long sweeps;      /* whole-grid iterations executed */
     long long launches;    /* kernel launches enqueued */
     int host_syncs;        /* stream synchronisations to read the residual norm */
+    int smoother_fell_back;/* 1 if the learned smoother was replaced by damped Jacobi
+                              during this solve (see homg_set_smoother) */
 } homg_info;
 
 /* Fill *opt with the defaults and set struct_size. */
@@ -184,7 +186,8 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   kind: 0 norm of f, 1 residual, 2 norm finalisation, 3 restriction from
  *   `level` to level+1, 4 whole-grid iteration at `level`, 5 sampling of the
  *   grid on the level lattice, 6 iterations on the compact lattice, 7
- *   whole-grid pass of a blocked level.
+ *   whole-grid pass of a blocked level, 8 learned relaxation of the level
+ *   lattice (level 0: of the whole grid).
  *   mode (kinds 4, 6, 7): bit 0 = starts from e = 0, bit 1 = adds into u;
  *   bit 2 (kind 6) = the whole lattice held by one workgroup.
  * homg_get_profile synchronises outstanding events, then writes up to cap
@@ -239,6 +242,117 @@ homg_status homg_batch_set_tile_rows(homg_batch b, int64_t side, int rows);
 homg_status homg_batch_tune(homg_batch b, const double *const *f, double *const *u, double tol,
                             void *stream, const char *cache_path);
 homg_status homg_batch_destroy(homg_batch b);
+
+/*
+ * Learned relaxation (2D stencils).  The paper relaxes the lattice nodes of
+ * the fused task with damped Jacobi (Sec. 2, level-m relaxation, the
+ * explicit Euler step of the heat equation).  With HOMG_SMOOTHER_LEARNED a
+ * small bias-free network replaces it; interpolation, restriction, schedule
+ * and restart are unchanged.  On the compact level-m lattice (spacing
+ * h_l = 2^m h) at every interior lattice node p:
+ *   rho = (h_l^2 r_m(p) - sum_q a_pq (x_p - x_q)) / sum_q a_pq  (a_pq: harmonic mean
+ *         of the nodal coefficient across the face to lattice neighbour q; 1 for
+ *         the Laplacian; damped Jacobi is x + omega rho),
+ *   X = (rho, rho (a_E - a_W)/(a_E + a_W), rho (a_N - a_S)/(a_N + a_S)),
+ *   H_c = max(0, sum_ci sum_k W1[c][ci][k] X_ci(p + o_k)), c = 0..15, 0 on the boundary,
+ *   x'(p) = x(p) + sum_c sum_k W2[c][k] H_c(p + o_k),
+ * with the 3x3 offsets o_k = (dy, dx), k = 3(dy+1) + (dx+1) (a correlation;
+ * on the whole grid, taps dilated by 2^m) and values outside the lattice 0.
+ * Weights: HOMG_SMOOTHER_WEIGHTS = 576 values, W1[c][ci][k] at 27c + 9ci + k,
+ * then W2[c][k] at 432 + 9c + k.  They are stored in BF16 (round to nearest
+ * even) and the network computes in FP32.
+ *
+ * homg_set_smoother: smoother HOMG_SMOOTHER_JACOBI or _LEARNED; w = 576 FP32
+ *   values on the DEVICE (NULL keeps the weights already set; required the
+ *   first time LEARNED is selected), rounded to BF16 on copy.
+ *   fallback_ratio (<= 0 selects 1.0): a solve that sees a cycle whose
+ *   relative residual is not below fallback_ratio times the previous one
+ *   switches to damped Jacobi for the rest of that solve (checked at each
+ *   host synchronisation; info->smoother_fell_back = 1).  HOMG_ERR_UNSUPPORTED
+ *   for 3D handles.
+ * homg_get_smoother_weights: copies the FP32 values of the BF16 weights (576)
+ *   to the device array w_out.
+ * homg_smoother_gate: for each of `count` held-out right-hand sides f[i]
+ *   (device arrays of the handle's size), runs `cycles` cycles from u = 0 with
+ *   damped Jacobi and with the learned weights and reports the geometric-mean
+ *   per-cycle contraction (relres_cycles / relres_0)^(1/cycles) of each in
+ *   rho_jacobi[i], rho_learned[i] (host arrays, may be NULL); *accepted = 1
+ *   iff the learned one is not worse on any problem.  Synchronises.
+ */
+#define HOMG_SMOOTHER_WEIGHTS 576
+enum { HOMG_SMOOTHER_JACOBI = 0, HOMG_SMOOTHER_LEARNED = 1 };
+
+homg_status homg_set_smoother(homg_handle h, int smoother, const float *w, double fallback_ratio,
+                              void *stream);
+homg_status homg_get_smoother_weights(homg_handle h, float *w_out, void *stream);
+homg_status homg_smoother_gate(homg_handle h, int count, const double *const *f, int cycles,
+                               void *stream, double *rho_learned, double *rho_jacobi,
+                               int *accepted);
+
+/*
+ * Training of the learned relaxation on pairs that plain HOMG generates.
+ *
+ * homg_trainer_add_problem: h is a 2D handle (its coefficient set for the
+ *   diffusion stencil); runs `cycles` plain damped-Jacobi HOMG cycles on the
+ *   device right-hand side f from u = 0 and records every relaxation input
+ *   of every level as a sample: the compact lattice iterate x_t, the level
+ *   residual r_m, the lattice coefficient and the error delta = x* - x_t
+ *   against the exact level solution x* (A_m x* = h_l^2 r_m, solved by HOMG
+ *   to relative residual 1e-12 on a handle of the compact side).  Samples
+ *   are stored on the device in FP32.  The handle's smoother is left as it was.
+ * homg_trainer_train: Adam (FP32 master weights, moments start at 0) from
+ *   the device weights w0 for opt->steps steps; each step draws opt->batch
+ *   samples uniformly (splitmix64 from opt->seed), and minimises the mean of
+ *   L = E(delta - y)/E(delta), E(v) = v^T A_m v, the energy-norm error left by
+ *   one learned relaxation relative to the error before it.  Writes the FP32
+ *   values of the trained BF16 weights to the device array w_out and, if
+ *   loss_hist (host, opt->steps entries) is given, each step's batch loss.
+ * homg_trainer_loss: the mean of L over all samples for device weights w
+ *   (used as given, no rounding), to *mean_loss (host).  Synchronises.
+ */
+typedef struct homg_trainer_ctx *homg_trainer;
+typedef struct homg_train_options {
+    size_t struct_size;    /* sizeof(homg_train_options) */
+    int steps;             /* Adam steps (>= 1) */
+    int batch;             /* samples per step (1..256) */
+    float lr, beta1, beta2, eps;
+    uint64_t seed;
+    int reserved[8];       /* must be 0 */
+} homg_train_options;
+
+void homg_train_options_init(homg_train_options *opt);  /* 300 steps, batch 8, lr 1e-3, Adam defaults */
+homg_status homg_trainer_create(homg_trainer *out);
+homg_status homg_trainer_add_problem(homg_trainer t, homg_handle h, const double *f, int cycles,
+                                     void *stream);
+homg_status homg_trainer_count(homg_trainer t, int *samples);
+homg_status homg_trainer_train(homg_trainer t, const float *w0, const homg_train_options *opt,
+                               float *w_out, double *loss_hist, void *stream);
+homg_status homg_trainer_loss(homg_trainer t, const float *w, double *mean_loss, void *stream);
+homg_status homg_trainer_destroy(homg_trainer t);
+
+/*
+ * Kernel-level entry points of the learned relaxation on one compact
+ * lattice (testing and measurement).  Dense FP32 device arrays of side
+ * nm >= 3 (node (J, I) at J*nm + I); x is the iterate with its boundary
+ * entries 0 (they enter the flux of the nodes next to the boundary);
+ * boundary entries of r and delta are not read; a = nodal coefficient
+ * (NULL: Laplacian); hl = lattice spacing; w = 576 FP32 weights used as given.
+ * homg_learn_forward: y (network output, interior nodes; boundary entries
+ *   not written).
+ * homg_learn_grad: grad (device, 577 doubles) = dL/dw for the sample, then
+ *   E(delta - y); *loss (host) = L.  Allocates its own workspace; synchronises.
+ * homg_learn_adam: one Adam step (Kingma and Ba) on 576 FP32 master weights
+ *   theta with moments m1, m2 (device, updated in place), gradient grad
+ *   (device, 576 doubles), 1-based step t; w_out (device, 576) receives the
+ *   FP32 values of theta rounded to BF16.
+ */
+homg_status homg_learn_forward(int nm, double hl, const float *x, const float *r, const float *a,
+                               const float *w, float *y, void *stream);
+homg_status homg_learn_grad(int nm, double hl, const float *x, const float *r, const float *a,
+                            const float *delta, const float *w, double *grad, double *loss,
+                            void *stream);
+homg_status homg_learn_adam(float *theta, float *m1, float *m2, const double *grad, int t, float lr,
+                            float beta1, float beta2, float eps, float *w_out, void *stream);
 
 /* Text of the last error on h (or of the calling thread if h is NULL). */
 const char *homg_last_error(homg_handle h);

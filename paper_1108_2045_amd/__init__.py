@@ -4,5 +4,6 @@ The solver runs in the HIP library libhomg.so (C ABI in include/homg.h);
 this package only loads it and marshals arguments.  Importing the package
 does not touch the GPU; creating a Solver does.
 """
-from .homg import (DIFFUSION_5PT_2D, LAPLACE_5PT_2D, LAPLACE_7PT_3D, BatchSolver, HomgError,  # noqa: F401
-                   Solver, lib, version)
+from .homg import (DIFFUSION_5PT_2D, JACOBI, LAPLACE_5PT_2D, LAPLACE_7PT_3D, LEARNED,  # noqa: F401
+                   SMOOTHER_WEIGHTS, BatchSolver, HomgError, Solver, Trainer, learn_adam, learn_forward,
+                   learn_grad, lib, version)

@@ -41,7 +41,7 @@ namespace {
 
 enum Kind {
   K_NORM = 0, K_RESIDUAL = 1, K_FINALIZE = 2, K_RESTRICT = 3, K_SWEEP = 4,
-  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7
+  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7, K_LEARNED = 8
 };
 
 // Event-pair timing of individual launches, harvested at synchronisation.
@@ -86,6 +86,12 @@ struct homg_ctx {
   std::string err;
   long long launches = 0;
   Profiler prof;
+  // learned relaxation (2D): 0 damped Jacobi, 1 the network with weights w
+  int smoother = 0;
+  int active_smoother = 0;     // smoother of the solve in progress (after any fallback)
+  double fallback_ratio = 1.0; // per-cycle contraction at which a solve falls back to Jacobi
+  uint16_t* wbf = nullptr;     // the 576 weights in BF16
+  float* w32 = nullptr;        // their FP32 values (what the kernels read)
 };
 
 namespace {
@@ -188,6 +194,8 @@ void free_ctx(homg_ctx* h) {
   (void)hipFree(h->st);
   (void)hipFree(h->hist);
   (void)hipFree(h->zero_flag);
+  (void)hipFree(h->wbf);
+  (void)hipFree(h->w32);
   if (h->h_st) (void)hipHostFree(h->h_st);
   if (h->h_hist) (void)hipHostFree(h->h_hist);
   for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
@@ -206,8 +214,12 @@ homg_status dev_alloc(homg_ctx* h, void** p, size_t bytes) {
 // `it` iterations of level m on the whole-grid state e[*cur] (Sec. 2, fused
 // relax+interpolate task), leaving the result in e[*cur] (or added into acc
 // when `last`).  `first`: the state is e = 0 (first level of a cycle).
+homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last, int* cur,
+                              double* acc, const int* done, hipStream_t s);
+
 homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cur, double* acc,
                       const int* done, hipStream_t s) {
+  if (h->active_smoother == 1) return run_level_learned(h, m, it, first, last, cur, acc, done, s);
   const Lay none;
   const double* am = h->has_coef ? h->a[m] : nullptr;
   const Lay& alm = am ? h->al[m] : none;
@@ -263,6 +275,51 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cu
   return HOMG_OK;
 }
 
+// `it` iterations of level m with the learned relaxation (same contract as
+// run_level).  A level-m iteration reads only lattice values, so the
+// iterations run on the compact lattice and one whole-grid pass writes the
+// level's final state (lattice nodes x_it, every other node the interpolant
+// of x_{it-1}); level 0 is the whole grid.
+homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last, int* cur,
+                              double* acc, const int* done, hipStream_t s) {
+  const Lay none;
+  const double* am = h->has_coef ? h->a[m] : nullptr;
+  const Lay& alm = am ? h->al[m] : none;
+  const int l = 1 << m, nm = (h->n - 1) / l + 1;
+  const double hl = double(l) / double(h->n - 1);
+  if (m == 0) {
+    for (int t = 0; t < it; ++t) {
+      int mode = 0;
+      if (first && t == 0) mode |= SW_ZERO_OLD;
+      if (last && t == it - 1) mode |= SW_ACCUM;
+      LAUNCH_K(h, s, K_LEARNED, 0, mode,
+               launch_learned_iter(h->prec, nm, hl, h->e[*cur], h->el, h->e[1 - *cur], h->r[0],
+                                   h->rl[0], am, alm, acc, h->dl, h->w32, mode, done, s));
+      *cur = 1 - *cur;
+    }
+    return HOMG_OK;
+  }
+  const Lay& cl = h->rl[m];
+  void* X[2] = {h->xc[2 * m], h->xc[2 * m + 1]};
+  if (!first)
+    LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X[0], cl, done, s));
+  int src = 0;
+  for (int t = 1; t <= it; ++t) {
+    const int mode = (first && t == 1) ? SW_ZERO_OLD : 0;
+    LAUNCH_K(h, s, K_LEARNED, m, mode,
+             launch_learned_iter(h->prec, nm, hl, X[src], cl, X[1 - src], h->r[m], h->rl[m], am,
+                                 alm, nullptr, none, h->w32, mode, done, s));
+    src = 1 - src;
+  }
+  int wmode = last ? SW_ACCUM : 0;
+  if (first && it == 1) wmode |= SW_ZERO_OLD;  // x_0 = 0 was never stored
+  LAUNCH_K(h, s, K_LEVEL_WRITE, m, wmode,
+           launch_level_write(h->prec, h->d, h->n, m, X[1 - src], X[src], cl, h->e[1 - *cur], h->el,
+                              acc, h->dl, wmode, done, s));
+  *cur = 1 - *cur;
+  return HOMG_OK;
+}
+
 // Enqueue one MFMG cycle (Sec. 2): restriction pyramid of r_0, the
 // schedule's whole-grid iterations with the last one adding e into acc,
 // then (if f != null) the new residual and its norm as history[cycle].
@@ -309,6 +366,8 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long launches0 = h->launches;
   const int* done = &h->st->done;
+  h->active_smoother = h->smoother;
+  int fell_back = 0;
 
   LAUNCH(h, launch_init_state(h->st, stop_on_tol ? tol : 0.0, stop_on_tol ? 1 : 0, s));
   int count = 0;
@@ -337,8 +396,18 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
     if (h->prof.on)
       if (homg_status pe = prof_harvest(h)) return pe;
     if (h->h_st->done || enqueued >= limit) break;
-    // size the next batch from the observed contraction
     const int c = h->h_st->cycles;
+    // learned relaxation: fall back to damped Jacobi for the rest of the solve
+    // once a cycle contracts the residual by less than fallback_ratio
+    if (h->active_smoother == 1) {
+      for (int i = 1; i <= c; ++i)
+        if (!(h->h_hist[i] < h->fallback_ratio * h->h_hist[i - 1])) {
+          h->active_smoother = 0;
+          fell_back = 1;
+          break;
+        }
+    }
+    // size the next batch from the observed contraction
     double q = 0.5;
     if (c >= 2 && h->h_hist[c - 1] > 0) q = h->h_hist[c] / h->h_hist[c - 1];
     q = std::min(std::max(q, 1e-3), 0.95);
@@ -359,7 +428,9 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
     info->sweeps = (long long)cycles * h->total_sweeps;
     info->launches = h->launches - launches0;
     info->host_syncs = syncs;
+    info->smoother_fell_back = fell_back;
   }
+  h->active_smoother = h->smoother;
   if (h->h_st->done == 2) return fail(h, HOMG_ERR_NUMERICAL, "non-finite residual norm");
   if (stop_on_tol && h->h_st->done != 1)
     return fail(h, HOMG_ERR_NOT_CONVERGED, "max_cycles reached above tol");
@@ -367,6 +438,27 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
 }
 
 }  // namespace
+
+namespace homg {
+
+void ctx_view(const homg_ctx* h, CtxView* v) {
+  v->d = h->d;
+  v->n = h->n;
+  v->levels = h->levels;
+  v->stencil = h->stencil;
+  v->prec = h->prec;
+  v->has_coef = h->has_coef ? 1 : 0;
+  v->smoother = h->smoother;
+  v->fallback_ratio = h->fallback_ratio;
+  v->sched = h->sched;
+}
+
+hipError_t ctx_level_coefficient(const homg_ctx* h, int m, double* dense, hipStream_t s) {
+  if (!h->has_coef || m < 0 || m >= h->levels) return hipErrorInvalidValue;
+  return launch_unpack(PREC_F64, h->d, h->a[m], h->al[m], dense, h->cdl[m], s);
+}
+
+}  // namespace homg
 
 extern "C" {
 
@@ -621,6 +713,7 @@ homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* 
   if (homg_status c = check_ready(h)) return c;
   DeviceGuard guard(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  h->active_smoother = h->smoother;
   LAUNCH(h, launch_pack(h->prec, h->d, e_old, h->dl, h->e[0], h->el, s));
   LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
   int cur = 0;
@@ -639,6 +732,7 @@ homg_status homg_step_cycle(homg_handle h, const double* r0, double* acc, void* 
   if (homg_status c = check_ready(h)) return c;
   DeviceGuard guard(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  h->active_smoother = h->smoother;
   LAUNCH(h, launch_pack(h->prec, h->d, r0, h->dl, h->r[0], h->rl[0], s));
   return enqueue_cycle(h, nullptr, acc, 1, h->zero_flag, s);
 }
@@ -670,6 +764,98 @@ homg_status homg_get_profile(homg_handle h, homg_kernel_time* out, int cap, int*
       ++i;
     }
   }
+  return HOMG_OK;
+}
+
+homg_status homg_set_smoother(homg_handle h, int smoother, const float* w, double fallback_ratio,
+                              void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (smoother != HOMG_SMOOTHER_JACOBI && smoother != HOMG_SMOOTHER_LEARNED)
+    return fail(h, HOMG_ERR_INVALID_ARG, "unknown smoother");
+  if (smoother == HOMG_SMOOTHER_LEARNED && h->d != 2)
+    return fail(h, HOMG_ERR_UNSUPPORTED, "the learned smoother is 2D only");
+  if (smoother == HOMG_SMOOTHER_LEARNED && !w && !h->w32)
+    return fail(h, HOMG_ERR_INVALID_ARG, "the learned smoother needs weights");
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (w) {
+    if (!h->w32) {
+      if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->w32), sizeof(float) * NW)) return e;
+      if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->wbf), sizeof(uint16_t) * NW)) return e;
+    }
+    LAUNCH(h, launch_round_weights(w, h->wbf, h->w32, s));
+  }
+  if (smoother == HOMG_SMOOTHER_LEARNED && h->xc.empty()) {
+    // compact lattice pairs of every coarse level (boundary nodes stay 0)
+    const int eb = prec_bytes(h->prec);
+    h->xc.assign(2 * h->levels, nullptr);
+    for (int m = 1; m < h->levels; ++m)
+      for (int b = 0; b < 2; ++b) {
+        if (homg_status e = dev_alloc(h, &h->xc[2 * m + b], size_t(h->rl[m].alloc) * eb)) return e;
+        HIPCHK(h, hipMemsetAsync(h->xc[2 * m + b], 0, size_t(h->rl[m].alloc) * eb, s));
+      }
+  }
+  h->smoother = smoother;
+  h->active_smoother = smoother;
+  h->fallback_ratio = fallback_ratio > 0.0 ? fallback_ratio : 1.0;
+  return HOMG_OK;
+}
+
+homg_status homg_get_smoother_weights(homg_handle h, float* w_out, void* stream) {
+  if (!h || !w_out) return fail(h, HOMG_ERR_INVALID_ARG, "null argument");
+  if (!h->w32) return fail(h, HOMG_ERR_INVALID_ARG, "no weights set");
+  DeviceGuard guard(h->device);
+  HIPCHK(h, hipMemcpyAsync(w_out, h->w32, sizeof(float) * NW, hipMemcpyDeviceToDevice,
+                           static_cast<hipStream_t>(stream)));
+  return HOMG_OK;
+}
+
+homg_status homg_smoother_gate(homg_handle h, int count, const double* const* f, int cycles,
+                               void* stream, double* rho_learned, double* rho_jacobi,
+                               int* accepted) {
+  if (!h || !f || count < 1 || cycles < 1 || !accepted)
+    return fail(h, HOMG_ERR_INVALID_ARG, "invalid gate arguments");
+  if (!h->w32) return fail(h, HOMG_ERR_INVALID_ARG, "no learned weights set");
+  if (cycles > h->max_cycles) return fail(h, HOMG_ERR_INVALID_ARG, "cycles exceeds max_cycles");
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* u = nullptr;
+  const size_t bytes = sizeof(double) * size_t(h->dl.alloc);
+  if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&u), bytes)) return e;
+  const int keep = h->smoother;
+  const double keep_ratio = h->fallback_ratio;
+  homg_status st = HOMG_OK;
+  int ok = 1;
+  std::vector<double> hist(cycles + 1);
+  for (int i = 0; i < count && st == HOMG_OK; ++i) {
+    double rho[2] = {0.0, 0.0};
+    for (int which = 0; which < 2 && st == HOMG_OK; ++which) {
+      h->smoother = which == 0 ? HOMG_SMOOTHER_JACOBI : HOMG_SMOOTHER_LEARNED;
+      h->fallback_ratio = 1e300;  // measure the smoother as it is
+      if (hipMemsetAsync(u, 0, bytes, s) != hipSuccess) {
+        st = fail(h, HOMG_ERR_HIP, "hipMemsetAsync failed");
+        break;
+      }
+      homg_info info{};
+      info.history = hist.data();
+      info.history_cap = cycles + 1;
+      st = solve_impl(h, f[i], u, 1.0, cycles, stream, &info);
+      if (st != HOMG_OK) break;
+      // geometric mean of the per-cycle contraction
+      rho[which] = (hist[0] > 0.0) ? std::pow(hist[cycles] / hist[0], 1.0 / cycles) : 0.0;
+    }
+    if (st != HOMG_OK) break;
+    if (rho_jacobi) rho_jacobi[i] = rho[0];
+    if (rho_learned) rho_learned[i] = rho[1];
+    if (!(rho[1] <= rho[0])) ok = 0;
+  }
+  h->smoother = keep;
+  h->active_smoother = keep;
+  h->fallback_ratio = keep_ratio;
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(u);
+  if (st != HOMG_OK) return st;
+  *accepted = ok;
   return HOMG_OK;
 }
 

@@ -4,6 +4,9 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
+
+struct homg_ctx;
 
 namespace homg {
 
@@ -134,10 +137,63 @@ hipError_t launch_batch(int prec, int P, int grid, const BatchProblem* probs, Ba
                         const int* levels_of_sweep, const BatchRun* run, BatchSync* sync,
                         hipStream_t s);
 
+// ---- learned lattice smoother (2D)
+constexpr int HID = 16;                 // hidden channels
+constexpr int NW1 = HID * 3 * 9;        // first layer: 16 x 3 channels x 3x3 taps
+constexpr int NW = NW1 + HID * 9;       // + second layer: 16 x 3x3 taps = 576 weights
+constexpr int TRAIN_MAX_ROWS = 1024;    // workgroups (partial-sum rows) of one backward launch
+constexpr int ENERGY_MAX_PARTS = 1024;  // workgroups of one energy launch
+
+// One learned relaxation of every interior node of a compact lattice of
+// side nm and spacing hl: xo = xi + y.  Layouts: xl for xi/xo, rl for r,
+// al for the FP64 nodal coefficient a (null: constant coefficient); mode
+// SW_ZERO_OLD (xi = 0, not read) / SW_ACCUM (u += xi + y instead of the store).
+// w: the 576 weights as FP32 values.
+hipError_t launch_learned_iter(int prec, int nm, double hl, const void* xi, const Lay& xl,
+                               void* xo, const void* r, const Lay& rl, const double* a,
+                               const Lay& al, double* u, const Lay& ul, const float* w, int mode,
+                               const int* done, hipStream_t s);
+// Training on dense FP32 compact arrays of side nm.  fwd: z = delta - y (y if
+// delta is null).  bwd: per-workgroup partial sums of dL/dw (576) and E(z)
+// into part[j * pstride + row], rows = train_bwd_rows(nm); e0 = &E(delta).
+hipError_t launch_train_fwd(int nm, float hl2, const float* x, const float* r, const float* a,
+                            const float* delta, float* z, const float* w, hipStream_t s);
+int train_bwd_rows(int nm);
+hipError_t launch_train_bwd(int nm, float hl2, const float* x, const float* r, const float* a,
+                            const float* z, const double* e0, const float* w, float* part,
+                            int64_t pstride, hipStream_t s);
+// out[j] = sum of part[j][0..rows) (FP64, fixed order), j = 0..NW.
+hipError_t launch_train_reduce(const float* part, int64_t pstride, int rows, double* out,
+                               hipStream_t s);
+hipError_t launch_train_adam(const double* sums, int batch, const double* e0s, const int* idx,
+                             float* theta, float* m1, float* m2, uint16_t* wbf, float* w32,
+                             int step, float lr, float beta1, float beta2, float eps, double* loss,
+                             hipStream_t s);
+// *out = E(v) = v^T A v over interior nodes (part: ENERGY_MAX_PARTS doubles).
+hipError_t launch_energy(const float* v, const float* a, int nm, double* part, double* out,
+                         hipStream_t s);
+hipError_t launch_round_weights(const float* src, uint16_t* wbf, float* w32, hipStream_t s);
+// dst (dense FP32, side nm) = src on the l-lattice, or sub - src when sub != null.
+hipError_t launch_lattice_f32(const double* src, int64_t sp, int l, const double* sub, int64_t bp,
+                              int nm, float* dst, hipStream_t s);
+
+hipError_t launch_add_dense(double* v, const double* e, int64_t count, hipStream_t s);
+
+// What the trainer needs to know about a solver handle.
+struct CtxView {
+  int d = 0, n = 0, levels = 0, stencil = 0, prec = 0, has_coef = 0, smoother = 0;
+  double fallback_ratio = 1.0;
+  std::vector<int> sched;  // (level, iterations) pairs
+};
+void ctx_view(const homg_ctx* h, CtxView* v);
+// The handle's level-m nodal coefficient as a dense FP64 array (side (n-1)/2^m + 1).
+hipError_t ctx_level_coefficient(const homg_ctx* h, int m, double* dense, hipStream_t s);
+
 // Record the text of the calling thread's last error (homg_last_error(NULL)).
 void set_last_error(const char* msg);
 
 // Start/stop events stamped on the next launch of this thread (null: none).
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
+void current_launch_events(hipEvent_t* start, hipEvent_t* stop);
 
 }  // namespace homg

@@ -933,6 +933,11 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   g_ev_stop = stop;
 }
 
+void current_launch_events(hipEvent_t* start, hipEvent_t* stop) {
+  *start = g_ev_start;
+  *stop = g_ev_stop;
+}
+
 #define HOMG_LAUNCH_SMEM(kernel, grid, block, smem, stream, ...)                              \
   do {                                                                                        \
     hipExtLaunchKernelGGL(kernel, grid, block, smem, stream, g_ev_start, g_ev_stop, 0,        \

@@ -1,0 +1,670 @@
+// homg_learned.hip -- gfx950 kernels of the learned lattice smoother.
+//
+// The relaxation of the HOMG fused task (Sec. 2 of arXiv:1108.2045: lattice
+// nodes relax, every other node interpolates) is damped Jacobi in the paper.
+// Here it can be replaced, on the 2D variable-coefficient diffusion
+// problem, by a small bias-free network evaluated on the compact level-m
+// lattice (spacing h_l = 2^m h, so on the whole grid its 3x3 taps are
+// dilated by 2^m):
+//   features at an interior lattice node p (0 on the boundary):
+//     rho = (h_l^2 r_m(p) - sum_q a_pq (x_p - x_q)) / sum_q a_pq
+//     X = (rho, rho (a_E - a_W)/(a_E + a_W), rho (a_N - a_S)/(a_N + a_S))
+//     with a_pq the harmonic mean of the nodal coefficients (W, E, S, N);
+//   P_c = sum_ci sum_k W1[c][ci][k] X_ci(p + o_k),  H_c = max(P_c, 0)
+//   (16 channels, interior nodes; 0 on the boundary),
+//   y = sum_c sum_k W2[c][k] H_c(p + o_k),  x' = x + y,
+// o_k = (dy, dx) with k = 3 (dy + 1) + (dx + 1), read as a correlation.
+// Weights are stored in BF16 and used as their exact FP32 values; all
+// network arithmetic is FP32 (features in the cycle's precision, then
+// FP32).  Damped Jacobi is the special case y = omega rho.
+//
+// The work is a dense 576-MAC contraction per node over LDS-resident tiles:
+// a workgroup owns a 14 x 14 block of lattice nodes and stages x and a on
+// its 20 x 20 halo region, the features on 18 x 18 and the hidden layer on
+// 16 x 16 (one node per lane, all 16 channels in registers, weights from
+// scalar loads).
+//
+// Training kernels (FP32, dense compact arrays): forward writes z = delta -
+// y; backward recomputes the tile's features and hidden layer, forms
+// g = dL/dy = -2 A_m z / E(delta) and accumulates the 576 weight gradients
+// and the energy E(z) in registers over the tiles a workgroup visits, then
+// writes one row of per-workgroup partial sums; a fixed-order reduction and
+// an Adam step (FP32 master weights -> BF16) follow.  Every sum has a fixed
+// order, so training is deterministic.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "homg_internal.h"
+
+namespace homg {
+
+namespace {
+
+struct bf16s {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ double ldv(const double* p) { return *p; }
+__device__ __forceinline__ float ldv(const float* p) { return *p; }
+__device__ __forceinline__ float ldv(const bf16s* p) { return __uint_as_float(uint32_t(p->bits) << 16); }
+__device__ __forceinline__ uint16_t to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ void stv(double* p, double v) { *p = v; }
+__device__ __forceinline__ void stv(float* p, float v) { *p = v; }
+__device__ __forceinline__ void stv(bf16s* p, float v) { p->bits = to_bf16_bits(v); }
+
+template <typename T> struct Acc { using C = float; };
+template <> struct Acc<double> { using C = double; };
+
+constexpr int TO = 14;          // owned tile side
+constexpr int R3 = TO + 6;      // x, a staged region (halo 3)
+constexpr int R2 = TO + 4;      // features (halo 2)
+constexpr int R1 = TO + 2;      // hidden layer (halo 1): 16 x 16 = one node per lane
+constexpr int NT = R1 * R1;     // 256 lanes
+constexpr int HP = HID + 4;     // padded hidden stride in floats (16-byte aligned)
+constexpr int NOWN = TO * TO;   // 196
+
+template <typename C>
+__device__ __forceinline__ C hmean(C a, C b) { return C(2) * a * b / (a + b); }
+
+// Shared memory of one tile.  Features as float4 (channel 3 unused).
+template <typename C>
+struct TileLds {
+  C x[R3 * R3];
+  C a[R3 * R3];
+  float4 f[R2 * R2];
+  float h[NT * HP];
+};
+
+// Stage x and a on the halo-3 region of the tile whose owned block starts
+// at (J0, I0), then the features on the halo-2 region.  Nodes outside the
+// lattice read x = 0, a = 1; features are 0 off the interior.  XT/RT/AT:
+// storage of x, r_m, a (AT = void: constant coefficient).
+template <typename C, typename XT, typename RT, typename AT>
+__device__ __forceinline__ void stage_features(TileLds<C>& L, const XT* __restrict__ x, int64_t xp,
+                                               const RT* __restrict__ r, int64_t rp,
+                                               const AT* __restrict__ a, int64_t ap, int nm,
+                                               int J0, int I0, C hl2) {
+  const int t = threadIdx.x;
+  for (int q = t; q < R3 * R3; q += NT) {
+    const int J = J0 - 3 + q / R3, I = I0 - 3 + q % R3;
+    const bool in = J >= 0 && J < nm && I >= 0 && I < nm;
+    L.x[q] = in ? C(ldv(x + int64_t(J) * xp + I)) : C(0);
+    if constexpr (!std::is_void<AT>::value) L.a[q] = in ? C(ldv(a + int64_t(J) * ap + I)) : C(1);
+  }
+  __syncthreads();
+  for (int q = t; q < R2 * R2; q += NT) {
+    const int jj = q / R2, ii = q % R2;
+    const int J = J0 - 2 + jj, I = I0 - 2 + ii;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) {
+      const int c3 = (jj + 1) * R3 + (ii + 1);
+      const C xc = L.x[c3];
+      const C xw = L.x[c3 - 1], xe = L.x[c3 + 1], xs = L.x[c3 - R3], xn = L.x[c3 + R3];
+      const C rv = C(ldv(r + int64_t(J) * rp + I));
+      if constexpr (std::is_void<AT>::value) {
+        const C flux = (((xc - xw) + (xc - xe)) + (xc - xs)) + (xc - xn);
+        v.x = float((hl2 * rv - flux) / C(4));
+      } else {
+        const C ac = L.a[c3];
+        const C aw = hmean(ac, L.a[c3 - 1]), ae = hmean(ac, L.a[c3 + 1]);
+        const C as = hmean(ac, L.a[c3 - R3]), an = hmean(ac, L.a[c3 + R3]);
+        const C sa = ((aw + ae) + as) + an;
+        const C flux = ((aw * (xc - xw) + ae * (xc - xe)) + as * (xc - xs)) + an * (xc - xn);
+        const C rho = (hl2 * rv - flux) / sa;
+        v.x = float(rho);
+        v.y = float(rho * (ae - aw) / (ae + aw));
+        v.z = float(rho * (an - as) / (an + as));
+      }
+    }
+    L.f[q] = v;
+  }
+  __syncthreads();
+}
+
+// Hidden layer at the lane's node of the halo-1 region (one node per lane):
+// pre-activations P[16] in registers, H = max(P, 0) stored in LDS (0 off the
+// interior).  Returns whether the node is interior.
+template <typename C>
+__device__ __forceinline__ bool stage_hidden(TileLds<C>& L, const float* __restrict__ w, int nm,
+                                             int J0, int I0, float P[HID]) {
+  const int t = threadIdx.x;
+  const int jj = t / R1, ii = t % R1;
+  const int J = J0 - 1 + jj, I = I0 - 1 + ii;
+  const bool in = J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2;
+#pragma unroll
+  for (int c = 0; c < HID; ++c) P[c] = 0.f;
+  if (in) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int dy = k / 3 - 1, dx = k % 3 - 1;
+      const float4 fv = L.f[(jj + 1 + dy) * R2 + (ii + 1 + dx)];
+#pragma unroll
+      for (int c = 0; c < HID; ++c) {
+        float p = P[c];
+        p = __builtin_fmaf(w[c * 27 + 0 * 9 + k], fv.x, p);
+        p = __builtin_fmaf(w[c * 27 + 1 * 9 + k], fv.y, p);
+        p = __builtin_fmaf(w[c * 27 + 2 * 9 + k], fv.z, p);
+        P[c] = p;
+      }
+    }
+  }
+  float* hrow = L.h + t * HP;
+#pragma unroll
+  for (int c = 0; c < HID; c += 4)
+    *reinterpret_cast<float4*>(hrow + c) =
+        make_float4(fmaxf(P[c], 0.f), fmaxf(P[c + 1], 0.f), fmaxf(P[c + 2], 0.f), fmaxf(P[c + 3], 0.f));
+  __syncthreads();
+  return in;
+}
+
+// Output at owned node o (0 <= o < 196): y = sum_c sum_k W2[c][k] H_c(p + o_k).
+template <typename C>
+__device__ __forceinline__ float tile_output(const TileLds<C>& L, const float* __restrict__ w, int o) {
+  const int oj = o / TO, oi = o % TO;
+  float y = 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int dy = k / 3 - 1, dx = k % 3 - 1;
+    const float* hv = L.h + ((oj + 1 + dy) * R1 + (oi + 1 + dx)) * HP;
+#pragma unroll
+    for (int c = 0; c < HID; c += 4) {
+      const float4 h4 = *reinterpret_cast<const float4*>(hv + c);
+      y = __builtin_fmaf(w[NW1 + (c + 0) * 9 + k], h4.x, y);
+      y = __builtin_fmaf(w[NW1 + (c + 1) * 9 + k], h4.y, y);
+      y = __builtin_fmaf(w[NW1 + (c + 2) * 9 + k], h4.z, y);
+      y = __builtin_fmaf(w[NW1 + (c + 3) * 9 + k], h4.w, y);
+    }
+  }
+  return y;
+}
+
+// ---------------------------------------------------------------- inference
+// One learned relaxation of every interior node of a compact level lattice:
+// xo = xi + y (or u += xi + y with ACCUM, the last iteration of a cycle).
+// ZERO: xi = 0 (the first iteration of a cycle; nothing is read from xi).
+template <typename T, bool ZERO, bool ACCUM, bool VAR>
+__global__ __launch_bounds__(NT) void k_learned_iter(
+    const T* __restrict__ xi, int64_t xp, T* __restrict__ xo, const T* __restrict__ r, int64_t rp,
+    const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up, int nm,
+    typename Acc<T>::C hl2, const float* __restrict__ w, const int* __restrict__ done) {
+  using C = typename Acc<T>::C;
+  if (*done) return;
+  __shared__ TileLds<C> L;
+  const int J0 = 1 + blockIdx.y * TO, I0 = 1 + blockIdx.x * TO;
+  if constexpr (ZERO) {  // x = 0: stage zeros, features from r (and a) only
+    for (int q = threadIdx.x; q < R3 * R3; q += NT) {
+      const int J = J0 - 3 + q / R3, I = I0 - 3 + q % R3;
+      const bool in = J >= 0 && J < nm && I >= 0 && I < nm;
+      L.x[q] = C(0);
+      if constexpr (VAR) L.a[q] = in ? C(a[int64_t(J) * ap + I]) : C(1);
+    }
+    __syncthreads();
+    // features with x = 0
+    for (int q = threadIdx.x; q < R2 * R2; q += NT) {
+      const int jj = q / R2, ii = q % R2;
+      const int J = J0 - 2 + jj, I = I0 - 2 + ii;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) {
+        const C rv = C(ldv(r + int64_t(J) * rp + I));
+        if constexpr (!VAR) {
+          v.x = float((hl2 * rv - C(0)) / C(4));
+        } else {
+          const int c3 = (jj + 1) * R3 + (ii + 1);
+          const C ac = L.a[c3];
+          const C aw = hmean(ac, L.a[c3 - 1]), ae = hmean(ac, L.a[c3 + 1]);
+          const C as = hmean(ac, L.a[c3 - R3]), an = hmean(ac, L.a[c3 + R3]);
+          const C sa = ((aw + ae) + as) + an;
+          const C rho = (hl2 * rv - C(0)) / sa;
+          v.x = float(rho);
+          v.y = float(rho * (ae - aw) / (ae + aw));
+          v.z = float(rho * (an - as) / (an + as));
+        }
+      }
+      L.f[q] = v;
+    }
+    __syncthreads();
+  } else {
+    if constexpr (VAR)
+      stage_features<C, T, T, double>(L, xi, xp, r, rp, a, ap, nm, J0, I0, hl2);
+    else
+      stage_features<C, T, T, void>(L, xi, xp, r, rp, nullptr, 0, nm, J0, I0, hl2);
+  }
+  float P[HID];
+  (void)stage_hidden<C>(L, w, nm, J0, I0, P);
+  const int o = threadIdx.x;
+  if (o < NOWN) {
+    const int J = J0 + o / TO, I = I0 + o % TO;
+    if (J <= nm - 2 && I <= nm - 2) {
+      const float y = tile_output<C>(L, w, o);
+      const C xc = L.x[(o / TO + 3) * R3 + (o % TO + 3)];
+      const C v = xc + C(y);
+      if constexpr (ACCUM) {
+        u[int64_t(J) * up + I] += double(v);
+      } else {
+        stv(xo + int64_t(J) * xp + I, v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- training
+// Dense FP32 compact arrays of side nm (node (J, I) at J nm + I).
+
+// z = delta - y at interior nodes (y alone when delta is null).
+template <bool VAR>
+__global__ __launch_bounds__(NT) void k_train_fwd(const float* __restrict__ x,
+                                                  const float* __restrict__ r,
+                                                  const float* __restrict__ a,
+                                                  const float* __restrict__ delta,
+                                                  float* __restrict__ z, int nm, float hl2,
+                                                  const float* __restrict__ w) {
+  __shared__ TileLds<float> L;
+  const int J0 = 1 + blockIdx.y * TO, I0 = 1 + blockIdx.x * TO;
+  if constexpr (VAR)
+    stage_features<float, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
+  else
+    stage_features<float, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
+  float P[HID];
+  (void)stage_hidden<float>(L, w, nm, J0, I0, P);
+  const int o = threadIdx.x;
+  if (o < NOWN) {
+    const int J = J0 + o / TO, I = I0 + o % TO;
+    if (J <= nm - 2 && I <= nm - 2) {
+      const float y = tile_output<float>(L, w, o);
+      const int64_t p = int64_t(J) * nm + I;
+      z[p] = delta ? delta[p] - y : y;
+    }
+  }
+}
+
+// Gradient partial sums of one sample.  Workgroup b visits tiles b, b + G,
+// ...; lane t accumulates elements t, t + 256, t + 512 of the 577-vector
+// (576 weight gradients of L = E(z)/E(delta), then E(z)); the row of
+// workgroup b goes to part[j * pstride + b].
+template <bool VAR>
+__global__ __launch_bounds__(NT) void k_train_bwd(const float* __restrict__ x,
+                                                  const float* __restrict__ r,
+                                                  const float* __restrict__ a,
+                                                  const float* __restrict__ z, int nm, float hl2,
+                                                  const double* __restrict__ e0,
+                                                  const float* __restrict__ w,
+                                                  float* __restrict__ part, int64_t pstride) {
+  __shared__ TileLds<float> L;
+  __shared__ float gs[NT];              // g on the halo-1 region
+  __shared__ float zs[R2 * R2];         // z on the halo-2 region
+  __shared__ float dp[NOWN * HP];       // dP on owned nodes
+  __shared__ float ez[NOWN];            // z (A z) on owned nodes
+  const int t = threadIdx.x;
+  const int tiles_x = (nm - 2 + TO - 1) / TO;
+  const int tiles = tiles_x * tiles_x;
+  const float gscale = float(-2.0 / *e0);
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int J0 = 1 + (tile / tiles_x) * TO, I0 = 1 + (tile % tiles_x) * TO;
+    if constexpr (VAR)
+      stage_features<float, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
+    else
+      stage_features<float, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
+    float P[HID];
+    (void)stage_hidden<float>(L, w, nm, J0, I0, P);
+    for (int q = t; q < R2 * R2; q += NT) {
+      const int J = J0 - 2 + q / R2, I = I0 - 2 + q % R2;
+      zs[q] = (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) ? z[int64_t(J) * nm + I] : 0.f;
+    }
+    __syncthreads();
+    {  // g = -2 (A z) / E(delta) on the halo-1 region, z (A z) on owned nodes
+      const int jj = t / R1, ii = t % R1;
+      const int J = J0 - 1 + jj, I = I0 - 1 + ii;
+      float g = 0.f;
+      if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) {
+        const int c2 = (jj + 1) * R2 + (ii + 1);
+        const float zc = zs[c2];
+        float az;
+        if constexpr (VAR) {
+          const int c3 = (jj + 2) * R3 + (ii + 2);
+          const float ac = L.a[c3];
+          const float aw = hmean(ac, L.a[c3 - 1]), ae = hmean(ac, L.a[c3 + 1]);
+          const float as = hmean(ac, L.a[c3 - R3]), an = hmean(ac, L.a[c3 + R3]);
+          az = ((aw * (zc - zs[c2 - 1]) + ae * (zc - zs[c2 + 1])) + as * (zc - zs[c2 - R2])) +
+               an * (zc - zs[c2 + R2]);
+        } else {
+          az = (((zc - zs[c2 - 1]) + (zc - zs[c2 + 1])) + (zc - zs[c2 - R2])) + (zc - zs[c2 + R2]);
+        }
+        g = gscale * az;
+        if (jj >= 1 && jj <= TO && ii >= 1 && ii <= TO) ez[(jj - 1) * TO + (ii - 1)] = zc * az;
+      } else if (jj >= 1 && jj <= TO && ii >= 1 && ii <= TO) {
+        ez[(jj - 1) * TO + (ii - 1)] = 0.f;
+      }
+      gs[t] = g;
+    }
+    __syncthreads();
+    if (t < NOWN) {  // dP_c(q) = [P_c(q) > 0] sum_k W2[c][k] g(q - o_k) at owned q
+      const int oj = t / TO, oi = t % TO;
+      const int J = J0 + oj, I = I0 + oi;
+      const bool in = J <= nm - 2 && I <= nm - 2;
+      float gk[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int dy = k / 3 - 1, dx = k % 3 - 1;
+        gk[k] = in ? gs[(oj + 1 - dy) * R1 + (oi + 1 - dx)] : 0.f;
+      }
+      const float* hq = L.h + ((oj + 1) * R1 + (oi + 1)) * HP;
+#pragma unroll
+      for (int c = 0; c < HID; ++c) {
+        float dh = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) dh = __builtin_fmaf(w[NW1 + c * 9 + k], gk[k], dh);
+        dp[t * HP + c] = hq[c] > 0.f ? dh : 0.f;
+      }
+    }
+    __syncthreads();
+    // weight gradients over the owned nodes (outside ones carry dP = g = 0)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int j = t + s * NT;
+      if (j < NW1) {
+        const int c = j / 27, ci = (j % 27) / 9, k = j % 9;
+        const int dy = k / 3 - 1, dx = k % 3 - 1;
+        float sum = 0.f;
+        for (int o = 0; o < NOWN; ++o) {
+          const int oj = o / TO, oi = o % TO;
+          const float4 fv = L.f[(oj + 2 + dy) * R2 + (oi + 2 + dx)];
+          const float xv = ci == 0 ? fv.x : (ci == 1 ? fv.y : fv.z);
+          sum = __builtin_fmaf(dp[o * HP + c], xv, sum);
+        }
+        acc[s] += sum;
+      } else if (j < NW) {
+        const int c = (j - NW1) / 9, k = (j - NW1) % 9;
+        const int dy = k / 3 - 1, dx = k % 3 - 1;
+        float sum = 0.f;
+        for (int o = 0; o < NOWN; ++o) {
+          const int oj = o / TO, oi = o % TO;
+          const float gv = gs[(oj + 1) * R1 + (oi + 1)];
+          sum = __builtin_fmaf(gv, L.h[((oj + 1 + dy) * R1 + (oi + 1 + dx)) * HP + c], sum);
+        }
+        acc[s] += sum;
+      } else if (j == NW) {
+        float sum = 0.f;
+        for (int o = 0; o < NOWN; ++o) sum += ez[o];
+        acc[s] += sum;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int j = t + s * NT;
+    if (j <= NW) part[int64_t(j) * pstride + blockIdx.x] = acc[s];
+  }
+}
+
+// Sum of each partial row in a fixed order: out[j] = sum_b part[j][b],
+// FP64 accumulation (one workgroup per element j).
+__global__ __launch_bounds__(256) void k_train_reduce(const float* __restrict__ part,
+                                                      int64_t pstride, int rows,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < rows; b += 256) s += double(part[int64_t(j) * pstride + b]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// Mean gradient over the batch (the `batch` rows of sums, stride NW + 1,
+// added in order), Adam on the FP32 masters, the BF16 copy (wbf, nullable)
+// and its FP32 expansion w32 for the kernels.  With loss != null,
+// loss[step - 1] = mean over the batch of E(z) / E(delta), E(delta) of row b
+// at e0s[idx[b]].
+__global__ __launch_bounds__(640) void k_train_adam(const double* __restrict__ sums, int batch,
+                                                    const double* __restrict__ e0s,
+                                                    const int* __restrict__ idx,
+                                                    float* __restrict__ theta,
+                                                    float* __restrict__ m1, float* __restrict__ m2,
+                                                    uint16_t* __restrict__ wbf,
+                                                    float* __restrict__ w32, int step, float lr,
+                                                    float beta1, float beta2, float eps,
+                                                    double* __restrict__ loss) {
+  const int j = threadIdx.x;
+  if (j < NW) {
+    double g = 0.0;
+    for (int b = 0; b < batch; ++b) g += sums[b * (NW + 1) + j];
+    const float gf = float(g / batch);
+    const float mm = beta1 * m1[j] + (1.f - beta1) * gf;
+    const float vv = beta2 * m2[j] + (1.f - beta2) * gf * gf;
+    m1[j] = mm;
+    m2[j] = vv;
+    const float mhat = mm / (1.f - powf(beta1, float(step)));
+    const float vhat = vv / (1.f - powf(beta2, float(step)));
+    const float th = theta[j] - lr * mhat / (sqrtf(vhat) + eps);
+    theta[j] = th;
+    const uint16_t b16 = to_bf16_bits(th);
+    if (wbf) wbf[j] = b16;
+    w32[j] = __uint_as_float(uint32_t(b16) << 16);
+  } else if (j == NW && loss) {
+    double l = 0.0;
+    for (int b = 0; b < batch; ++b) l += sums[b * (NW + 1) + NW] / e0s[idx[b]];
+    loss[step - 1] = l / batch;
+  }
+}
+
+// E(v) = sum_p v_p (A v)_p over interior nodes: per-workgroup partials.
+template <bool VAR>
+__global__ __launch_bounds__(256) void k_energy_part(const float* __restrict__ v,
+                                                     const float* __restrict__ a, int nm,
+                                                     double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const int64_t inner = int64_t(nm - 2) * (nm - 2);
+  for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < inner; q += int64_t(gridDim.x) * 256) {
+    const int J = 1 + int(q / (nm - 2)), I = 1 + int(q % (nm - 2));
+    const int64_t p = int64_t(J) * nm + I;
+    auto val = [&](int JJ, int II) {
+      return (JJ >= 1 && JJ <= nm - 2 && II >= 1 && II <= nm - 2) ? double(v[int64_t(JJ) * nm + II]) : 0.0;
+    };
+    const double c = v[p];
+    double av;
+    if constexpr (VAR) {
+      const double ac = a[p];
+      av = hmean(ac, double(a[p - 1])) * (c - val(J, I - 1)) + hmean(ac, double(a[p + 1])) * (c - val(J, I + 1)) +
+           hmean(ac, double(a[p - nm])) * (c - val(J - 1, I)) + hmean(ac, double(a[p + nm])) * (c - val(J + 1, I));
+    } else {
+      av = (c - val(J, I - 1)) + (c - val(J, I + 1)) + (c - val(J - 1, I)) + (c - val(J + 1, I));
+    }
+    s += c * av;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_small(const double* __restrict__ part, int count, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < count; ++i) s += part[i];
+    *out = s;
+  }
+}
+
+// FP32 values -> BF16 (RNE) and their FP32 expansion.
+__global__ void k_round_weights(const float* __restrict__ src, uint16_t* __restrict__ wbf,
+                                float* __restrict__ w32, int count) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < count) {
+    const uint16_t b = to_bf16_bits(src[j]);
+    wbf[j] = b;
+    w32[j] = __uint_as_float(uint32_t(b) << 16);
+  }
+}
+
+// Training-sample extraction from a dense FP64 whole grid: the level-l
+// lattice, rounded to FP32 (dst side nm, dense).  With sub != null,
+// dst = sub[l-lattice] - src[l-lattice] (the error of an iterate).
+__global__ void k_lattice_f32(const double* __restrict__ src, int64_t sp, int l,
+                              const double* __restrict__ sub, int64_t bp, int nm,
+                              float* __restrict__ dst) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x, J = blockIdx.y;
+  if (I >= nm) return;
+  const double v = src[int64_t(J) * l * sp + int64_t(I) * l];
+  dst[int64_t(J) * nm + I] = sub ? float(sub[int64_t(J) * bp + I] - v) : float(v);
+}
+
+// v += e over `count` contiguous FP64 values.
+__global__ void k_add_dense(double* __restrict__ v, const double* __restrict__ e, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) v[i] += e[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+#define LL_LAUNCH(kernel, grid, block, stream, ...)                                          \
+  do {                                                                                      \
+    hipEvent_t ev0_, ev1_;                                                                  \
+    current_launch_events(&ev0_, &ev1_);                                                    \
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, ev0_, ev1_, 0, __VA_ARGS__);     \
+    return hipGetLastError();                                                               \
+  } while (0)
+
+static dim3 tile_grid(int nm) {
+  const int t = (nm - 2 + TO - 1) / TO;
+  return dim3(t, t);
+}
+
+template <typename T, bool ZERO, bool ACCUM>
+static hipError_t learned_t(int nm, double hl, const void* xi, const Lay& xl, void* xo,
+                            const void* r, const Lay& rl, const double* a, const Lay& al,
+                            double* u, const Lay& ul, const float* w, const int* done,
+                            hipStream_t s) {
+  using C = typename Acc<T>::C;
+  using S = T;
+  const S* x = xi ? static_cast<const S*>(xi) + xl.off : nullptr;
+  S* y = xo ? static_cast<S*>(xo) + xl.off : nullptr;
+  const S* rr = static_cast<const S*>(r) + rl.off;
+  const double* aa = a ? a + al.off : nullptr;
+  double* uu = u ? u + ul.off : nullptr;
+  const C hl2 = C(hl * hl);
+  if (a)
+    LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, true>), tile_grid(nm), dim3(NT), s, x, xl.pitch, y,
+              rr, rl.pitch, aa, al.pitch, uu, ul.pitch, nm, hl2, w, done);
+  LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, false>), tile_grid(nm), dim3(NT), s, x, xl.pitch, y, rr,
+            rl.pitch, aa, al.pitch, uu, ul.pitch, nm, hl2, w, done);
+}
+
+template <typename T>
+static hipError_t learned_tm(int nm, double hl, const void* xi, const Lay& xl, void* xo,
+                             const void* r, const Lay& rl, const double* a, const Lay& al,
+                             double* u, const Lay& ul, const float* w, int mode,
+                             const int* done, hipStream_t s) {
+  switch (mode & 3) {
+    case 0: return learned_t<T, false, false>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, done, s);
+    case 1: return learned_t<T, true, false>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, done, s);
+    case 2: return learned_t<T, false, true>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, done, s);
+    default: return learned_t<T, true, true>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, done, s);
+  }
+}
+
+hipError_t launch_learned_iter(int prec, int nm, double hl, const void* xi, const Lay& xl,
+                               void* xo, const void* r, const Lay& rl, const double* a,
+                               const Lay& al, double* u, const Lay& ul, const float* w, int mode,
+                               const int* done, hipStream_t s) {
+  if (nm < 3) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return learned_tm<double>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, mode, done, s);
+    case PREC_F32: return learned_tm<float>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, mode, done, s);
+    default: return learned_tm<bf16s>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, mode, done, s);
+  }
+}
+
+hipError_t launch_train_fwd(int nm, float hl2, const float* x, const float* r, const float* a,
+                            const float* delta, float* z, const float* w, hipStream_t s) {
+  if (nm < 3) return hipErrorInvalidValue;
+  if (a) LL_LAUNCH(k_train_fwd<true>, tile_grid(nm), dim3(NT), s, x, r, a, delta, z, nm, hl2, w);
+  LL_LAUNCH(k_train_fwd<false>, tile_grid(nm), dim3(NT), s, x, r, a, delta, z, nm, hl2, w);
+}
+
+int train_bwd_rows(int nm) {
+  const int t = (nm - 2 + TO - 1) / TO;
+  const int tiles = t * t;
+  return tiles < TRAIN_MAX_ROWS ? tiles : TRAIN_MAX_ROWS;
+}
+
+hipError_t launch_train_bwd(int nm, float hl2, const float* x, const float* r, const float* a,
+                            const float* z, const double* e0, const float* w, float* part,
+                            int64_t pstride, hipStream_t s) {
+  if (nm < 3) return hipErrorInvalidValue;
+  const dim3 g(train_bwd_rows(nm));
+  if (a) LL_LAUNCH(k_train_bwd<true>, g, dim3(NT), s, x, r, a, z, nm, hl2, e0, w, part, pstride);
+  LL_LAUNCH(k_train_bwd<false>, g, dim3(NT), s, x, r, a, z, nm, hl2, e0, w, part, pstride);
+}
+
+hipError_t launch_train_reduce(const float* part, int64_t pstride, int rows, double* out,
+                               hipStream_t s) {
+  LL_LAUNCH(k_train_reduce, dim3(NW + 1), dim3(256), s, part, pstride, rows, out);
+}
+
+hipError_t launch_train_adam(const double* sums, int batch, const double* e0s, const int* idx,
+                             float* theta, float* m1, float* m2, uint16_t* wbf, float* w32,
+                             int step, float lr, float beta1, float beta2, float eps, double* loss,
+                             hipStream_t s) {
+  LL_LAUNCH(k_train_adam, dim3(1), dim3(640), s, sums, batch, e0s, idx, theta, m1, m2, wbf, w32,
+            step, lr, beta1, beta2, eps, loss);
+}
+
+hipError_t launch_energy(const float* v, const float* a, int nm, double* part, double* out,
+                         hipStream_t s) {
+  if (nm < 3) return hipErrorInvalidValue;
+  const int64_t inner = int64_t(nm - 2) * (nm - 2);
+  int blocks = int((inner + 255) / 256);
+  if (blocks > ENERGY_MAX_PARTS) blocks = ENERGY_MAX_PARTS;
+  hipError_t e;
+  {
+    hipEvent_t ev0, ev1;
+    current_launch_events(&ev0, &ev1);
+    if (a)
+      hipExtLaunchKernelGGL(k_energy_part<true>, dim3(blocks), dim3(256), 0, s, ev0, ev1, 0, v, a, nm, part);
+    else
+      hipExtLaunchKernelGGL(k_energy_part<false>, dim3(blocks), dim3(256), 0, s, ev0, ev1, 0, v, a, nm, part);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sum_small, dim3(1), dim3(64), 0, s, part, blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_round_weights(const float* src, uint16_t* wbf, float* w32, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_weights, dim3((NW + 255) / 256), dim3(256), 0, s, src, wbf, w32, NW);
+  return hipGetLastError();
+}
+
+hipError_t launch_lattice_f32(const double* src, int64_t sp, int l, const double* sub, int64_t bp,
+                              int nm, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_lattice_f32, dim3((nm + 255) / 256, nm), dim3(256), 0, s, src, sp, l, sub,
+                     bp, nm, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_dense(double* v, const double* e, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_dense, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, v, e, count);
+  return hipGetLastError();
+}
+
+}  // namespace homg

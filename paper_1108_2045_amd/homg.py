@@ -39,7 +39,17 @@ class Info(ctypes.Structure):
                 ("relres0", ctypes.c_double), ("final_relres", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
                 ("sweeps", ctypes.c_longlong), ("launches", ctypes.c_longlong),
-                ("host_syncs", ctypes.c_int)]
+                ("host_syncs", ctypes.c_int), ("smoother_fell_back", ctypes.c_int)]
+
+
+class TrainOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("steps", ctypes.c_int), ("batch", ctypes.c_int),
+                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int * 8)]
+
+
+SMOOTHER_WEIGHTS = 576
+JACOBI, LEARNED = 0, 1
 
 
 class KernelTime(ctypes.Structure):
@@ -48,7 +58,7 @@ class KernelTime(ctypes.Structure):
 
 
 KIND_NAMES = {0: "norm", 1: "residual", 2: "finalize", 3: "restrict", 4: "sweep",
-              5: "gather", 6: "lattice", 7: "level_write"}
+              5: "gather", 6: "lattice", 7: "level_write", 8: "learned"}
 
 
 def load_library(path=LIB_PATH):
@@ -81,6 +91,24 @@ def load_library(path=LIB_PATH):
     L.homg_batch_set_tile_rows.argtypes = [H, ctypes.c_int64, ctypes.c_int]
     L.homg_batch_tune.argtypes = [H, PP, PP, ctypes.c_double, vp, ctypes.c_char_p]
     L.homg_batch_destroy.argtypes = [H]
+    L.homg_set_smoother.argtypes = [H, ctypes.c_int, vp, ctypes.c_double, vp]
+    L.homg_get_smoother_weights.argtypes = [H, vp, vp]
+    L.homg_smoother_gate.argtypes = [H, ctypes.c_int, PP, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ip]
+    L.homg_train_options_init.argtypes = [ctypes.POINTER(TrainOptions)]
+    L.homg_train_options_init.restype = None
+    L.homg_trainer_create.argtypes = [ctypes.POINTER(H)]
+    L.homg_trainer_add_problem.argtypes = [H, H, dp, ctypes.c_int, vp]
+    L.homg_trainer_count.argtypes = [H, ip]
+    L.homg_trainer_train.argtypes = [H, vp, ctypes.POINTER(TrainOptions), vp,
+                                     ctypes.POINTER(ctypes.c_double), vp]
+    L.homg_trainer_loss.argtypes = [H, vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.homg_trainer_destroy.argtypes = [H]
+    L.homg_learn_forward.argtypes = [ctypes.c_int, ctypes.c_double, vp, vp, vp, vp, vp, vp]
+    L.homg_learn_grad.argtypes = [ctypes.c_int, ctypes.c_double, vp, vp, vp, vp, vp, vp,
+                                  ctypes.POINTER(ctypes.c_double), vp]
+    L.homg_learn_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, vp, vp]
     L.homg_last_error.argtypes = [H]
     L.homg_last_error.restype = ctypes.c_char_p
     L.homg_version.argtypes = []
@@ -89,7 +117,10 @@ def load_library(path=LIB_PATH):
                  "homg_solve_cycles", "homg_residual", "homg_get_schedule", "homg_step_restrict",
                  "homg_step_sweeps", "homg_step_cycle", "homg_set_profiling", "homg_get_profile",
                  "homg_batch_create", "homg_batch_solve", "homg_batch_set_tile_rows", "homg_batch_tune",
-                 "homg_batch_destroy"):
+                 "homg_batch_destroy", "homg_set_smoother", "homg_get_smoother_weights",
+                 "homg_smoother_gate", "homg_trainer_create", "homg_trainer_add_problem",
+                 "homg_trainer_count", "homg_trainer_train", "homg_trainer_loss", "homg_trainer_destroy",
+                 "homg_learn_forward", "homg_learn_grad", "homg_learn_adam"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -112,8 +143,9 @@ def _ptr(t, dtype=None):
         raise ValueError("arrays must live on the GPU")
     if not t.is_contiguous():
         raise ValueError("arrays must be contiguous (C order, x fastest)")
-    if t.dtype != (dtype or torch.float64):
-        raise ValueError("arrays must be float64")
+    want = dtype or torch.float64
+    if t.dtype != want:
+        raise ValueError("arrays must be %s" % str(want).replace("torch.", ""))
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -182,7 +214,8 @@ class Solver:
     def _result(info, hist):
         return {"cycles": info.cycles, "converged": bool(info.converged), "relres0": info.relres0,
                 "final_relres": info.final_relres, "history": list(hist[:info.cycles + 1]),
-                "sweeps": info.sweeps, "launches": info.launches, "host_syncs": info.host_syncs}
+                "sweeps": info.sweeps, "launches": info.launches, "host_syncs": info.host_syncs,
+                "smoother_fell_back": bool(info.smoother_fell_back)}
 
     def solve(self, f, u, tol=1e-10, stream=None, raise_on_status=True):
         info, hist = self._info()
@@ -232,6 +265,125 @@ class Solver:
 
     def step_cycle(self, r0, acc, stream=None):
         self._check(lib().homg_step_cycle(self._h, _ptr(r0), _ptr(acc), _stream(stream)))
+
+    def set_smoother(self, smoother, w=None, fallback_ratio=0.0, stream=None):
+        """smoother: JACOBI or LEARNED; w: 576 float32 weights on the GPU (rounded to BF16)."""
+        import torch
+        wp = _ptr(_weights(w), torch.float32) if w is not None else None
+        self._check(lib().homg_set_smoother(self._h, int(smoother), wp, fallback_ratio, _stream(stream)))
+
+    def smoother_weights(self, stream=None):
+        """The FP32 values of the BF16 weights in use (a new GPU tensor)."""
+        import torch
+        out = torch.empty(SMOOTHER_WEIGHTS, dtype=torch.float32, device="cuda")
+        self._check(lib().homg_get_smoother_weights(self._h, _ptr(out, torch.float32), _stream(stream)))
+        return out
+
+    def smoother_gate(self, fs, cycles, stream=None):
+        n = len(fs)
+        arr = (ctypes.c_void_p * n)(*[_ptr(f).value for f in fs])
+        rl = (ctypes.c_double * n)()
+        rj = (ctypes.c_double * n)()
+        acc = ctypes.c_int()
+        self._check(lib().homg_smoother_gate(self._h, n, arr, cycles, _stream(stream), rl, rj, ctypes.byref(acc)))
+        return {"accepted": bool(acc.value), "rho_learned": list(rl), "rho_jacobi": list(rj)}
+
+
+def _weights(w):
+    if tuple(w.shape) != (SMOOTHER_WEIGHTS,):
+        raise ValueError("the smoother has %d weights" % SMOOTHER_WEIGHTS)
+    return w
+
+
+class Trainer:
+    """Training of the learned relaxation on pairs generated by plain HOMG."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        st = lib().homg_trainer_create(ctypes.byref(h))
+        if st != HOMG_OK:
+            raise HomgError(st, lib().homg_last_error(None).decode())
+        self._h = h
+
+    def _check(self, st):
+        if st != HOMG_OK:
+            raise HomgError(st, lib().homg_last_error(None).decode())
+
+    def add_problem(self, solver, f, cycles=1, stream=None):
+        self._check(lib().homg_trainer_add_problem(self._h, solver._h, _ptr(f), cycles, _stream(stream)))
+
+    def count(self):
+        n = ctypes.c_int()
+        self._check(lib().homg_trainer_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    def train(self, w0, steps=300, batch=8, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
+              stream=None):
+        """Returns (FP32 values of the trained BF16 weights, per-step batch losses)."""
+        import torch
+        opt = TrainOptions()
+        lib().homg_train_options_init(ctypes.byref(opt))
+        opt.steps, opt.batch, opt.lr, opt.beta1, opt.beta2, opt.eps, opt.seed = (
+            steps, batch, lr, beta1, beta2, eps, seed)
+        out = torch.empty(SMOOTHER_WEIGHTS, dtype=torch.float32, device="cuda")
+        hist = (ctypes.c_double * steps)()
+        self._check(lib().homg_trainer_train(self._h, _ptr(_weights(w0), torch.float32), ctypes.byref(opt),
+                                             _ptr(out, torch.float32), hist, _stream(stream)))
+        return out, list(hist)
+
+    def loss(self, w, stream=None):
+        import torch
+        v = ctypes.c_double()
+        self._check(lib().homg_trainer_loss(self._h, _ptr(_weights(w), torch.float32), ctypes.byref(v),
+                                            _stream(stream)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().homg_trainer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_global(st):
+    if st != HOMG_OK:
+        raise HomgError(st, lib().homg_last_error(None).decode())
+
+
+def learn_forward(x, r, a, w, hl, y, stream=None):
+    """Network output of the learned relaxation on one compact lattice
+    (dense float32 GPU arrays of side nm; a may be None)."""
+    import torch
+    f32 = torch.float32
+    nm = x.shape[0]
+    _check_global(lib().homg_learn_forward(nm, hl, _ptr(x, f32), _ptr(r, f32),
+                                           _ptr(a, f32) if a is not None else None,
+                                           _ptr(_weights(w), f32), _ptr(y, f32), _stream(stream)))
+
+
+def learn_grad(x, r, a, delta, w, hl, stream=None):
+    """(dL/dw as a float64 GPU tensor of 576, E(delta - y), L) for one sample."""
+    import torch
+    f32 = torch.float32
+    nm = x.shape[0]
+    g = torch.empty(SMOOTHER_WEIGHTS + 1, dtype=torch.float64, device="cuda")
+    loss = ctypes.c_double()
+    _check_global(lib().homg_learn_grad(nm, hl, _ptr(x, f32), _ptr(r, f32),
+                                        _ptr(a, f32) if a is not None else None, _ptr(delta, f32),
+                                        _ptr(_weights(w), f32), _ptr(g), ctypes.byref(loss), _stream(stream)))
+    return g[:SMOOTHER_WEIGHTS], float(g[SMOOTHER_WEIGHTS]), loss.value
+
+
+def learn_adam(theta, m1, m2, grad, t, lr, w_out, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+    f32 = torch.float32
+    _check_global(lib().homg_learn_adam(_ptr(theta, f32), _ptr(m1, f32), _ptr(m2, f32), _ptr(grad), t, lr,
+                                        beta1, beta2, eps, _ptr(w_out, f32), _stream(stream)))
 
 
 class BatchSolver:

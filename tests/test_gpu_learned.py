@@ -1,0 +1,315 @@
+"""GPU parity of the learned lattice relaxation, its training kernels and
+its place in the solver, against the FP64 oracle (oracle/learned.py).
+
+Tolerances, from the arithmetic:
+  * the network runs in FP32 (BF16 weights are exact in FP32): a value
+    computed as a sum of T products differs from the FP64 one by at most
+    about T * 2^-24 times the sum of the magnitudes of its terms; the tests
+    bound each output by 1e-5 times that magnitude sum (T <= 27 + 144);
+  * gradients are FP32 sums over up to 196 nodes per tile and tiles per
+    workgroup, then FP64 across workgroups: within 2e-4 of max |gradient|;
+  * in the solver the features are formed in the cycle precision (FP64) and
+    rounded to FP32 before the network: a step agrees with the oracle to
+    1e-5 times max |e|; whole solves meet the FP64 tolerance and lie within
+    the rigorous bound (||r_gpu|| + ||r_oracle||) / lambda_min of the
+    oracle's solution, lambda_min >= min(a) lambda_min(Laplacian).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import homg as O
+from oracle import learned as LO
+from oracle import textbook as T
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def B(torch_cuda):
+    import paper_1108_2045_amd as P
+    return P
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def dev32(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to("cuda")
+
+
+def dev64(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda")
+
+
+def rand_weights(rng, scale=0.3):
+    return LO.to_bf16(rng.standard_normal(LO.NW) * scale)
+
+
+def rand_sample(rng, nm, var, seed):
+    x = np.zeros((nm, nm))
+    x[1:-1, 1:-1] = rng.standard_normal((nm - 2, nm - 2))
+    r = np.zeros((nm, nm))
+    r[1:-1, 1:-1] = rng.standard_normal((nm - 2, nm - 2)) * (nm - 1) ** 2
+    a = W.grf_problem(nm, seed=seed)[0] if var else None
+    return f32(x), f32(r), (f32(a) if var else None)
+
+
+def magnitude_bound(X, w):
+    """Sum of |terms| of the network output at every node (FP64)."""
+    W1, W2 = LO.split(w)
+    Xa = np.abs(X)
+    Ha = LO.forward(Xa, LO.join(np.abs(W1), np.zeros_like(W2)))[1]
+    nm = X.shape[-1]
+    yb = np.zeros((nm, nm))
+    for c in range(LO.HID):
+        for k, (dy, dx) in enumerate(LO.OFFS):
+            yb += abs(W2[c, k]) * LO.shifted(Ha[c], dy, dx)
+    return yb
+
+
+# ------------------------------------------------------------ kernels
+
+@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("nm", [3, 5, 17, 45, 129, 257])
+def test_forward_matches_oracle(B, torch_cuda, nm, var):
+    torch = torch_cuda
+    rng = np.random.default_rng(nm + 7 * var)
+    say("learned forward nm=%d var=%s" % (nm, var))
+    x, r, a = rand_sample(rng, nm, var, seed=nm)
+    w = rand_weights(rng)
+    hl = 1.0 / (nm - 1)
+    X = LO.features(x, r, a, hl)
+    _, _, want = LO.forward(X, w)
+    y = torch.zeros((nm, nm), dtype=torch.float32, device="cuda")
+    B.learn_forward(dev32(torch, x), dev32(torch, r), dev32(torch, a) if var else None,
+                    dev32(torch, w), hl, y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    bound = 1e-5 * magnitude_bound(X, w) + 1e-30
+    inn = (slice(1, -1), slice(1, -1))
+    assert np.all(np.abs(got[inn] - want[inn]) <= bound[inn]), np.max(np.abs(got - want))
+
+
+@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("nm", [5, 33, 45, 129])
+def test_gradient_matches_oracle(B, torch_cuda, nm, var):
+    torch = torch_cuda
+    rng = np.random.default_rng(100 + nm + var)
+    say("learned grad nm=%d var=%s" % (nm, var))
+    x, r, a = rand_sample(rng, nm, var, seed=nm + 1)
+    delta = np.zeros((nm, nm))
+    delta[1:-1, 1:-1] = f32(rng.standard_normal((nm - 2, nm - 2)))
+    w = rand_weights(rng)
+    hl = 1.0 / (nm - 1)
+    Lw, gw = LO.loss_and_grad(x, r, a, hl, delta, w)
+    g, ez, Lg = B.learn_grad(dev32(torch, x), dev32(torch, r), dev32(torch, a) if var else None,
+                             dev32(torch, delta), dev32(torch, w), hl)
+    got = g.cpu().numpy()
+    assert Lg == pytest.approx(Lw, rel=1e-4)
+    assert np.all(np.abs(got - gw) <= 2e-4 * np.max(np.abs(gw))), np.max(np.abs(got - gw)) / np.max(np.abs(gw))
+
+
+def test_adam_step_matches_oracle(B, torch_cuda):
+    torch = torch_cuda
+    rng = np.random.default_rng(5)
+    theta = f32(rng.standard_normal(LO.NW) * 0.2)
+    m1 = np.zeros(LO.NW)
+    m2 = np.zeros(LO.NW)
+    th_d, m1_d, m2_d = dev32(torch, theta), dev32(torch, m1), dev32(torch, m2)
+    w_out = torch.zeros(LO.NW, dtype=torch.float32, device="cuda")
+    for t in range(1, 4):
+        g = rng.standard_normal(LO.NW)
+        B.learn_adam(th_d, m1_d, m2_d, dev64(torch, g), t, 1e-2, w_out)
+        torch.cuda.synchronize()
+        theta, m1, m2 = LO.adam_step(theta, f32(g), m1, m2, t, 1e-2)
+        got = th_d.cpu().numpy().astype(np.float64)
+        # FP32 moments and update: a few ulp of the step (lr) and of theta
+        assert np.all(np.abs(got - theta) <= 1e-6 * np.abs(theta) + 1e-6 * 1e-2)
+        theta = got  # continue from the GPU's masters
+        np.testing.assert_array_equal(w_out.cpu().numpy().astype(np.float64), LO.to_bf16(got))
+
+
+# ------------------------------------------------------------ in the solver
+
+@pytest.mark.parametrize("var", [False, True])
+def test_solver_learned_iterations_match_oracle(B, torch_cuda, var):
+    """Whole-grid learned iterations (lattice relax + interpolation) at every
+    level, 1 and 3 iterations, FP64 cycle precision."""
+    torch = torch_cuda
+    n = 129
+    rng = np.random.default_rng(21 + var)
+    k = O.check_side(n)
+    a = W.grf_problem(n, seed=3)[0] if var else None
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D if var else None)
+    if var:
+        s.set_coefficient(dev64(torch, a))
+    w = rand_weights(rng, 0.15)
+    s.set_smoother(B.LEARNED, dev32(torch, w))
+    for level in range(k):
+        nm = (n - 1) // (1 << level) + 1
+        for iters in (1, 3):
+            say("learned sweeps level=%d iters=%d var=%s" % (level, iters, var))
+            e0 = np.zeros((n, n))
+            e0[1:-1, 1:-1] = rng.standard_normal((n - 2, n - 2))
+            rm = np.zeros((nm, nm))
+            rm[1:-1, 1:-1] = rng.standard_normal((nm - 2, nm - 2))
+            out = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+            s.step_sweeps(level, iters, dev64(torch, e0), dev64(torch, rm), out)
+            torch.cuda.synchronize()
+            want = e0
+            for _ in range(iters):
+                want = LO.sweep(n, level, rm, want, w, a)
+            got = out.cpu().numpy()
+            assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want)), (level, iters)
+
+
+def test_jacobi_weights_reproduce_plain_homg(B, torch_cuda):
+    """The Jacobi-equivalent weights (omega = 0.8 rounds to 0.80078125 in
+    BF16) give the residual history of plain HOMG with that omega."""
+    torch = torch_cuda
+    n = 257
+    a, f = W.grf_problem(n, seed=4)
+    fd, ad = dev64(torch, f), dev64(torch, a)
+    wj = LO.jacobi_weights(0.8)
+    assert LO.to_bf16(wj)[LO.NW1 + 4] == 0.80078125
+    hist = []
+    for learned in (False, True):
+        s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D, omega=0.80078125)
+        s.set_coefficient(ad)
+        if learned:
+            s.set_smoother(B.LEARNED, dev32(torch, wj))
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        res = s.solve_cycles(fd, u, 6)
+        hist.append(np.array(res["history"]))
+    np.testing.assert_allclose(hist[1], hist[0], rtol=1e-4)
+
+
+def test_learned_solve_matches_oracle(B, torch_cuda):
+    """A learned-smoother solve to 1e-10 (FP64 residual, recomputed by the
+    oracle) and within the rigorous bound of the oracle's learned solve at
+    the same cycle count."""
+    torch = torch_cuda
+    n = 65
+    a, f = W.grf_problem(n, seed=6)
+    rng = np.random.default_rng(6)
+    w = LO.to_bf16(LO.jacobi_weights(0.7) + rng.standard_normal(LO.NW) * 0.01)
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+    s.set_coefficient(dev64(torch, a))
+    s.set_smoother(B.LEARNED, dev32(torch, w))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    res = s.solve(dev64(torch, f), u, tol=1e-10)
+    ug = u.cpu().numpy()
+    say("learned solve cycles %d fell_back %s" % (res["cycles"], res["smoother_fell_back"]))
+    _, s2 = O.residual(2, n, f, ug, a)
+    fn = np.sqrt(O.norm2_interior(2, n, f))
+    assert np.sqrt(s2) / fn <= 1e-10 * (1 + 1e-6) + 1e-14
+    uo, ho = LO.solve(n, f, w, a, fixed_cycles=res["cycles"])
+    _, so = O.residual(2, n, f, uo, a)
+    h = 1.0 / (n - 1)
+    lam = np.min(a) * (8 / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    assert np.linalg.norm(ug - uo) <= (np.sqrt(s2) + np.sqrt(so)) / lam * (1 + 1e-6)
+    # the first cycles agree closely (FP32 network noise grows with the cycles)
+    np.testing.assert_allclose(res["history"][:3], ho[:3], rtol=1e-3)
+
+
+def test_fallback_to_jacobi(B, torch_cuda):
+    """Weights that make the relaxation diverge: the solve falls back to
+    damped Jacobi and still converges."""
+    torch = torch_cuda
+    n = 129
+    a, f = W.grf_problem(n, seed=8)
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+    s.set_coefficient(dev64(torch, a))
+    s.set_smoother(B.LEARNED, dev32(torch, LO.jacobi_weights(1.5)))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    res = s.solve(dev64(torch, f), u, tol=1e-10)
+    assert res["smoother_fell_back"] and res["converged"]
+    assert s.residual(dev64(torch, f), u) <= 1e-10 * (1 + 1e-6)
+
+
+def test_learned_smoother_is_2d_only(B, torch_cuda):
+    torch = torch_cuda
+    s = B.Solver(3, 17)
+    with pytest.raises(B.HomgError):
+        s.set_smoother(B.LEARNED, dev32(torch, LO.jacobi_weights(0.8)))
+
+
+# ------------------------------------------------------------ training
+
+def oracle_pairs(n, f, a, max_i=4):
+    """The training pairs of one plain-HOMG cycle from u = 0, rebuilt on the
+    CPU: every relaxation input x_t of every level, its level residual and
+    coefficient, and delta = x* - x_t with x* from a dense LU solve of the
+    level system (independent of HOMG)."""
+    k = O.check_side(n)
+    sched = O.default_schedule(k, max_i)
+    rs = O.pyramid(2, f, k)
+    e = np.zeros((n, n))
+    out = []
+    for m, it in sched:
+        l = 1 << m
+        nm = (n - 1) // l + 1
+        am = a[::l, ::l].copy() if a is not None else None
+        xs = T.dense_solve(2, nm, rs[m], am)
+        for _ in range(it):
+            x = e[::l, ::l].copy()
+            out.append((f32(x), f32(rs[m]), f32(am) if a is not None else None, f32(xs - x), 1.0 / (nm - 1)))
+            e = O.sweep(2, n, m, 0.8, rs[m], e, a)
+    return out
+
+
+def test_training_pairs_match_oracle(B, torch_cuda):
+    """The trainer's pairs, seen through the mean loss of two weight sets,
+    against pairs rebuilt independently on the CPU."""
+    torch = torch_cuda
+    n = 33
+    a, f = W.grf_problem(n, seed=11)
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+    s.set_coefficient(dev64(torch, a))
+    tr = B.Trainer()
+    tr.add_problem(s, dev64(torch, f), cycles=1)
+    pairs = oracle_pairs(n, f, a)
+    assert tr.count() == len(pairs)
+    rng = np.random.default_rng(12)
+    for w in (LO.to_bf16(LO.jacobi_weights(0.8)), rand_weights(rng, 0.2)):
+        want = np.mean([LO.loss(x, r, am, hl, d, w) for x, r, am, d, hl in pairs])
+        got = tr.loss(dev32(torch, w))
+        assert got == pytest.approx(want, rel=1e-4)
+
+
+def test_training_reduces_the_loss(B, torch_cuda):
+    torch = torch_cuda
+    n = 129
+    tr = B.Trainer()
+    for seed in (100, 101):
+        a, f = W.grf_problem(n, seed=seed)
+        s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+        s.set_coefficient(dev64(torch, a))
+        tr.add_problem(s, dev64(torch, f), cycles=2)
+    rng = np.random.default_rng(13)
+    w0 = LO.to_bf16(LO.jacobi_weights(0.8) + rng.standard_normal(LO.NW) * 0.02)
+    l0 = tr.loss(dev32(torch, w0))
+    w, hist = tr.train(dev32(torch, w0), steps=60, batch=8, lr=2e-3, seed=1)
+    l1 = tr.loss(w)
+    say("loss %.4f -> %.4f (batch losses %.4f .. %.4f)" % (l0, l1, hist[0], hist[-1]))
+    assert l1 < l0
+    assert np.all(np.isfinite(hist))
+    # deterministic: the same run gives the same bits
+    w2, hist2 = tr.train(dev32(torch, w0), steps=60, batch=8, lr=2e-3, seed=1)
+    assert torch.equal(w, w2) and hist == hist2
