@@ -54,17 +54,22 @@ def sweep_bytes(d, n, level, mode, elem=8):
 
 
 def kernel_symbol(d, kind, level, mode):
+    """The kernel's name as the profiler prints it (without the namespace and
+    argument list), so the bench line and the rocprofv3 summary can be matched."""
+    var2 = ", false" if d == 2 else ""
     if kind == "sweep":
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
-        return "%s<double, %d>" % (base, mode)
+        return "%s<double, %d%s>" % (base, mode, var2)
     if kind == "lattice":
         if mode & 4:
-            return "k_lattice_small_%dd<double, %s>" % (d, "true" if mode & 1 else "false")
-        return "k_sweep_%dd_l0<double, %d> (compact lattice)" % (d, mode & 3)
+            return "k_lattice_small_%dd<double, %s%s>" % (d, "true" if mode & 1 else "false", var2)
+        return "k_lattice_sweep_%dd<double, %d%s>" % (d, mode & 3, var2)
     if kind == "level_write":
         return "k_level_write_%dd<double, %d>" % (d, mode)
-    return {"residual": "k_residual_%dd" % d, "restrict": "k_restrict_%dd" % d,
-            "norm": "k_norm2_%dd" % d, "finalize": "k_finalize", "gather": "k_gather<double>"}[kind]
+    if kind == "residual":
+        return "k_residual_%dd<double%s>" % (d, var2)
+    return {"restrict": "k_restrict_%dd<double>" % d, "norm": "k_norm2_%dd" % d,
+            "finalize": "k_finalize", "gather": "k_gather<double>"}[kind]
 
 
 def kernel_bytes(d, n, entry):
@@ -169,6 +174,59 @@ def mixed_precision_section(P, W, torch, dev, reps=3):
             "results": out}
 
 
+def batched_section(P, W, torch, dev, count=512, reps=3):
+    """512 independent 2D Poisson problems, sides drawn uniformly from
+    {65, 129, 257, 513, 1025} (seed 0), f ~ U[-1, 1]: FP32 sweeps under FP64
+    residual/update, all problems in one persistent launch (a HIP graph
+    replayed per solve), tile rows tuned per side; every problem to 1e-10.
+    Beside it: the same problems solved one after another by the
+    single-problem solver in the same precision."""
+    sides, fnp = W.batch2d(count, seed=0)
+    fs = [torch.from_numpy(f).to(dev) for f in fnp]
+    del fnp
+    us = [torch.zeros_like(f) for f in fs]
+    bs = P.BatchSolver(sides, precision="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs.tune(fs, us, tol=1e-10)
+    tune_s = time.perf_counter() - t0
+    times, res = [], None
+    for _ in range(reps + 1):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bs.solve(fs, us, tol=1e-10, raise_on_status=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = sorted(times[1:])[len(times[1:]) // 2]
+    sweeps = {}
+    for s in set(sides):
+        k = (s - 1).bit_length() - 1
+        sweeps[s] = sum(min(2 ** (k - 1 - m + 1), 4) for m in range(k - 1, -1, -1))
+    updates = sum(c * sweeps[s] * float(s) ** 2 for c, s in zip(res["cycles"], sides))
+    # one problem at a time with the single-problem solver
+    solvers = {s: P.Solver(2, s, precision="fp32") for s in set(sides)}
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f, u, s in zip(fs, us, sides):
+        solvers[s].solve(f, u, tol=1e-10, raise_on_status=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {"workload": "%d 2D Poisson problems, sides uniform from {65,129,257,513,1025} (seed 0), "
+                       "f ~ U[-1,1], FP32 sweeps + FP64 refinement, tol 1e-10" % count,
+           "total_nodes": int(sum(s * s for s in sides)), "status": res["status"],
+           "all_converged": all(st == 0 for st in res["statuses"]),
+           "max_final_relres": max(res["relres"]), "cycles_min_max": [min(res["cycles"]), max(res["cycles"])],
+           "time_to_1e-10_s": t, "node_updates_per_s": updates / t, "tune_s": tune_s,
+           "one_by_one_single_solver_s": t_seq, "speedup_vs_one_by_one": t_seq / t}
+    log("batched: %s" % out)
+    bs.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +236,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 precision comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched solve")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (scale for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -192,6 +253,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "launches": 5}), flush=True)
+        return
 
     probs = []
     for name, d, n in PROBLEMS:
@@ -267,6 +337,9 @@ def main():
     mixed = None
     if not args.no_mixed:
         mixed = mixed_precision_section(P, W, torch, dev)
+    batched = None
+    if not args.no_batched:
+        batched = batched_section(P, W, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -281,7 +354,7 @@ def main():
                                   "MaxI %d, omega 4/5 (2D) 6/7 (3D)" % args.max_i,
                       "problems": per, "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:10],
-           "mixed_precision": mixed}
+           "mixed_precision": mixed, "batched": batched}
     print(json.dumps(out), flush=True)
 
 

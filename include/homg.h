@@ -315,7 +315,7 @@ typedef struct homg_train_options {
     size_t struct_size;    /* sizeof(homg_train_options) */
     int steps;             /* Adam steps (>= 1) */
     int batch;             /* samples per step (1..256) */
-    float lr, beta1, beta2, eps;
+    double lr, beta1, beta2, eps;  /* Adam step size and parameters */
     uint64_t seed;
     int reserved[8];       /* must be 0 */
 } homg_train_options;
@@ -344,15 +344,16 @@ homg_status homg_trainer_destroy(homg_trainer t);
  * homg_learn_adam: one Adam step (Kingma and Ba) on 576 FP32 master weights
  *   theta with moments m1, m2 (device, updated in place), gradient grad
  *   (device, 576 doubles), 1-based step t; w_out (device, 576) receives the
- *   FP32 values of theta rounded to BF16.
+ *   FP32 values of theta rounded to BF16.  Moments are FP32; the bias
+ *   corrections and the update are formed in FP64 and theta is rounded back.
  */
 homg_status homg_learn_forward(int nm, double hl, const float *x, const float *r, const float *a,
                                const float *w, float *y, void *stream);
 homg_status homg_learn_grad(int nm, double hl, const float *x, const float *r, const float *a,
                             const float *delta, const float *w, double *grad, double *loss,
                             void *stream);
-homg_status homg_learn_adam(float *theta, float *m1, float *m2, const double *grad, int t, float lr,
-                            float beta1, float beta2, float eps, float *w_out, void *stream);
+homg_status homg_learn_adam(float *theta, float *m1, float *m2, const double *grad, int t, double lr,
+                            double beta1, double beta2, double eps, float *w_out, void *stream);
 
 /* Text of the last error on h (or of the calling thread if h is NULL). */
 const char *homg_last_error(homg_handle h);

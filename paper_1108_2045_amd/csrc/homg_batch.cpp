@@ -7,7 +7,8 @@
 // launch (state reset + persistent kernel) is captured once into a HIP
 // graph on an internal stream and replayed on the caller's stream; the
 // per-call inputs (array pointers, tolerance) live in device descriptors
-// uploaded before each replay, so the graph never changes.
+// uploaded before each replay, so the graph never changes.  The persistent
+// node is a cooperative launch, so all its workgroups are resident at once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,7 +42,6 @@ struct homg_batch_ctx {
   BatchSync* h_sync = nullptr;
   BatchSync* d_sync = nullptr;
   void* arena = nullptr;
-  hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int grid = 0, device = 0;
@@ -76,7 +76,6 @@ void free_batch(homg_batch_ctx* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->cap) (void)hipStreamDestroy(b->cap);
   (void)hipFree(b->arena);
   (void)hipFree(b->d_probs);
   (void)hipFree(b->d_run);
@@ -115,16 +114,11 @@ homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u
                          hipMemcpyHostToDevice, s));
   BHIP(b, hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
   if (!b->exec) {
-    BHIP(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_batch(b->prec, b->count, b->grid, b->d_probs, b->d_state, b->d_done,
-                                 b->d_sweep_levels, b->d_run, b->d_sync, b->cap);
     hipGraph_t g = nullptr;
-    hipError_t ce = hipStreamEndCapture(b->cap, &g);
-    if (le != hipSuccess || ce != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return bfail(b, HOMG_ERR_HIP, std::string("graph capture failed: ") +
-                                        hipGetErrorString(le != hipSuccess ? le : ce));
-    }
+    hipError_t ge = build_batch_graph(b->prec, b->count, b->grid, b->d_probs, b->d_state, b->d_done,
+                                      b->d_sweep_levels, b->d_run, b->d_sync, &g);
+    if (ge != hipSuccess)
+      return bfail(b, HOMG_ERR_HIP, std::string("graph construction failed: ") + hipGetErrorString(ge));
     b->graph = g;
     BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
@@ -223,7 +217,6 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_state), sizeof(BatchState) * count, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_done), sizeof(int) * count, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_sync), sizeof(BatchSync), hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     free_batch(b);

@@ -261,7 +261,7 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cu
       const int mode = (first && t == 1) ? SW_ZERO_OLD : 0;
       LAUNCH_K(h, s, K_LATTICE, m, mode,
                launch_sweep(h->prec, h->d, nm, 0, h->omega, X[src], X[1 - src], cl, h->r[m],
-                            h->rl[m], am, alm, nullptr, none, mode, done, s));
+                            h->rl[m], am, alm, nullptr, none, mode, done, s, true));
       src = 1 - src;
     }
     xcur = X[src];

@@ -65,11 +65,12 @@ hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void*
 // arrays (layout el); rm: compact level-m residual (layout rl); am: compact
 // level-m nodal coefficient (FP64, layout al) or null; mode: SweepMode bits;
 // with SW_ACCUM the iterate is added to u (FP64, layout ul) instead of
-// being stored in en.
+// being stored in en.  compact: a level-0 iteration on the compact lattice
+// of a coarse level (same arithmetic, a kernel symbol of its own).
 hipError_t launch_sweep(int prec, int d, int n, int m, double omega, const void* eo, void* en,
                         const Lay& el, const void* rm, const Lay& rl, const double* am,
                         const Lay& al, double* u, const Lay& ul, int mode, const int* done,
-                        hipStream_t s);
+                        hipStream_t s, bool compact = false);
 // Convert between a dense FP64 array and an internal array of `prec`.
 hipError_t launch_pack(int prec, int d, const double* src, const Lay& sl, void* dst,
                        const Lay& dl, hipStream_t s);
@@ -117,7 +118,7 @@ struct BatchProblem {         // one problem, read by the persistent kernel
 };
 struct BatchState {
   int cycles;
-  int pad;
+  int retired;                // step in which the problem finished (INT32_MAX while active)
   double fnorm;
   double final_rel;
 };
@@ -136,6 +137,9 @@ int batch_tiles(int side, int len);
 hipError_t launch_batch(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs, int* done,
                         const int* levels_of_sweep, const BatchRun* run, BatchSync* sync,
                         hipStream_t s);
+hipError_t build_batch_graph(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs,
+                             int* done, const int* levels_of_sweep, const BatchRun* run,
+                             BatchSync* sync, hipGraph_t* out);
 
 // ---- learned lattice smoother (2D)
 constexpr int HID = 16;                 // hidden channels
@@ -167,8 +171,8 @@ hipError_t launch_train_reduce(const float* part, int64_t pstride, int rows, dou
                                hipStream_t s);
 hipError_t launch_train_adam(const double* sums, int batch, const double* e0s, const int* idx,
                              float* theta, float* m1, float* m2, uint16_t* wbf, float* w32,
-                             int step, float lr, float beta1, float beta2, float eps, double* loss,
-                             hipStream_t s);
+                             int step, double lr, double beta1, double beta2, double eps,
+                             double* loss, hipStream_t s);
 // *out = E(v) = v^T A v over interior nodes (part: ENERGY_MAX_PARTS doubles).
 hipError_t launch_energy(const float* v, const float* a, int nm, double* part, double* out,
                          hipStream_t s);

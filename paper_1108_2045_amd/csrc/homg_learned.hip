@@ -425,7 +425,9 @@ __global__ __launch_bounds__(256) void k_train_reduce(const float* __restrict__ 
 }
 
 // Mean gradient over the batch (the `batch` rows of sums, stride NW + 1,
-// added in order), Adam on the FP32 masters, the BF16 copy (wbf, nullable)
+// added in order), Adam on the FP32 masters (FP32 moments; bias corrections
+// and the update in FP64, since 1 - beta^t loses digits in FP32), the BF16
+// copy (wbf, nullable)
 // and its FP32 expansion w32 for the kernels.  With loss != null,
 // loss[step - 1] = mean over the batch of E(z) / E(delta), E(delta) of row b
 // at e0s[idx[b]].
@@ -435,21 +437,21 @@ __global__ __launch_bounds__(640) void k_train_adam(const double* __restrict__ s
                                                     float* __restrict__ theta,
                                                     float* __restrict__ m1, float* __restrict__ m2,
                                                     uint16_t* __restrict__ wbf,
-                                                    float* __restrict__ w32, int step, float lr,
-                                                    float beta1, float beta2, float eps,
+                                                    float* __restrict__ w32, int step, double lr,
+                                                    double beta1, double beta2, double eps,
                                                     double* __restrict__ loss) {
   const int j = threadIdx.x;
   if (j < NW) {
     double g = 0.0;
     for (int b = 0; b < batch; ++b) g += sums[b * (NW + 1) + j];
     const float gf = float(g / batch);
-    const float mm = beta1 * m1[j] + (1.f - beta1) * gf;
-    const float vv = beta2 * m2[j] + (1.f - beta2) * gf * gf;
+    const float mm = float(beta1) * m1[j] + float(1.0 - beta1) * gf;
+    const float vv = float(beta2) * m2[j] + float(1.0 - beta2) * (gf * gf);
     m1[j] = mm;
     m2[j] = vv;
-    const float mhat = mm / (1.f - powf(beta1, float(step)));
-    const float vhat = vv / (1.f - powf(beta2, float(step)));
-    const float th = theta[j] - lr * mhat / (sqrtf(vhat) + eps);
+    const double mhat = double(mm) / (1.0 - pow(beta1, double(step)));
+    const double vhat = double(vv) / (1.0 - pow(beta2, double(step)));
+    const float th = float(double(theta[j]) - lr * mhat / (sqrt(vhat) + eps));
     theta[j] = th;
     const uint16_t b16 = to_bf16_bits(th);
     if (wbf) wbf[j] = b16;
@@ -623,8 +625,8 @@ hipError_t launch_train_reduce(const float* part, int64_t pstride, int rows, dou
 
 hipError_t launch_train_adam(const double* sums, int batch, const double* e0s, const int* idx,
                              float* theta, float* m1, float* m2, uint16_t* wbf, float* w32,
-                             int step, float lr, float beta1, float beta2, float eps, double* loss,
-                             hipStream_t s) {
+                             int step, double lr, double beta1, double beta2, double eps,
+                             double* loss, hipStream_t s) {
   LL_LAUNCH(k_train_adam, dim3(1), dim3(640), s, sums, batch, e0s, idx, theta, m1, m2, wbf, w32,
             step, lr, beta1, beta2, eps, loss);
 }

@@ -103,10 +103,10 @@ void homg_train_options_init(homg_train_options* opt) {
   opt->struct_size = sizeof(homg_train_options);
   opt->steps = 300;
   opt->batch = 8;
-  opt->lr = 1e-3f;
-  opt->beta1 = 0.9f;
-  opt->beta2 = 0.999f;
-  opt->eps = 1e-8f;
+  opt->lr = 1e-3;
+  opt->beta1 = 0.9;
+  opt->beta2 = 0.999;
+  opt->eps = 1e-8;
   opt->seed = 0;
 }
 
@@ -288,8 +288,8 @@ homg_status homg_trainer_train(homg_trainer t, const float* w0, const homg_train
     if (opt->reserved[i]) return tfail(t, HOMG_ERR_INVALID_ARG, "reserved options must be 0");
   if (opt->steps < 1 || opt->steps > 1000000 || opt->batch < 1 || opt->batch > 256)
     return tfail(t, HOMG_ERR_INVALID_ARG, "steps must be >= 1 and batch in [1, 256]");
-  if (!(opt->lr > 0.f) || !(opt->beta1 >= 0.f && opt->beta1 < 1.f) ||
-      !(opt->beta2 >= 0.f && opt->beta2 < 1.f) || !(opt->eps > 0.f))
+  if (!(opt->lr > 0.0) || !(opt->beta1 >= 0.0 && opt->beta1 < 1.0) ||
+      !(opt->beta2 >= 0.0 && opt->beta2 < 1.0) || !(opt->eps > 0.0))
     return tfail(t, HOMG_ERR_INVALID_ARG, "invalid Adam parameters");
   const int S = int(t->samples.size());
   if (S < 1) return tfail(t, HOMG_ERR_INVALID_ARG, "no samples");
@@ -402,10 +402,11 @@ homg_status homg_learn_grad(int nm, double hl, const float* x, const float* r, c
   return HOMG_OK;
 }
 
-homg_status homg_learn_adam(float* theta, float* m1, float* m2, const double* grad, int t, float lr,
-                            float beta1, float beta2, float eps, float* w_out, void* stream) {
+homg_status homg_learn_adam(float* theta, float* m1, float* m2, const double* grad, int t, double lr,
+                            double beta1, double beta2, double eps, float* w_out, void* stream) {
   if (!theta || !m1 || !m2 || !grad || !w_out) return tfail(nullptr, HOMG_ERR_INVALID_ARG, "null array");
-  if (t < 1 || !(lr > 0.f) || !(eps > 0.f)) return tfail(nullptr, HOMG_ERR_INVALID_ARG, "invalid Adam parameters");
+  if (t < 1 || !(lr > 0.0) || !(eps > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    return tfail(nullptr, HOMG_ERR_INVALID_ARG, "invalid Adam parameters");
   hipStream_t s = static_cast<hipStream_t>(stream);
   TCHK(nullptr, launch_train_adam(grad, 1, nullptr, nullptr, theta, m1, m2, nullptr, w_out, t, lr,
                                   beta1, beta2, eps, nullptr, s));

@@ -44,8 +44,8 @@ class Info(ctypes.Structure):
 
 class TrainOptions(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("steps", ctypes.c_int), ("batch", ctypes.c_int),
-                ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int * 8)]
+                ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("seed", ctypes.c_uint64), ("reserved", ctypes.c_int * 8)]
 
 
 SMOOTHER_WEIGHTS = 576
@@ -107,8 +107,8 @@ def load_library(path=LIB_PATH):
     L.homg_learn_forward.argtypes = [ctypes.c_int, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     L.homg_learn_grad.argtypes = [ctypes.c_int, ctypes.c_double, vp, vp, vp, vp, vp, vp,
                                   ctypes.POINTER(ctypes.c_double), vp]
-    L.homg_learn_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
-                                  ctypes.c_float, ctypes.c_float, vp, vp]
+    L.homg_learn_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, vp, vp]
     L.homg_last_error.argtypes = [H]
     L.homg_last_error.restype = ctypes.c_char_p
     L.homg_version.argtypes = []
