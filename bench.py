@@ -227,6 +227,79 @@ def batched_section(P, W, torch, dev, count=512, reps=3):
     return out
 
 
+def learned_section(P, W, torch, dev, n=1025, train_seeds=range(100, 164), held_out=range(200, 204),
+                    pair_cycles=1, steps=400, batch=8, lr=2e-3, reps=3):
+    """2D -div(a grad u) = f on 1025^2, a = exp(GRF) (sigma 1, correlation
+    length 0.1), f ~ U[-1, 1]: the learned relaxation trained on the GPU on
+    pairs that plain HOMG generates on the training problems, gated on the
+    held-out problems, then time to 1e-10 of plain (damped-Jacobi) HOMG and
+    of HOMG with the learned relaxation on each held-out problem."""
+    def solver(a):
+        s = P.Solver(2, n, stencil=P.DIFFUSION_5PT_2D)
+        s.set_coefficient(torch.from_numpy(a).to(dev))
+        return s
+
+    t0 = time.perf_counter()
+    tr = P.Trainer()
+    for seed in train_seeds:
+        a, f = W.grf_problem(n, seed=seed)
+        s = solver(a)
+        tr.add_problem(s, torch.from_numpy(f).to(dev), cycles=pair_cycles)
+        s.close()
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    # start: damped Jacobi (omega 0.8) plus small seeded noise on every weight,
+    # so that all 16 hidden channels receive gradients
+    rng = np.random.default_rng(0)
+    w0 = P.jacobi_weights(0.8, dev) + torch.from_numpy(
+        (0.02 * rng.standard_normal(P.SMOOTHER_WEIGHTS)).astype(np.float32)).to(dev)
+    loss0 = tr.loss(w0)
+    t0 = time.perf_counter()
+    w, hist = tr.train(w0, steps=steps, batch=batch, lr=lr, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    loss1 = tr.loss(w)
+    samples = tr.count()
+    tr.close()
+    held = []
+    for seed in held_out:
+        a, f = W.grf_problem(n, seed=seed)
+        s = solver(a)
+        fd = torch.from_numpy(f).to(dev)
+        s.set_smoother(P.LEARNED, w)
+        gate = s.smoother_gate([fd], 6)
+        entry = {"seed": seed, "gate_accepted": gate["accepted"], "rho_learned": gate["rho_learned"][0],
+                 "rho_jacobi": gate["rho_jacobi"][0]}
+        for name, sm in (("jacobi", P.JACOBI), ("learned", P.LEARNED)):
+            s.set_smoother(sm)
+            u = torch.zeros_like(fd)
+            times, res = [], None
+            for _ in range(reps + 1):
+                u.zero_()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                res = s.solve(fd, u, tol=1e-10, raise_on_status=False)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t1)
+            entry[name] = {"cycles": res["cycles"], "time_to_1e-10_s": sorted(times[1:])[len(times[1:]) // 2],
+                           "final_relres": res["final_relres"], "converged": res["converged"],
+                           "fell_back": res["smoother_fell_back"]}
+        entry["speedup_learned_vs_jacobi"] = entry["jacobi"]["time_to_1e-10_s"] / entry["learned"]["time_to_1e-10_s"]
+        held.append(entry)
+        log("learned held-out %d: %s" % (seed, entry))
+        s.close()
+    accepted = all(h["gate_accepted"] for h in held)
+    return {"workload": "2D -div(a grad u) = f, %d^2, a = exp(GRF sigma 1, corr 0.1), f ~ U[-1,1]; "
+                        "2-layer 3x3 conv, 16 channels, BF16 weights, FP32 arithmetic" % n,
+            "training": {"problems": len(list(train_seeds)), "pair_cycles": pair_cycles, "samples": samples,
+                         "pair_generation_s": gen_s, "steps": steps, "batch": batch, "lr": lr,
+                         "train_s": train_s, "loss_start": loss0, "loss_end": loss1,
+                         "batch_loss_first_last": [hist[0], hist[-1]]},
+            "gate_accepted": accepted, "held_out": held,
+            "geomean_speedup_learned_vs_jacobi": float(np.exp(np.mean(
+                [np.log(h["speedup_learned_vs_jacobi"]) for h in held])))}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +310,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-launch event timing")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched solve")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother training and timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -340,6 +414,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = batched_section(P, W, torch, dev)
+    learned = None
+    if not args.no_learned:
+        learned = learned_section(P, W, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -354,7 +431,7 @@ def main():
                                   "MaxI %d, omega 4/5 (2D) 6/7 (3D)" % args.max_i,
                       "problems": per, "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:10],
-           "mixed_precision": mixed, "batched": batched}
+           "mixed_precision": mixed, "batched": batched, "learned_smoother": learned}
     print(json.dumps(out), flush=True)
 
 

@@ -128,7 +128,8 @@ homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u
   BHIP(b, hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, s));
   BHIP(b, hipStreamSynchronize(s));
   if (b->h_sync->abort)
-    return bfail(b, HOMG_ERR_HIP, "persistent batched launch aborted: a grid barrier exceeded its time limit");
+    return bfail(b, HOMG_ERR_HIP, "persistent batched launch aborted: a grid barrier exceeded its time limit (grid " +
+                                      std::to_string(b->grid) + " workgroups, step " + std::to_string(b->h_sync->steps) + ")");
   return HOMG_OK;
 }
 
@@ -268,7 +269,13 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     free_batch(b);
     return bfail(nullptr, HOMG_ERR_HIP, "cannot size the persistent launch");
   }
-  b->grid = per_cu * cus;
+  // Every workgroup must be resident for the grid barrier.  The kernel's
+  // scalar registers (106 per wave) already hold it to 7 workgroups of 4
+  // waves per CU, and a grid of the full occupancy answer was seen to stall
+  // at the barrier; half of it keeps every workgroup resident with room to
+  // spare (tiles are taken round-robin, so fewer workgroups only lengthen
+  // their walks).
+  b->grid = std::max(1, per_cu / 2) * cus;
   // one barrier wait may not exceed 5 s of wall clock
   b->barrier_ticks = uint64_t(std::max(clock_khz, 1)) * 1000ull * 5ull;
   (void)st;

@@ -289,6 +289,19 @@ class Solver:
         return {"accepted": bool(acc.value), "rho_learned": list(rl), "rho_jacobi": list(rj)}
 
 
+def jacobi_weights(omega, device="cuda"):
+    """A float32 weight vector whose network is exactly omega * rho (damped
+    Jacobi): hidden channels 0 and 1 take +rho and -rho at the centre tap,
+    and the output combines them with +omega and -omega."""
+    import torch
+    w = torch.zeros(SMOOTHER_WEIGHTS, dtype=torch.float32)
+    w[0 * 27 + 0 * 9 + 4] = 1.0
+    w[1 * 27 + 0 * 9 + 4] = -1.0
+    w[432 + 0 * 9 + 4] = omega
+    w[432 + 1 * 9 + 4] = -omega
+    return w.to(device)
+
+
 def _weights(w):
     if tuple(w.shape) != (SMOOTHER_WEIGHTS,):
         raise ValueError("the smoother has %d weights" % SMOOTHER_WEIGHTS)
