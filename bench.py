@@ -98,6 +98,27 @@ def kernel_bytes(d, n, entry):
     return 0.0
 
 
+def measured_traffic(symbol):
+    """HBM bytes per launch of `symbol` from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs recorded in profiles/hbm_traffic.json (scaled by the
+    counters' reading of a plain copy), or None if none were taken for this
+    kernel or the kernel sources changed since they were."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    for name, digest in rec.get("source_sha256", {}).items():
+        src = os.path.join(ROOT, "paper_1108_2045_amd", "csrc", name)
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != digest:
+            return None
+    k = rec.get("kernels", {}).get(symbol)
+    if not k:
+        return None
+    return k["read_bytes"] + k["write_bytes"]
+
+
 def cpu_baseline():
     """The FP64 oracle (as it stands) on a bounded sample: one MFMG cycle of
     each problem from u = 0 (residual, restriction, all iterations, update,
@@ -401,7 +422,7 @@ def main():
         k = by_sym[(dom["problem"], dom["kernel"])]
         achieved = (k["bytes"] / k["launches"]) / (k["ms"] / k["launches"] / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom["kernel"]),
                     "kernel": dom["kernel"], "problem": dom["problem"],
                     "bytes_per_launch": k["bytes"] / k["launches"],
                     "avg_launch_us": 1e3 * k["ms"] / k["launches"]}

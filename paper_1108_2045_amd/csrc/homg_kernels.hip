@@ -54,6 +54,13 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return uint16_t(u >> 16);
 }
 __device__ __forceinline__ void st(bf16* p, float v) { __builtin_nontemporal_store(f2bf(v), &p->bits); }
+// Write-only passes (a level's whole-grid write, the coarse-level sweeps)
+// keep ordinary stores: on MI355X a pure write stream runs faster with them
+// (5.6 against 4.5 TB/s), while streams that also read gain from streaming
+// stores.
+__device__ __forceinline__ void st_w(double* p, double v) { *p = v; }
+__device__ __forceinline__ void st_w(float* p, float v) { *p = v; }
+__device__ __forceinline__ void st_w(bf16* p, float v) { p->bits = f2bf(v); }
 // u += v on the caller's FP64 array (the last iteration of a cycle).
 __device__ __forceinline__ void add_to(double* p, double v) { __builtin_nontemporal_store(*p + v, p); }
 
@@ -154,7 +161,13 @@ static dim3 grid_of(int d, int n, int len) {
 int partials_bound(int d, int n) {
   if (n < 3) return 1;
   dim3 g = grid_of(d, n, walk_len(d, n));
-  return int(g.x * g.y * g.z);
+  int64_t count = int64_t(g.x) * g.y * g.z;
+  if (d == 3) {  // the 3D residual's grid: 4 rows per lane, walks of 8 planes
+    const int64_t inner = n - 2, len3 = inner < 8 ? inner : 8;
+    const int64_t c3 = ((inner + BX3 - 1) / BX3) * ((inner + 4 * BY3 - 1) / (4 * BY3)) * ((inner + len3 - 1) / len3);
+    if (c3 > count) count = c3;
+  }
+  return int(count);
 }
 
 Lay dense_layout(int d, int side) {
@@ -278,31 +291,61 @@ __global__ __launch_bounds__(256) void k_residual_2d(
   tile_residual_2d<T, VAR>(u, up, f, fp, a, ap, r, rp, n, len, inv_h2, partials, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
+// 3D residual: a lane owns R3Y consecutive y rows (as the level-0 sweep),
+// walks of 8 planes.
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual_3d(
     const double* __restrict__ u, int64_t up, int64_t upl, const double* __restrict__ f,
     int64_t fp, int64_t fpl, T* __restrict__ r, int64_t rp, int64_t rpl, int n, int len,
     double inv_h2, double* __restrict__ partials, const int* __restrict__ done) {
   if (*done) return;
+  constexpr int R = 4;  // = R3Y (declared with the sweeps below)
   const int x = 1 + blockIdx.x * BX3 + threadIdx.x;
-  const int y = 1 + blockIdx.y * BY3 + threadIdx.y;
+  const int yb = 1 + (blockIdx.y * BY3 + threadIdx.y) * R;
   const int z0 = 1 + blockIdx.z * len;
   const int z1 = min(n - 1, z0 + len);
   double s = 0.0;
-  if (x <= n - 2 && y <= n - 2) {
-    const int64_t col = int64_t(y) * up + x;
-    double zm = u[int64_t(z0 - 1) * upl + col];
-    double c = u[int64_t(z0) * upl + col];
+  if (x <= n - 2 && yb <= n - 2) {
+    double c[R], zm[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int64_t col = int64_t(min(yb + k, n - 2)) * up + x;
+      zm[k] = u[int64_t(z0 - 1) * upl + col];
+      c[k] = u[int64_t(z0) * upl + col];
+    }
+    const int64_t ylo = int64_t(yb - 1) * up + x;
+    const int64_t yhi = int64_t(min(yb + R, n - 1)) * up + x;
     for (int z = z0; z < z1; ++z) {
-      const double* pl = u + int64_t(z) * upl + col;
-      const double zp = pl[upl];
-      const double xm = pl[-1], xp = pl[1], ym = pl[-up], yp = pl[up];
-      const double au = fmac(6.0, c, -(((xm + xp) + (ym + yp)) + (zm + zp)));
-      const double rv = fmac(-inv_h2, au, f[int64_t(z) * fpl + int64_t(y) * fp + x]);
-      st(r + int64_t(z) * rpl + int64_t(y) * rp + x, typename Tr<T>::C(rv));
-      s = fmac(rv, rv, s);
-      zm = c;
-      c = zp;
+      double zp[R], xm[R], xp[R], fv[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int yk = min(yb + k, n - 2);
+        const double* q = u + int64_t(z) * upl + int64_t(yk) * up + x;
+        zp[k] = q[upl];
+        xm[k] = q[-1];
+        xp[k] = q[1];
+        fv[k] = f[int64_t(z) * fpl + int64_t(yk) * fp + x];
+      }
+      const double below = u[int64_t(z) * upl + ylo];
+      const double above = u[int64_t(z) * upl + yhi];
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        // u's boundary rows carry the Dirichlet data, so the row above the
+        // last interior row is read from memory, never assumed 0
+        const double ym = k == 0 ? below : c[k - 1];
+        const double yp = k == R - 1 ? above : (yb + k + 1 <= n - 2 ? c[k + 1] : u[int64_t(z) * upl + int64_t(n - 1) * up + x]);
+        const double au = fmac(6.0, c[k], -(((xm[k] + xp[k]) + (ym + yp)) + (zm[k] + zp[k])));
+        const double rv = fmac(-inv_h2, au, fv[k]);
+        if (yb + k <= n - 2) {
+          st(r + int64_t(z) * rpl + int64_t(yb + k) * rp + x, typename Tr<T>::C(rv));
+          s = fmac(rv, rv, s);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        zm[k] = c[k];
+        c[k] = zp[k];
+      }
     }
   }
   s = block_sum<256>(s);
@@ -415,14 +458,25 @@ __global__ __launch_bounds__(256) void k_restrict_3d(const T* __restrict__ rf, i
 // reads of e).  ACCUM: the new iterate is added to u instead of stored (last
 // iteration of a cycle).
 
-template <typename T, int MODE, bool VAR>
+template <typename T, int MODE, bool VAR, bool WRITE_ONLY = false>
 __device__ __forceinline__ void emit_2d(T* en, int64_t eoff, double* u, int64_t uoff,
                                         typename Tr<T>::C v) {
   if (MODE & SW_ACCUM) {
     add_to(u + uoff, double(v));
+  } else if (WRITE_ONLY) {
+    st_w(en + eoff, v);
   } else {
     st(en + eoff, v);
   }
+}
+
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (workgroup h
+// runs on XCD h % 8).  xcd_order maps h to a logical index so that each XCD
+// receives one contiguous range of logical workgroups (a bijection on
+// [0, count)).
+__device__ __forceinline__ unsigned xcd_order(unsigned h, unsigned count) {
+  const unsigned q = count / 8, rem = count % 8, x = h % 8;
+  return x * q + min(x, rem) + h / 8;
 }
 
 // Level 0: every interior node relaxes (plain damped Jacobi).  The walk
@@ -504,7 +558,11 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
     int64_t rp, const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up,
     int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done) {
   if (*done) return;
-  tile_sweep_2d_l0<T, MODE, VAR>(eo, en, ep, r, rp, a, ap, u, up, n, len, w, hl2, blockIdx.x, blockIdx.y);
+  // one-dimensional grid in XCD order: the walks of one XCD form one band of
+  // rows, so the rows shared by vertically adjacent walks stay in its L2
+  const unsigned lg = xcd_order(blockIdx.x, gridDim.x);
+  const int gx = (n - 2 + BX2 - 1) / BX2;
+  tile_sweep_2d_l0<T, MODE, VAR>(eo, en, ep, r, rp, a, ap, u, up, n, len, w, hl2, int(lg % gx), int(lg / gx));
 }
 
 // Levels m >= 1: lattice nodes relax, the rest interpolate.  The lane keeps
@@ -565,7 +623,7 @@ __device__ __forceinline__ void tile_sweep_2d_coarse(
     } else {
       v = lerp(top, bot, C(y - ya) * inv_l);
     }
-    emit_2d<T, MODE, VAR>(en, int64_t(y) * ep + x, u, int64_t(y) * up + x, v);
+    emit_2d<T, MODE, VAR, true>(en, int64_t(y) * ep + x, u, int64_t(y) * up + x, v);
   }
 }
 
@@ -579,6 +637,12 @@ __global__ __launch_bounds__(256) void k_sweep_2d_coarse(
   tile_sweep_2d_coarse<T, MODE, VAR>(eo, en, ep, rm, rp, am, ap, u, up, n, len, m, w, hl2, blockIdx.x, blockIdx.y);
 }
 
+// 3D level 0: a lane owns R3Y consecutive y rows of one x column and walks
+// z, so the y neighbours of its inner rows come from its own registers and
+// only the rows just below and above its group are loaded (the block's
+// 64 x 4 lanes cover 64 x 16 nodes of each plane).
+constexpr int R3Y = 4;
+
 template <typename T, int MODE>
 __device__ __forceinline__ void tile_sweep_3d_l0(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, int64_t epl,
@@ -586,34 +650,61 @@ __device__ __forceinline__ void tile_sweep_3d_l0(
     int64_t upl, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2) {
   using C = typename Tr<T>::C;
   const int x = 1 + blockIdx.x * BX3 + threadIdx.x;
-  const int y = 1 + blockIdx.y * BY3 + threadIdx.y;
-  if (x > n - 2 || y > n - 2) return;
+  const int yb = 1 + (blockIdx.y * BY3 + threadIdx.y) * R3Y;
+  if (x > n - 2 || yb > n - 2) return;
   const int z0 = 1 + blockIdx.z * len;
   const int z1 = min(n - 1, z0 + len);
-  const int64_t col = int64_t(y) * ep + x;
-  C zm = C(0), c = C(0);
-  if (!(MODE & SW_ZERO_OLD)) {
-    zm = ld(eo + int64_t(z0 - 1) * epl + col);
-    c = ld(eo + int64_t(z0) * epl + col);
-  }
-  for (int z = z0; z < z1; ++z) {
-    const C rv = ld(r + int64_t(z) * rpl + int64_t(y) * rp + x);
-    C zp = C(0), xm = C(0), xp = C(0), ym = C(0), yp = C(0);
+  // rows yb .. yb+R3Y-1; those past n-2 are clamped (computed, not stored)
+  C c[R3Y], zm[R3Y];
+#pragma unroll
+  for (int k = 0; k < R3Y; ++k) {
+    const int64_t col = int64_t(min(yb + k, n - 2)) * ep + x;
+    c[k] = zm[k] = C(0);
     if (!(MODE & SW_ZERO_OLD)) {
-      const T* p = eo + int64_t(z) * epl + col;
-      zp = ld(p + epl);
-      xm = ld(p - 1);
-      xp = ld(p + 1);
-      ym = ld(p - ep);
-      yp = ld(p + ep);
+      zm[k] = ld(eo + int64_t(z0 - 1) * epl + col);
+      c[k] = ld(eo + int64_t(z0) * epl + col);
     }
-    const C v = relax_const<C>(c, ((xm + xp) + (ym + yp)) + (zm + zp), rv, w, hl2, C(6));
-    if (MODE & SW_ACCUM)
-      add_to(u + int64_t(z) * upl + int64_t(y) * up + x, double(v));
-    else
-      st(en + int64_t(z) * epl + col, v);
-    zm = c;
-    c = zp;
+  }
+  const int64_t ylo = int64_t(yb - 1) * ep + x;
+  const int64_t yhi = int64_t(min(yb + R3Y, n - 1)) * ep + x;
+  for (int z = z0; z < z1; ++z) {
+    C zp[R3Y], xm[R3Y], xp[R3Y], rv[R3Y];
+    C below = C(0), above = C(0);
+#pragma unroll
+    for (int k = 0; k < R3Y; ++k) {
+      const int yk = min(yb + k, n - 2);
+      rv[k] = ld(r + int64_t(z) * rpl + int64_t(yk) * rp + x);
+      zp[k] = xm[k] = xp[k] = C(0);
+      if (!(MODE & SW_ZERO_OLD)) {
+        const T* q = eo + int64_t(z) * epl + int64_t(yk) * ep + x;
+        zp[k] = ld(q + epl);
+        xm[k] = ld(q - 1);
+        xp[k] = ld(q + 1);
+      }
+    }
+    if (!(MODE & SW_ZERO_OLD)) {
+      below = ld(eo + int64_t(z) * epl + ylo);
+      above = ld(eo + int64_t(z) * epl + yhi);
+    }
+#pragma unroll
+    for (int k = 0; k < R3Y; ++k) {
+      const C ym = k == 0 ? below : c[k - 1];
+      // the row above is the next owned row, or the group's upper neighbour
+      // (the boundary row, 0, when the group ends at n-2)
+      const C yp = k == R3Y - 1 ? above : (yb + k + 1 <= n - 2 ? c[k + 1] : C(0));
+      const C v = relax_const<C>(c[k], ((xm[k] + xp[k]) + (ym + yp)) + (zm[k] + zp[k]), rv[k], w, hl2, C(6));
+      if (yb + k <= n - 2) {
+        if (MODE & SW_ACCUM)
+          add_to(u + int64_t(z) * upl + int64_t(yb + k) * up + x, double(v));
+        else
+          st(en + int64_t(z) * epl + int64_t(yb + k) * ep + x, v);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R3Y; ++k) {
+      zm[k] = c[k];
+      c[k] = zp[k];
+    }
   }
 }
 
@@ -711,7 +802,7 @@ __global__ __launch_bounds__(256) void k_sweep_3d_coarse(
     if (MODE & SW_ACCUM)
       add_to(u + int64_t(z) * upl + int64_t(y) * up + x, double(v));
     else
-      st(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
+      st_w(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
   }
 }
 
@@ -889,7 +980,7 @@ __global__ __launch_bounds__(256) void k_level_write_2d(
     if (MODE & SW_ACCUM)
       add_to(u + int64_t(y) * up + x, double(v));
     else
-      st(en + int64_t(y) * ep + x, v);
+      st_w(en + int64_t(y) * ep + x, v);
   }
 }
 
@@ -943,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_level_write_3d(
     if (MODE & SW_ACCUM)
       add_to(u + int64_t(z) * upl + int64_t(y) * up + x, double(v));
     else
-      st(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
+      st_w(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
   }
 }
 
@@ -1039,8 +1130,11 @@ static hipError_t residual_t(int d, int n, const double* u, const Lay& ul, const
                 fl.pitch, (const double*)nullptr, int64_t(0), r, rl.pitch, n, len, inv_h2,
                 partials, done);
   }
-  HOMG_LAUNCH((k_residual_3d<T>), g, dim3(BX3, BY3), s, u + ul.off, ul.pitch, ul.plane,
-              f + fl.off, fl.pitch, fl.plane, r, rl.pitch, rl.plane, n, len, inv_h2, partials,
+  const int inner = n - 2, len3 = inner < 8 ? inner : 8;
+  const dim3 g3((inner + BX3 - 1) / BX3, (inner + 4 * BY3 - 1) / (4 * BY3), (inner + len3 - 1) / len3);
+  *count = int(g3.x * g3.y * g3.z);
+  HOMG_LAUNCH((k_residual_3d<T>), g3, dim3(BX3, BY3), s, u + ul.off, ul.pitch, ul.plane,
+              f + fl.off, fl.pitch, fl.plane, r, rl.pitch, rl.plane, n, len3, inv_h2, partials,
               done);
 }
 
@@ -1112,11 +1206,14 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
                   rl.pitch, a, al.pitch, uu, ul.pitch, n, len, w, hl2, done);
     }
     if (m == 0) {
+      // walks of 8 rows, one-dimensional grid in XCD order
+      const int inner = n - 2, len0 = inner < 8 ? inner : 8;
+      const dim3 g1(((inner + BX2 - 1) / BX2) * ((inner + len0 - 1) / len0));
       if (am)
-        HOMG_LAUNCH((k_sweep_2d_l0<T, MODE, true>), g, dim3(BX2), s, eo, en, el.pitch, rm,
-                    rl.pitch, a, al.pitch, uu, ul.pitch, n, len, w, hl2, done);
-      HOMG_LAUNCH((k_sweep_2d_l0<T, MODE, false>), g, dim3(BX2), s, eo, en, el.pitch, rm,
-                  rl.pitch, a, al.pitch, uu, ul.pitch, n, len, w, hl2, done);
+        HOMG_LAUNCH((k_sweep_2d_l0<T, MODE, true>), g1, dim3(BX2), s, eo, en, el.pitch, rm,
+                    rl.pitch, a, al.pitch, uu, ul.pitch, n, len0, w, hl2, done);
+      HOMG_LAUNCH((k_sweep_2d_l0<T, MODE, false>), g1, dim3(BX2), s, eo, en, el.pitch, rm,
+                  rl.pitch, a, al.pitch, uu, ul.pitch, n, len0, w, hl2, done);
     }
     if (am)
       HOMG_LAUNCH((k_sweep_2d_coarse<T, MODE, true>), g, dim3(BX2), s, eo, en, el.pitch, rm,
@@ -1125,12 +1222,15 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
                 rl.pitch, a, al.pitch, uu, ul.pitch, n, len, m, w, hl2, done);
   }
   const C w = C(omega / 6.0);
+  // level 0: lanes own R3Y rows each, walks of 8 planes
+  const int inner = n - 2, len0 = inner < 8 ? inner : 8;
+  const dim3 g0((inner + BX3 - 1) / BX3, (inner + BY3 * R3Y - 1) / (BY3 * R3Y), (inner + len0 - 1) / len0);
   if (m == 0 && compact)
-    HOMG_LAUNCH((k_lattice_sweep_3d<T, MODE>), g, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane,
-                rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done);
+    HOMG_LAUNCH((k_lattice_sweep_3d<T, MODE>), g0, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane,
+                rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len0, w, hl2, done);
   if (m == 0)
-    HOMG_LAUNCH((k_sweep_3d_l0<T, MODE>), g, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane, rm,
-                rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done);
+    HOMG_LAUNCH((k_sweep_3d_l0<T, MODE>), g0, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane, rm,
+                rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len0, w, hl2, done);
   HOMG_LAUNCH((k_sweep_3d_coarse<T, MODE>), g, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane,
               rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, m, w, hl2, done);
 }

@@ -186,6 +186,139 @@ __device__ __forceinline__ float tile_output(const TileLds<C>& L, const float* _
   return y;
 }
 
+// ---------------------------------------------------------------- MFMA contraction
+// The two channel contractions of the inference kernel run on the matrix
+// cores (v_mfma_f32_16x16x32_bf16: a 16 x 32 by 32 x 16 product of BF16
+// operands accumulated in FP32).  The weights are BF16 already; each FP32
+// activation is carried as the sum of three BF16 parts (hi + mid + lo,
+// each the rounded remainder of the previous), so the products cover the
+// activation to about 2^-24 relative and the result matches FP32
+// arithmetic.  Operand layout (one wave): A[i][k] in lane l with
+// i = l % 16, k = 8 (l / 16) + e; B[k][j] with j = l % 16, same k;
+// D[i][j] with j = l % 16, i = 4 (l / 16) + r.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 as_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+
+// v = hi + mid + lo (each BF16, round to nearest even of the remainder).
+__device__ __forceinline__ void split3(float v, __bf16& hi, __bf16& mid, __bf16& lo) {
+  const uint16_t h = to_bf16_bits(v);
+  const float r1 = v - bf16_value(h);
+  const uint16_t m = to_bf16_bits(r1);
+  const float r2 = r1 - bf16_value(m);
+  hi = as_bf16(h);
+  mid = as_bf16(m);
+  lo = as_bf16(to_bf16_bits(r2));
+}
+
+// First layer over the halo-1 region (16 x 16 nodes: row-block jj = one
+// row of 16 nodes; wave w takes rows 4w .. 4w+3).  K index t = 3 tap + ci
+// (27 used of 32).  H = max(P, 0) on interior nodes, 0 elsewhere, stored
+// to L.h[node][c].
+template <typename C>
+__device__ __forceinline__ void mfma_hidden(TileLds<C>& L, const float* __restrict__ w, int nm,
+                                            int J0, int I0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ii = lane & 15, g = lane >> 4;
+  bf16x8 b;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int t = 8 * g + e;
+    const float wv = t < 27 ? w[ii * 27 + (t % 3) * 9 + t / 3] : 0.f;  // B[t][c = ii]
+    b[e] = as_bf16(to_bf16_bits(wv));
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int jj = wave * 4 + rr;
+    bf16x8 ah, am, al;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int t = 8 * g + e;
+      float xv = 0.f;
+      if (t < 27) {
+        const int tap = t / 3, ci = t % 3;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const float4 fv = L.f[(jj + 1 + dy) * R2 + (ii + 1 + dx)];
+        xv = ci == 0 ? fv.x : (ci == 1 ? fv.y : fv.z);
+      }
+      __bf16 h, m, l;
+      split3(xv, h, m, l);
+      ah[e] = h;
+      am[e] = m;
+      al[e] = l;
+    }
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, b, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, d, 0, 0, 0);
+    const int J = J0 - 1 + jj;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int node = 4 * g + r;  // column within the row
+      const int I = I0 - 1 + node;
+      const bool in = J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2;
+      L.h[(jj * R1 + node) * HP + ii] = in ? fmaxf(d[r], 0.f) : 0.f;  // channel c = ii
+    }
+  }
+}
+
+// Second layer as Z[node][tap] = sum_c H[node][c] W2[c][tap] over the same
+// rows (K index t = 16 part + c, parts hi/mid/lo, two MFMAs); Z overwrites
+// the first 9 entries of the node's row of L.h (each wave reads and writes
+// only its own rows).  After a block barrier the output at a node is
+// y = sum_k Z[node + o_k][k].
+template <typename C>
+__device__ __forceinline__ void mfma_output(TileLds<C>& L, const float* __restrict__ w) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ii = lane & 15, g = lane >> 4;
+  bf16x8 b0, b1;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int t0 = 8 * g + e, t1 = 32 + 8 * g + e;  // t < 48 used
+    const int tap = ii;
+    const float w0 = tap < 9 ? w[NW1 + (t0 % 16) * 9 + tap] : 0.f;
+    const float w1 = (tap < 9 && t1 < 48) ? w[NW1 + (t1 % 16) * 9 + tap] : 0.f;
+    b0[e] = as_bf16(to_bf16_bits(w0));
+    b1[e] = as_bf16(to_bf16_bits(w1));
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int jj = wave * 4 + rr;
+    const float* hrow = L.h + (jj * R1 + ii) * HP;  // node ii of row jj
+    bf16x8 a0, a1;
+    // t = 8g + e: part t / 16, channel t % 16 (first MFMA: parts 0, 1; second: part 2, pad)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = (8 * g + e) % 16;
+      __bf16 h, m, l;
+      split3(hrow[c], h, m, l);
+      a0[e] = g < 2 ? h : m;
+      a1[e] = g < 2 ? l : as_bf16(0);
+    }
+    f32x4 d = {0.f, 0.f, 0.f, 0.f};
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, d, 0, 0, 0);
+    if (ii < 9) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) L.h[(jj * R1 + 4 * g + r) * HP + ii] = d[r];  // Z[node][tap = ii]
+    }
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ float mfma_sum_output(const TileLds<C>& L, int o) {
+  const int oj = o / TO, oi = o % TO;
+  float y = 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int dy = k / 3 - 1, dx = k % 3 - 1;
+    y += L.h[((oj + 1 + dy) * R1 + (oi + 1 + dx)) * HP + k];
+  }
+  return y;
+}
+
 // ---------------------------------------------------------------- inference
 // One learned relaxation of every interior node of a compact level lattice:
 // xo = xi + y (or u += xi + y with ACCUM, the last iteration of a cycle).
@@ -237,13 +370,14 @@ __global__ __launch_bounds__(NT) void k_learned_iter(
     else
       stage_features<C, T, T, void>(L, xi, xp, r, rp, nullptr, 0, nm, J0, I0, hl2);
   }
-  float P[HID];
-  (void)stage_hidden<C>(L, w, nm, J0, I0, P);
+  mfma_hidden<C>(L, w, nm, J0, I0);
+  mfma_output<C>(L, w);
+  __syncthreads();
   const int o = threadIdx.x;
   if (o < NOWN) {
     const int J = J0 + o / TO, I = I0 + o % TO;
     if (J <= nm - 2 && I <= nm - 2) {
-      const float y = tile_output<C>(L, w, o);
+      const float y = mfma_sum_output<C>(L, o);
       const C xc = L.x[(o / TO + 3) * R3 + (o % TO + 3)];
       const C v = xc + C(y);
       if constexpr (ACCUM) {

@@ -313,3 +313,42 @@ def test_training_reduces_the_loss(B, torch_cuda):
     # deterministic: the same run gives the same bits
     w2, hist2 = tr.train(dev32(torch, w0), steps=60, batch=8, lr=2e-3, seed=1)
     assert torch.equal(w, w2) and hist == hist2
+
+
+def test_trained_smoother_gains_over_jacobi(B, torch_cuda):
+    """Train on pairs from plain HOMG on 257^2 GRF problems (seeds 100-107),
+    then on held-out problems (seeds 200, 201): the gate accepts the network,
+    its per-cycle contraction is well below Jacobi's, and it reaches 1e-10
+    (residual recomputed by the oracle) in fewer cycles."""
+    torch = torch_cuda
+    n = 257
+    tr = B.Trainer()
+    for seed in range(100, 108):
+        a, f = W.grf_problem(n, seed=seed)
+        s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+        s.set_coefficient(dev64(torch, a))
+        tr.add_problem(s, dev64(torch, f), cycles=2)
+    rng = np.random.default_rng(0)
+    w0 = B.jacobi_weights(0.8) + dev32(torch, 0.02 * rng.standard_normal(LO.NW))
+    w, _ = tr.train(w0, steps=300, batch=8, lr=2e-3, seed=1)
+    for seed in (200, 201):
+        a, f = W.grf_problem(n, seed=seed)
+        s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+        s.set_coefficient(dev64(torch, a))
+        fd = dev64(torch, f)
+        s.set_smoother(B.LEARNED, w)
+        gate = s.smoother_gate([fd], 6)
+        say("held-out %d: rho learned %.3f jacobi %.3f" % (seed, gate["rho_learned"][0], gate["rho_jacobi"][0]))
+        assert gate["accepted"]
+        assert gate["rho_learned"][0] < 0.6 * gate["rho_jacobi"][0]
+        cycles = {}
+        for name, sm in (("jacobi", B.JACOBI), ("learned", B.LEARNED)):
+            s.set_smoother(sm)
+            u = torch.zeros_like(fd)
+            res = s.solve(fd, u, tol=1e-10)
+            _, s2 = O.residual(2, n, f, u.cpu().numpy(), a)
+            assert np.sqrt(s2) / np.sqrt(O.norm2_interior(2, n, f)) <= 1e-10 * (1 + 1e-6) + 1e-14
+            assert not res["smoother_fell_back"]
+            cycles[name] = res["cycles"]
+        say("held-out %d: cycles jacobi %d learned %d" % (seed, cycles["jacobi"], cycles["learned"]))
+        assert cycles["learned"] < cycles["jacobi"]
