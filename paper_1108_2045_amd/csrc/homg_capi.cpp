@@ -41,7 +41,7 @@ namespace {
 
 enum Kind {
   K_NORM = 0, K_RESIDUAL = 1, K_FINALIZE = 2, K_RESTRICT = 3, K_SWEEP = 4,
-  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7, K_LEARNED = 8
+  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7, K_LEARNED = 8, K_TRANSFER = 9
 };
 
 // Event-pair timing of individual launches, harvested at synchronisation.
@@ -87,6 +87,7 @@ struct homg_ctx {
   long long launches = 0;
   Profiler prof;
   // learned relaxation (2D): 0 damped Jacobi, 1 the network with weights w
+  int chain_ready = -1;        // chained path: level whose x_0 the previous level already wrote
   int smoother = 0;
   int active_smoother = 0;     // smoother of the solve in progress (after any fallback)
   double fallback_ratio = 1.0; // per-cycle contraction at which a solve falls back to Jacobi
@@ -214,12 +215,14 @@ homg_status dev_alloc(homg_ctx* h, void** p, size_t bytes) {
 // `it` iterations of level m on the whole-grid state e[*cur] (Sec. 2, fused
 // relax+interpolate task), leaving the result in e[*cur] (or added into acc
 // when `last`).  `first`: the state is e = 0 (first level of a cycle).
-homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last, int* cur,
-                              double* acc, const int* done, hipStream_t s);
+homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last, int next_m,
+                              int* cur, double* acc, const int* done, hipStream_t s);
+homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, void* xprev,
+                         void* xcur, int* cur, double* acc, const int* done, hipStream_t s);
 
-homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cur, double* acc,
-                      const int* done, hipStream_t s) {
-  if (h->active_smoother == 1) return run_level_learned(h, m, it, first, last, cur, acc, done, s);
+homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int next_m, int* cur,
+                      double* acc, const int* done, hipStream_t s) {
+  if (h->active_smoother == 1) return run_level_learned(h, m, it, first, last, next_m, cur, acc, done, s);
   const Lay none;
   const double* am = h->has_coef ? h->a[m] : nullptr;
   const Lay& alm = am ? h->al[m] : none;
@@ -246,14 +249,18 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cu
   void* xprev;
   void* xcur;
   int wmode = last ? SW_ACCUM : 0;
+  // chained path: the previous level already left x_0 in X0
+  const bool chained_in = !first && h->chain_ready == m;
+  h->chain_ready = -1;
   if (lattice_small_lds(h->prec, h->d, nm, am != nullptr) <= h->lds_limit) {
     LAUNCH_K(h, s, K_LATTICE, m, 4 | (first ? 1 : 0),
-             launch_lattice_small(h->prec, h->d, nm, l, it, h->omega, first, h->e[*cur], h->el,
+             launch_lattice_small(h->prec, h->d, nm, chained_in ? 1 : l, it, h->omega, first,
+                                  chained_in ? X0 : h->e[*cur], chained_in ? cl : h->el,
                                   h->r[m], h->rl[m], am, alm, X0, X1, cl, done, s));
     xprev = X0;
     xcur = X1;
   } else {
-    if (!first)
+    if (!first && !chained_in)
       LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X0, cl, done, s));
     void* X[2] = {X0, X1};
     int src = 0;
@@ -268,8 +275,25 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cu
     xprev = X[1 - src];
     if (first && it == 1) wmode |= SW_ZERO_OLD;  // x_0 = 0 was never stored
   }
+  return finish_level(h, m, last, next_m, wmode, xprev, xcur, cur, acc, done, s);
+}
+
+// The end of a blocked coarse level: one whole-grid pass, or -- on the
+// chained path, when the next level is a different coarse level -- only
+// that level's x_0 (the same values the whole-grid pass would leave at its
+// lattice nodes).  Level 0 reads every node, so the pass before it is
+// always whole-grid.
+homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, void* xprev,
+                         void* xcur, int* cur, double* acc, const int* done, hipStream_t s) {
+  if (h->temporal == 2 && !last && next_m >= 1 && next_m != m) {
+    LAUNCH_K(h, s, K_TRANSFER, next_m, wmode & SW_ZERO_OLD,
+             launch_level_transfer(h->prec, h->d, m, xprev, xcur, h->rl[m], next_m, h->xc[2 * next_m],
+                                   h->rl[next_m], (wmode & SW_ZERO_OLD) != 0, done, s));
+    h->chain_ready = next_m;
+    return HOMG_OK;
+  }
   LAUNCH_K(h, s, K_LEVEL_WRITE, m, wmode,
-           launch_level_write(h->prec, h->d, h->n, m, xprev, xcur, cl, h->e[1 - *cur], h->el, acc,
+           launch_level_write(h->prec, h->d, h->n, m, xprev, xcur, h->rl[m], h->e[1 - *cur], h->el, acc,
                               h->dl, wmode, done, s));
   *cur = 1 - *cur;
   return HOMG_OK;
@@ -280,8 +304,8 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int* cu
 // iterations run on the compact lattice and one whole-grid pass writes the
 // level's final state (lattice nodes x_it, every other node the interpolant
 // of x_{it-1}); level 0 is the whole grid.
-homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last, int* cur,
-                              double* acc, const int* done, hipStream_t s) {
+homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last, int next_m,
+                              int* cur, double* acc, const int* done, hipStream_t s) {
   const Lay none;
   const double* am = h->has_coef ? h->a[m] : nullptr;
   const Lay& alm = am ? h->al[m] : none;
@@ -301,7 +325,9 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
   }
   const Lay& cl = h->rl[m];
   void* X[2] = {h->xc[2 * m], h->xc[2 * m + 1]};
-  if (!first)
+  const bool chained_in = !first && h->chain_ready == m;
+  h->chain_ready = -1;
+  if (!first && !chained_in)
     LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X[0], cl, done, s));
   int src = 0;
   for (int t = 1; t <= it; ++t) {
@@ -313,11 +339,7 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
   }
   int wmode = last ? SW_ACCUM : 0;
   if (first && it == 1) wmode |= SW_ZERO_OLD;  // x_0 = 0 was never stored
-  LAUNCH_K(h, s, K_LEVEL_WRITE, m, wmode,
-           launch_level_write(h->prec, h->d, h->n, m, X[1 - src], X[src], cl, h->e[1 - *cur], h->el,
-                              acc, h->dl, wmode, done, s));
-  *cur = 1 - *cur;
-  return HOMG_OK;
+  return finish_level(h, m, last, next_m, wmode, X[1 - src], X[src], cur, acc, done, s);
 }
 
 // Enqueue one MFMG cycle (Sec. 2): restriction pyramid of r_0, the
@@ -331,9 +353,17 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   int cur = 0;
   const Lay none;
   const size_t np = h->sched.size() / 2;
+  h->chain_ready = -1;
   for (size_t p = 0; p < np; ++p) {
     const int m = h->sched[2 * p], it = h->sched[2 * p + 1];
-    if (homg_status e = run_level(h, m, it, p == 0, p + 1 == np, &cur, acc, done, s)) return e;
+    // the next level, if it starts from a compact x_0 (blocked coarse level)
+    int next_m = -1;
+    if (p + 1 < np) {
+      const int mn = h->sched[2 * (p + 1)];
+      const bool next_last = p + 2 == np;
+      if (mn != 0 && (h->active_smoother == 1 || !(next_last && h->prec != PREC_F64))) next_m = mn;
+    }
+    if (homg_status e = run_level(h, m, it, p == 0, p + 1 == np, next_m, &cur, acc, done, s)) return e;
   }
   if (f) {
     int count = 0;
@@ -511,7 +541,8 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   if (max_cycles > 100000) return fail(nullptr, HOMG_ERR_INVALID_ARG, "max_cycles too large");
   if (o.precision < HOMG_FP64 || o.precision > HOMG_BF16_IR)
     return fail(nullptr, HOMG_ERR_INVALID_ARG, "unknown precision");
-  if (o.temporal_block < 0) return fail(nullptr, HOMG_ERR_INVALID_ARG, "temporal_block must be >= 0");
+  if (o.temporal_block < 0 || o.temporal_block > 2)
+    return fail(nullptr, HOMG_ERR_INVALID_ARG, "temporal_block must be 0, 1 or 2");
 
   std::vector<int> sched;
   if (o.schedule) {
@@ -717,7 +748,8 @@ homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* 
   LAUNCH(h, launch_pack(h->prec, h->d, e_old, h->dl, h->e[0], h->el, s));
   LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
   int cur = 0;
-  if (homg_status e = run_level(h, level, iters, false, false, &cur, nullptr, h->zero_flag, s)) return e;
+  h->chain_ready = -1;
+  if (homg_status e = run_level(h, level, iters, false, false, -1, &cur, nullptr, h->zero_flag, s)) return e;
   LAUNCH(h, launch_unpack(h->prec, h->d, h->e[cur], h->el, e_new, h->dl, s));
   // the solver relies on zero boundaries in both e buffers
   const size_t eb = size_t(prec_bytes(h->prec));

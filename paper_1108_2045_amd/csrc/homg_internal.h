@@ -101,6 +101,12 @@ size_t level_write_lds(int prec, int d, int n, int m);
 hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, const void* xcur,
                               const Lay& cl, void* en, const Lay& el, double* u, const Lay& ul,
                               int mode, const int* done, hipStream_t s);
+// Chained path: the state the level-m write would produce, sampled at the
+// interior nodes of the level-mt lattice into that level's compact array
+// (layout tl); zero_old: x_{it-1} = 0.
+hipError_t launch_level_transfer(int prec, int d, int m, const void* xprev, const void* xcur,
+                                 const Lay& cl, int mt, void* dst, const Lay& tl, bool zero_old,
+                                 const int* done, hipStream_t s);
 // ---- batched persistent solver (2D, constant coefficient)
 constexpr int BATCH_MAX_LEVELS = 16;
 struct BatchProblem {         // one problem, read by the persistent kernel

@@ -1038,6 +1038,74 @@ __global__ __launch_bounds__(256) void k_level_write_3d(
   }
 }
 
+// Chained transfer: the whole-grid state a level-m pass would write, but
+// evaluated only at the interior nodes of the level-mt lattice and stored
+// in that level's compact array -- what the next level would gather.  The
+// node formula and its rounding are those of the level write above, so the
+// chained path matches the whole-grid path bit for bit.  Boundary nodes of
+// the target are never written (they stay 0).
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(256) void k_level_transfer_2d(
+    const T* __restrict__ xprev, const T* __restrict__ xcur, int64_t cp, int m,
+    T* __restrict__ dst, int64_t dp, int nt, int mt, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  const int I = 1 + blockIdx.x * 256 + threadIdx.x, J = 1 + blockIdx.y;
+  if (I > nt - 2) return;
+  const int x = I << mt, y = J << mt;
+  const int l = 1 << m, mask = l - 1;
+  const C inv_l = C(1) / C(l);
+  const int xi = x >> m, yj = y >> m;
+  const C tx = C(x & mask) * inv_l;
+  C v;
+  if ((x & mask) == 0 && (y & mask) == 0) {
+    v = ld(xcur + int64_t(yj) * cp + xi);
+  } else {
+    C p00 = C(0), p01 = C(0), p10 = C(0), p11 = C(0);
+    if (!ZERO) {
+      const T* p = xprev + int64_t(yj) * cp + xi;
+      p00 = ld(p);
+      p01 = ld(p + 1);
+      p10 = ld(p + cp);
+      p11 = ld(p + cp + 1);
+    }
+    const C top = lerp(p00, p01, tx), bot = lerp(p10, p11, tx);
+    v = lerp(top, bot, C(y & mask) * inv_l);
+  }
+  st(dst + int64_t(J) * dp + I, v);
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(256) void k_level_transfer_3d(
+    const T* __restrict__ xprev, const T* __restrict__ xcur, int64_t cp, int64_t cpl, int m,
+    T* __restrict__ dst, int64_t dp, int64_t dpl, int nt, int mt, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  const int I = 1 + blockIdx.x * 256 + threadIdx.x, J = 1 + blockIdx.y, K = 1 + blockIdx.z;
+  if (I > nt - 2) return;
+  const int x = I << mt, y = J << mt, z = K << mt;
+  const int l = 1 << m, mask = l - 1;
+  const C inv_l = C(1) / C(l);
+  const int xi = x >> m, yj = y >> m, zk = z >> m;
+  const C tx = C(x & mask) * inv_l, ty = C(y & mask) * inv_l;
+  C v;
+  if ((x & mask) == 0 && (y & mask) == 0 && (z & mask) == 0) {
+    v = ld(xcur + int64_t(zk) * cpl + int64_t(yj) * cp + xi);
+  } else {
+    C t[8] = {C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+    if (!ZERO) {
+      const T* p = xprev + int64_t(zk) * cpl + int64_t(yj) * cp + xi;
+      t[0] = ld(p); t[1] = ld(p + 1); t[2] = ld(p + cp); t[3] = ld(p + cp + 1);
+      const T* q = p + cpl;
+      t[4] = ld(q); t[5] = ld(q + 1); t[6] = ld(q + cp); t[7] = ld(q + cp + 1);
+    }
+    const C top = lerp(lerp(t[0], t[1], tx), lerp(t[2], t[3], tx), ty);
+    const C bot = lerp(lerp(t[4], t[5], tx), lerp(t[6], t[7], tx), ty);
+    v = lerp(top, bot, C(z & mask) * inv_l);
+  }
+  st(dst + int64_t(K) * dpl + int64_t(J) * dp + I, v);
+}
+
 // ------------------------------------------------------------ pack / unpack
 
 template <typename T>
@@ -1385,6 +1453,36 @@ hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double o
     default: SMALL_CASE(bf16);
   }
 #undef SMALL_CASE
+}
+
+template <typename T>
+static hipError_t transfer_t(int d, int m, const void* xprev, const void* xcur, const Lay& cl, int mt,
+                             void* dst, const Lay& tl, bool zero, const int* done, hipStream_t s) {
+  const T* xp = static_cast<const T*>(xprev) + cl.off;
+  const T* xc = static_cast<const T*>(xcur) + cl.off;
+  T* o = static_cast<T*>(dst) + tl.off;
+  const int nt = tl.side;
+  const dim3 g((nt - 2 + 255) / 256, nt - 2, d == 3 ? nt - 2 : 1);
+  if (d == 2) {
+    if (zero) HOMG_LAUNCH((k_level_transfer_2d<T, true>), g, dim3(256), s, xp, xc, cl.pitch, m, o, tl.pitch, nt, mt, done);
+    HOMG_LAUNCH((k_level_transfer_2d<T, false>), g, dim3(256), s, xp, xc, cl.pitch, m, o, tl.pitch, nt, mt, done);
+  }
+  if (zero)
+    HOMG_LAUNCH((k_level_transfer_3d<T, true>), g, dim3(256), s, xp, xc, cl.pitch, cl.plane, m, o, tl.pitch,
+                tl.plane, nt, mt, done);
+  HOMG_LAUNCH((k_level_transfer_3d<T, false>), g, dim3(256), s, xp, xc, cl.pitch, cl.plane, m, o, tl.pitch,
+              tl.plane, nt, mt, done);
+}
+
+hipError_t launch_level_transfer(int prec, int d, int m, const void* xprev, const void* xcur,
+                                 const Lay& cl, int mt, void* dst, const Lay& tl, bool zero_old,
+                                 const int* done, hipStream_t s) {
+  if (tl.side < 3) return hipSuccess;  // no interior node
+  switch (prec) {
+    case PREC_F64: return transfer_t<double>(d, m, xprev, xcur, cl, mt, dst, tl, zero_old, done, s);
+    case PREC_F32: return transfer_t<float>(d, m, xprev, xcur, cl, mt, dst, tl, zero_old, done, s);
+    default: return transfer_t<bf16>(d, m, xprev, xcur, cl, mt, dst, tl, zero_old, done, s);
+  }
 }
 
 size_t level_write_lds(int prec, int d, int n, int m) {

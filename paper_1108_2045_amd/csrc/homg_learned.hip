@@ -74,21 +74,37 @@ constexpr int NOWN = TO * TO;   // 196
 template <typename C>
 __device__ __forceinline__ C hmean(C a, C b) { return C(2) * a * b / (a + b); }
 
-// Shared memory of one tile.  Features as float4 (channel 3 unused).
-template <typename C>
+// Shared memory of one tile.  Features as float4 per node (channel 3
+// unused), or, for the matrix-core kernel (PL), as three channel planes
+// followed by zero words that stand for the padded K entries.
+constexpr int FPL = R2 * R2;     // one feature plane
+constexpr int FZERO = 3 * FPL;   // index of a zero word after the planes
+template <typename C, bool PL = false>
 struct TileLds {
   C x[R3 * R3];
   C a[R3 * R3];
-  float4 f[R2 * R2];
+  typename std::conditional<PL, float[3 * FPL + 4], float4[FPL]>::type f;
   float h[NT * HP];
 };
+
+template <typename C, bool PL>
+__device__ __forceinline__ void put_feature(TileLds<C, PL>& L, int q, float4 v) {
+  if constexpr (PL) {
+    L.f[q] = v.x;
+    L.f[FPL + q] = v.y;
+    L.f[2 * FPL + q] = v.z;
+    if (q < 4) L.f[FZERO + q] = 0.f;
+  } else {
+    L.f[q] = v;
+  }
+}
 
 // Stage x and a on the halo-3 region of the tile whose owned block starts
 // at (J0, I0), then the features on the halo-2 region.  Nodes outside the
 // lattice read x = 0, a = 1; features are 0 off the interior.  XT/RT/AT:
 // storage of x, r_m, a (AT = void: constant coefficient).
-template <typename C, typename XT, typename RT, typename AT>
-__device__ __forceinline__ void stage_features(TileLds<C>& L, const XT* __restrict__ x, int64_t xp,
+template <typename C, bool PL, typename XT, typename RT, typename AT>
+__device__ __forceinline__ void stage_features(TileLds<C, PL>& L, const XT* __restrict__ x, int64_t xp,
                                                const RT* __restrict__ r, int64_t rp,
                                                const AT* __restrict__ a, int64_t ap, int nm,
                                                int J0, int I0, C hl2) {
@@ -124,7 +140,7 @@ __device__ __forceinline__ void stage_features(TileLds<C>& L, const XT* __restri
         v.z = float(rho * (an - as) / (an + as));
       }
     }
-    L.f[q] = v;
+    put_feature(L, q, v);
   }
   __syncthreads();
 }
@@ -189,70 +205,110 @@ __device__ __forceinline__ float tile_output(const TileLds<C>& L, const float* _
 // ---------------------------------------------------------------- MFMA contraction
 // The two channel contractions of the inference kernel run on the matrix
 // cores (v_mfma_f32_16x16x32_bf16: a 16 x 32 by 32 x 16 product of BF16
-// operands accumulated in FP32).  The weights are BF16 already; each FP32
-// activation is carried as the sum of three BF16 parts (hi + mid + lo,
-// each the rounded remainder of the previous), so the products cover the
-// activation to about 2^-24 relative and the result matches FP32
-// arithmetic.  Operand layout (one wave): A[i][k] in lane l with
+// operands accumulated in FP32).  The weights are BF16 values already; each
+// FP32 activation is split exactly into three BF16 parts by truncation
+// (hi = the top 8 significant bits, mid = the next 8 of the remainder,
+// lo = the rest, which fits BF16 exactly: 24 = 3 x 8), so every product is
+// exact and only the FP32 accumulation rounds -- FP32 arithmetic, on the
+// matrix cores.  Operand layout (one wave): A[i][k] in lane l with
 // i = l % 16, k = 8 (l / 16) + e; B[k][j] with j = l % 16, same k;
 // D[i][j] with j = l % 16, i = 4 (l / 16) + r.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ __bf16 as_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
-__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
+struct Split8 {  // eight activations as three BF16 vectors
+  bf16x8 hi, mid, lo;
+};
 
-// v = hi + mid + lo (each BF16, round to nearest even of the remainder).
-__device__ __forceinline__ void split3(float v, __bf16& hi, __bf16& mid, __bf16& lo) {
-  const uint16_t h = to_bf16_bits(v);
-  const float r1 = v - bf16_value(h);
-  const uint16_t m = to_bf16_bits(r1);
-  const float r2 = r1 - bf16_value(m);
-  hi = as_bf16(h);
-  mid = as_bf16(m);
-  lo = as_bf16(to_bf16_bits(r2));
+// Exact three-way split of 8 FP32 values; the BF16 parts are the upper
+// halves of FP32 words whose lower halves are zero.
+__device__ __forceinline__ Split8 split8(const float (&v)[8]) {
+  uint32_t h[8], m[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t u = __float_as_uint(v[e]);
+    h[e] = u & 0xffff0000u;
+    const float r1 = v[e] - __uint_as_float(h[e]);
+    m[e] = __float_as_uint(r1) & 0xffff0000u;
+    l[e] = __float_as_uint(r1 - __uint_as_float(m[e]));
+  }
+  uint32_t ph[4], pm[4], pl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ph[k] = (h[2 * k] >> 16) | (h[2 * k + 1] & 0xffff0000u);
+    pm[k] = (m[2 * k] >> 16) | (m[2 * k + 1] & 0xffff0000u);
+    pl[k] = (l[2 * k] >> 16) | (l[2 * k + 1] & 0xffff0000u);
+  }
+  Split8 r;
+  r.hi = __builtin_bit_cast(bf16x8, ph);
+  r.mid = __builtin_bit_cast(bf16x8, pm);
+  r.lo = __builtin_bit_cast(bf16x8, pl);
+  return r;
+}
+
+// Eight BF16-valued FP32 weights as a BF16 vector (exact).
+__device__ __forceinline__ bf16x8 pack8(const float (&v)[8]) {
+  uint32_t p[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    p[k] = (__float_as_uint(v[2 * k]) >> 16) | (__float_as_uint(v[2 * k + 1]) & 0xffff0000u);
+  return __builtin_bit_cast(bf16x8, p);
 }
 
 // First layer over the halo-1 region (16 x 16 nodes: row-block jj = one
 // row of 16 nodes; wave w takes rows 4w .. 4w+3).  K index t = 3 tap + ci
-// (27 used of 32).  H = max(P, 0) on interior nodes, 0 elsewhere, stored
-// to L.h[node][c].
-template <typename C>
-__device__ __forceinline__ void mfma_hidden(TileLds<C>& L, const float* __restrict__ w, int nm,
-                                            int J0, int I0) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// (27 used of 32; the padding reads a zero word).  H = max(P, 0) on
+// interior nodes, 0 elsewhere, stored to L.h[node][c].
+// The lane's B operands of the two contractions (loaded once per workgroup).
+struct LearnedB {
+  bf16x8 b1, b20, b21;
+};
+
+__device__ __forceinline__ LearnedB learned_b(const float* __restrict__ w) {
+  const int lane = threadIdx.x & 63;
   const int ii = lane & 15, g = lane >> 4;
-  bf16x8 b;
+  float wv[8], w0[8], w1[8];
+  const int c0 = 8 * (g & 1);
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const int t = 8 * g + e;
-    const float wv = t < 27 ? w[ii * 27 + (t % 3) * 9 + t / 3] : 0.f;  // B[t][c = ii]
-    b[e] = as_bf16(to_bf16_bits(wv));
+    const int t = 8 * g + e, tap = t / 3, ci = t % 3;
+    wv[e] = t < 27 ? w[ii * 27 + ci * 9 + tap] : 0.f;  // first layer: B[t][c = ii]
+    const float wt = ii < 9 ? w[NW1 + (c0 + e) * 9 + ii] : 0.f;  // second: B[t][tap = ii]
+    w0[e] = wt;
+    w1[e] = g < 2 ? wt : 0.f;
+  }
+  LearnedB b;
+  b.b1 = pack8(wv);
+  b.b20 = pack8(w0);
+  b.b21 = pack8(w1);
+  return b;
+}
+
+template <typename C>
+__device__ __forceinline__ void mfma_hidden(TileLds<C, true>& L, const bf16x8& b, int nm, int J0,
+                                            int I0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ii = lane & 15, g = lane >> 4;
+  int off[8];
+  bool use[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int t = 8 * g + e, tap = t / 3, ci = t % 3;
+    use[e] = t < 27;
+    off[e] = ci * FPL + (tap / 3 - 1) * R2 + (tap % 3 - 1);
   }
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int jj = wave * 4 + rr;
-    bf16x8 ah, am, al;
+    const int base = (jj + 1) * R2 + (ii + 1);
+    float xv[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int t = 8 * g + e;
-      float xv = 0.f;
-      if (t < 27) {
-        const int tap = t / 3, ci = t % 3;
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const float4 fv = L.f[(jj + 1 + dy) * R2 + (ii + 1 + dx)];
-        xv = ci == 0 ? fv.x : (ci == 1 ? fv.y : fv.z);
-      }
-      __bf16 h, m, l;
-      split3(xv, h, m, l);
-      ah[e] = h;
-      am[e] = m;
-      al[e] = l;
-    }
+    for (int e = 0; e < 8; ++e) xv[e] = L.f[use[e] ? base + off[e] : FZERO];
+    const Split8 a = split8(xv);
     f32x4 d = {0.f, 0.f, 0.f, 0.f};
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, b, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.mid, b, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b, d, 0, 0, 0);
     const int J = J0 - 1 + jj;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -265,41 +321,27 @@ __device__ __forceinline__ void mfma_hidden(TileLds<C>& L, const float* __restri
 }
 
 // Second layer as Z[node][tap] = sum_c H[node][c] W2[c][tap] over the same
-// rows (K index t = 16 part + c, parts hi/mid/lo, two MFMAs); Z overwrites
-// the first 9 entries of the node's row of L.h (each wave reads and writes
-// only its own rows).  After a block barrier the output at a node is
-// y = sum_k Z[node + o_k][k].
+// rows: K index t = 16 part + c (first product: parts hi, mid; second: lo
+// and zero padding).  Z overwrites the first 9 entries of the node's row of
+// L.h (each wave reads and writes only its own rows).  After a block
+// barrier the output at a node is y = sum_k Z[node + o_k][k].
 template <typename C>
-__device__ __forceinline__ void mfma_output(TileLds<C>& L, const float* __restrict__ w) {
+__device__ __forceinline__ void mfma_output(TileLds<C, true>& L, const bf16x8& b0, const bf16x8& b1) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ii = lane & 15, g = lane >> 4;
-  bf16x8 b0, b1;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int t0 = 8 * g + e, t1 = 32 + 8 * g + e;  // t < 48 used
-    const int tap = ii;
-    const float w0 = tap < 9 ? w[NW1 + (t0 % 16) * 9 + tap] : 0.f;
-    const float w1 = (tap < 9 && t1 < 48) ? w[NW1 + (t1 % 16) * 9 + tap] : 0.f;
-    b0[e] = as_bf16(to_bf16_bits(w0));
-    b1[e] = as_bf16(to_bf16_bits(w1));
-  }
+  const int c0 = 8 * (g & 1);  // first of the lane's 8 channels
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int jj = wave * 4 + rr;
-    const float* hrow = L.h + (jj * R1 + ii) * HP;  // node ii of row jj
-    bf16x8 a0, a1;
-    // t = 8g + e: part t / 16, channel t % 16 (first MFMA: parts 0, 1; second: part 2, pad)
+    const float* hrow = L.h + (jj * R1 + ii) * HP + c0;  // node ii of row jj
+    float hv[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = (8 * g + e) % 16;
-      __bf16 h, m, l;
-      split3(hrow[c], h, m, l);
-      a0[e] = g < 2 ? h : m;
-      a1[e] = g < 2 ? l : as_bf16(0);
-    }
+    for (int e = 0; e < 8; ++e) hv[e] = hrow[e];
+    const Split8 a = split8(hv);
+    const bf16x8 zero = {};
     f32x4 d = {0.f, 0.f, 0.f, 0.f};
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g < 2 ? a.hi : a.mid, b0, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g < 2 ? a.lo : zero, b1, d, 0, 0, 0);
     if (ii < 9) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) L.h[(jj * R1 + 4 * g + r) * HP + ii] = d[r];  // Z[node][tap = ii]
@@ -308,7 +350,7 @@ __device__ __forceinline__ void mfma_output(TileLds<C>& L, const float* __restri
 }
 
 template <typename C>
-__device__ __forceinline__ float mfma_sum_output(const TileLds<C>& L, int o) {
+__device__ __forceinline__ float mfma_sum_output(const TileLds<C, true>& L, int o) {
   const int oj = o / TO, oi = o % TO;
   float y = 0.f;
 #pragma unroll
@@ -323,6 +365,41 @@ __device__ __forceinline__ float mfma_sum_output(const TileLds<C>& L, int o) {
 // One learned relaxation of every interior node of a compact level lattice:
 // xo = xi + y (or u += xi + y with ACCUM, the last iteration of a cycle).
 // ZERO: xi = 0 (the first iteration of a cycle; nothing is read from xi).
+//
+// A workgroup walks the tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
+// global inputs of its next tile (x and a on the halo-3 region, r on the
+// halo-2 region: at most two values each per lane) are loaded into
+// registers while the current tile runs its contractions, so the memory
+// latency is hidden behind the matrix-core work.
+template <typename T, bool ZERO, bool VAR>
+struct TileInputs {
+  using C = typename Acc<T>::C;
+  C x[2], a[2], r[2];
+
+  __device__ __forceinline__ void load(const T* __restrict__ xi, int64_t xp, const T* __restrict__ rr,
+                                       int64_t rp, const double* __restrict__ aa, int64_t ap, int nm,
+                                       int J0, int I0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = threadIdx.x + k * NT;
+      x[k] = C(0);
+      a[k] = C(1);
+      r[k] = C(0);
+      if (q < R3 * R3) {
+        const int J = J0 - 3 + q / R3, I = I0 - 3 + q % R3;
+        if (J >= 0 && J < nm && I >= 0 && I < nm) {
+          if constexpr (!ZERO) x[k] = C(ldv(xi + int64_t(J) * xp + I));
+          if constexpr (VAR) a[k] = C(aa[int64_t(J) * ap + I]);
+        }
+      }
+      if (q < R2 * R2) {
+        const int J = J0 - 2 + q / R2, I = I0 - 2 + q % R2;
+        if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) r[k] = C(ldv(rr + int64_t(J) * rp + I));
+      }
+    }
+  }
+};
+
 template <typename T, bool ZERO, bool ACCUM, bool VAR>
 __global__ __launch_bounds__(NT) void k_learned_iter(
     const T* __restrict__ xi, int64_t xp, T* __restrict__ xo, const T* __restrict__ r, int64_t rp,
@@ -330,62 +407,75 @@ __global__ __launch_bounds__(NT) void k_learned_iter(
     typename Acc<T>::C hl2, const float* __restrict__ w, const int* __restrict__ done) {
   using C = typename Acc<T>::C;
   if (*done) return;
-  __shared__ TileLds<C> L;
-  const int J0 = 1 + blockIdx.y * TO, I0 = 1 + blockIdx.x * TO;
-  if constexpr (ZERO) {  // x = 0: stage zeros, features from r (and a) only
-    for (int q = threadIdx.x; q < R3 * R3; q += NT) {
-      const int J = J0 - 3 + q / R3, I = I0 - 3 + q % R3;
-      const bool in = J >= 0 && J < nm && I >= 0 && I < nm;
-      L.x[q] = C(0);
-      if constexpr (VAR) L.a[q] = in ? C(a[int64_t(J) * ap + I]) : C(1);
+  __shared__ TileLds<C, true> L;
+  const int tiles_x = (nm - 2 + TO - 1) / TO, tiles = tiles_x * tiles_x;
+  const LearnedB wb = learned_b(w);
+  TileInputs<T, ZERO, VAR> in;
+  int tile = blockIdx.x;
+  if (tile < tiles) in.load(xi, xp, r, rp, a, ap, nm, 1 + (tile / tiles_x) * TO, 1 + (tile % tiles_x) * TO);
+  for (; tile < tiles; tile += gridDim.x) {
+    const int J0 = 1 + (tile / tiles_x) * TO, I0 = 1 + (tile % tiles_x) * TO;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = threadIdx.x + k * NT;
+      if (q < R3 * R3) {
+        L.x[q] = in.x[k];
+        if constexpr (VAR) L.a[q] = in.a[k];
+      }
     }
     __syncthreads();
-    // features with x = 0
-    for (int q = threadIdx.x; q < R2 * R2; q += NT) {
+    // features on the halo-2 region (0 off the interior), r from registers
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int q = threadIdx.x + k * NT;
+      if (q >= R2 * R2) continue;
       const int jj = q / R2, ii = q % R2;
       const int J = J0 - 2 + jj, I = I0 - 2 + ii;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) {
-        const C rv = C(ldv(r + int64_t(J) * rp + I));
+        const int c3 = (jj + 1) * R3 + (ii + 1);
+        const C xc = L.x[c3];
+        const C xw = L.x[c3 - 1], xe = L.x[c3 + 1], xs = L.x[c3 - R3], xn = L.x[c3 + R3];
+        const C rv = in.r[k];
         if constexpr (!VAR) {
-          v.x = float((hl2 * rv - C(0)) / C(4));
+          const C flux = (((xc - xw) + (xc - xe)) + (xc - xs)) + (xc - xn);
+          v.x = float((hl2 * rv - flux) / C(4));
         } else {
-          const int c3 = (jj + 1) * R3 + (ii + 1);
           const C ac = L.a[c3];
           const C aw = hmean(ac, L.a[c3 - 1]), ae = hmean(ac, L.a[c3 + 1]);
           const C as = hmean(ac, L.a[c3 - R3]), an = hmean(ac, L.a[c3 + R3]);
           const C sa = ((aw + ae) + as) + an;
-          const C rho = (hl2 * rv - C(0)) / sa;
+          const C flux = ((aw * (xc - xw) + ae * (xc - xe)) + as * (xc - xs)) + an * (xc - xn);
+          const C rho = (hl2 * rv - flux) / sa;
           v.x = float(rho);
           v.y = float(rho * (ae - aw) / (ae + aw));
           v.z = float(rho * (an - as) / (an + as));
         }
       }
-      L.f[q] = v;
+      put_feature(L, q, v);
     }
     __syncthreads();
-  } else {
-    if constexpr (VAR)
-      stage_features<C, T, T, double>(L, xi, xp, r, rp, a, ap, nm, J0, I0, hl2);
-    else
-      stage_features<C, T, T, void>(L, xi, xp, r, rp, nullptr, 0, nm, J0, I0, hl2);
-  }
-  mfma_hidden<C>(L, w, nm, J0, I0);
-  mfma_output<C>(L, w);
-  __syncthreads();
-  const int o = threadIdx.x;
-  if (o < NOWN) {
-    const int J = J0 + o / TO, I = I0 + o % TO;
-    if (J <= nm - 2 && I <= nm - 2) {
-      const float y = mfma_sum_output<C>(L, o);
-      const C xc = L.x[(o / TO + 3) * R3 + (o % TO + 3)];
-      const C v = xc + C(y);
-      if constexpr (ACCUM) {
-        u[int64_t(J) * up + I] += double(v);
-      } else {
-        stv(xo + int64_t(J) * xp + I, v);
+    // the next tile's inputs travel while this one computes
+    const int next = tile + gridDim.x;
+    if (next < tiles) in.load(xi, xp, r, rp, a, ap, nm, 1 + (next / tiles_x) * TO, 1 + (next % tiles_x) * TO);
+    mfma_hidden<C>(L, wb.b1, nm, J0, I0);
+    mfma_output<C>(L, wb.b20, wb.b21);
+    __syncthreads();
+    const int o = threadIdx.x;
+    if (o < NOWN) {
+      const int J = J0 + o / TO, I = I0 + o % TO;
+      if (J <= nm - 2 && I <= nm - 2) {
+        const float y = mfma_sum_output<C>(L, o);
+        const C xc = L.x[(o / TO + 3) * R3 + (o % TO + 3)];
+        const C v = xc + C(y);
+        if constexpr (ACCUM) {
+          u[int64_t(J) * up + I] += double(v);
+        } else {
+          stv(xo + int64_t(J) * xp + I, v);
+        }
       }
     }
+    __syncthreads();  // LDS is restaged for the next tile
   }
 }
 
@@ -403,9 +493,9 @@ __global__ __launch_bounds__(NT) void k_train_fwd(const float* __restrict__ x,
   __shared__ TileLds<float> L;
   const int J0 = 1 + blockIdx.y * TO, I0 = 1 + blockIdx.x * TO;
   if constexpr (VAR)
-    stage_features<float, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
+    stage_features<float, false, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
   else
-    stage_features<float, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
+    stage_features<float, false, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
   float P[HID];
   (void)stage_hidden<float>(L, w, nm, J0, I0, P);
   const int o = threadIdx.x;
@@ -444,9 +534,9 @@ __global__ __launch_bounds__(NT) void k_train_bwd(const float* __restrict__ x,
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int J0 = 1 + (tile / tiles_x) * TO, I0 = 1 + (tile % tiles_x) * TO;
     if constexpr (VAR)
-      stage_features<float, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
+      stage_features<float, false, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
     else
-      stage_features<float, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
+      stage_features<float, false, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
     float P[HID];
     (void)stage_hidden<float>(L, w, nm, J0, I0, P);
     for (int q = t; q < R2 * R2; q += NT) {
@@ -698,10 +788,13 @@ static hipError_t learned_t(int nm, double hl, const void* xi, const Lay& xl, vo
   const double* aa = a ? a + al.off : nullptr;
   double* uu = u ? u + ul.off : nullptr;
   const C hl2 = C(hl * hl);
+  // one workgroup per tile up to 1280 (five resident per CU), then they walk
+  const int tx = (nm - 2 + TO - 1) / TO, tiles = tx * tx;
+  const int blocks = tiles < 1280 ? tiles : 1280;
   if (a)
-    LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, true>), tile_grid(nm), dim3(NT), s, x, xl.pitch, y,
+    LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, true>), dim3(blocks), dim3(NT), s, x, xl.pitch, y,
               rr, rl.pitch, aa, al.pitch, uu, ul.pitch, nm, hl2, w, done);
-  LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, false>), tile_grid(nm), dim3(NT), s, x, xl.pitch, y, rr,
+  LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, false>), dim3(blocks), dim3(NT), s, x, xl.pitch, y, rr,
             rl.pitch, aa, al.pitch, uu, ul.pitch, nm, hl2, w, done);
 }
 

@@ -228,6 +228,23 @@ def test_learned_solve_matches_oracle(B, torch_cuda):
     np.testing.assert_allclose(res["history"][:3], ho[:3], rtol=1e-3)
 
 
+def test_learned_chained_path_is_bitwise_identical(B, torch_cuda):
+    torch = torch_cuda
+    n = 257
+    a, f = W.grf_problem(n, seed=9)
+    rng = np.random.default_rng(9)
+    w = dev32(torch, LO.to_bf16(LO.jacobi_weights(0.7) + rng.standard_normal(LO.NW) * 0.01))
+    outs = []
+    for blocked in (1, 2):
+        s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D, temporal_block=blocked)
+        s.set_coefficient(dev64(torch, a))
+        s.set_smoother(B.LEARNED, w)
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        s.solve_cycles(dev64(torch, f), u, 3)
+        outs.append(u.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_fallback_to_jacobi(B, torch_cuda):
     """Weights that make the relaxation diverge: the solve falls back to
     damped Jacobi and still converges."""

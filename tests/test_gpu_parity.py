@@ -176,7 +176,8 @@ def test_step_cycle_fp64(B, torch_cuda, d, n, max_i):
                                            (3, 129, 4, False), (3, 65, 8, False)])
 def test_level_blocked_path_is_bitwise_identical(B, torch_cuda, d, n, max_i, var, prec):
     """The level-blocked path (compact-lattice iterations, one whole-grid pass
-    per level) and the one-launch-per-iteration path give the same bits."""
+    per level), the chained path (the whole grid written only before level 0)
+    and the one-launch-per-iteration path give the same bits."""
     torch = torch_cuda
     if var and prec != "fp64":
         pytest.skip("variable coefficient covered in FP64")
@@ -187,7 +188,7 @@ def test_level_blocked_path_is_bitwise_identical(B, torch_cuda, d, n, max_i, var
         a_np, _ = W.grf_problem(n, seed=17)
         a = dev(torch, a_np)
     outs = []
-    for blocked in (0, 1):
+    for blocked in (0, 1, 2):
         s = B.Solver(d, n, max_i=max_i, precision=prec, temporal_block=blocked,
                      stencil=B.DIFFUSION_5PT_2D if var else None)
         if var:
@@ -196,6 +197,7 @@ def test_level_blocked_path_is_bitwise_identical(B, torch_cuda, d, n, max_i, var
         s.solve_cycles(f, u, 3)
         outs.append(host(u))
     assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
 
 
 def test_schedule_matches_oracle(B, torch_cuda):
@@ -265,6 +267,23 @@ def test_explicit_zigzag_schedule(B, torch_cuda):
     n = 129
     sched = [(6, 2), (5, 2), (6, 1), (5, 2), (4, 2), (3, 2), (4, 1), (3, 2), (2, 2), (1, 2), (0, 2)]
     solve_and_compare(B, torch_cuda, 2, n, W.uniform(2, n, seed=8), schedule=sched)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_chained_path_with_revisits_and_coarse_end(B, torch_cuda, prec):
+    """Chained transfers to coarser, finer and repeated levels, and a schedule
+    that ends on a coarse level, give the bits of the whole-grid path."""
+    torch = torch_cuda
+    n = 129
+    f = dev(torch, W.uniform(2, n, seed=18))
+    sched = [(6, 2), (5, 1), (6, 1), (6, 2), (4, 3), (2, 1), (3, 2), (1, 2), (0, 1), (2, 2)]
+    outs = []
+    for blocked in (1, 2):
+        s = B.Solver(2, n, schedule=sched, precision=prec, temporal_block=blocked)
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        s.solve_cycles(f, u, 2)
+        outs.append(host(u))
+    assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("n", [129, 257])
