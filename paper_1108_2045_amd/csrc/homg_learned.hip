@@ -35,6 +35,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "homg_internal.h"
@@ -74,37 +77,23 @@ constexpr int NOWN = TO * TO;   // 196
 template <typename C>
 __device__ __forceinline__ C hmean(C a, C b) { return C(2) * a * b / (a + b); }
 
-// Shared memory of one tile.  Features as float4 per node (channel 3
-// unused), or, for the matrix-core kernel (PL), as three channel planes
-// followed by zero words that stand for the padded K entries.
+// Shared memory of one tile of the training kernels: features as float4
+// per node (channel 3 unused), hidden layer with padded rows.
 constexpr int FPL = R2 * R2;     // one feature plane
-constexpr int FZERO = 3 * FPL;   // index of a zero word after the planes
-template <typename C, bool PL = false>
+template <typename C>
 struct TileLds {
   C x[R3 * R3];
   C a[R3 * R3];
-  typename std::conditional<PL, float[3 * FPL + 4], float4[FPL]>::type f;
+  float4 f[FPL];
   float h[NT * HP];
 };
-
-template <typename C, bool PL>
-__device__ __forceinline__ void put_feature(TileLds<C, PL>& L, int q, float4 v) {
-  if constexpr (PL) {
-    L.f[q] = v.x;
-    L.f[FPL + q] = v.y;
-    L.f[2 * FPL + q] = v.z;
-    if (q < 4) L.f[FZERO + q] = 0.f;
-  } else {
-    L.f[q] = v;
-  }
-}
 
 // Stage x and a on the halo-3 region of the tile whose owned block starts
 // at (J0, I0), then the features on the halo-2 region.  Nodes outside the
 // lattice read x = 0, a = 1; features are 0 off the interior.  XT/RT/AT:
 // storage of x, r_m, a (AT = void: constant coefficient).
-template <typename C, bool PL, typename XT, typename RT, typename AT>
-__device__ __forceinline__ void stage_features(TileLds<C, PL>& L, const XT* __restrict__ x, int64_t xp,
+template <typename C, typename XT, typename RT, typename AT>
+__device__ __forceinline__ void stage_features(TileLds<C>& L, const XT* __restrict__ x, int64_t xp,
                                                const RT* __restrict__ r, int64_t rp,
                                                const AT* __restrict__ a, int64_t ap, int nm,
                                                int J0, int I0, C hl2) {
@@ -140,7 +129,7 @@ __device__ __forceinline__ void stage_features(TileLds<C, PL>& L, const XT* __re
         v.z = float(rho * (an - as) / (an + as));
       }
     }
-    put_feature(L, q, v);
+    L.f[q] = v;
   }
   __syncthreads();
 }
@@ -202,51 +191,51 @@ __device__ __forceinline__ float tile_output(const TileLds<C>& L, const float* _
   return y;
 }
 
-// ---------------------------------------------------------------- MFMA contraction
-// The two channel contractions of the inference kernel run on the matrix
-// cores (v_mfma_f32_16x16x32_bf16: a 16 x 32 by 32 x 16 product of BF16
-// operands accumulated in FP32).  The weights are BF16 values already; each
-// FP32 activation is split exactly into three BF16 parts by truncation
-// (hi = the top 8 significant bits, mid = the next 8 of the remainder,
-// lo = the rest, which fits BF16 exactly: 24 = 3 x 8), so every product is
-// exact and only the FP32 accumulation rounds -- FP32 arithmetic, on the
-// matrix cores.  Operand layout (one wave): A[i][k] in lane l with
-// i = l % 16, k = 8 (l / 16) + e; B[k][j] with j = l % 16, same k;
-// D[i][j] with j = l % 16, i = 4 (l / 16) + r.
+// ---------------------------------------------------------------- inference
+// One learned relaxation of every interior node of a compact level lattice:
+// xo = xi + y (or u += xi + y with ACCUM, the last iteration of a cycle).
+// ZERO: xi = 0 (the first iteration of a cycle; nothing is read from xi).
+//
+// The two channel contractions run on the matrix cores
+// (v_mfma_f32_16x16x32_bf16: D = A B + D with A 16 x 32, B 32 x 16, BF16
+// operands, FP32 accumulation).  Operand layout (one wave, lane l,
+// g = l / 16): A[i][k] with i = l % 16, k = 8 g + e; B[k][j] with
+// j = l % 16, same k; D[i][j] with j = l % 16, i = 4 g + r.  The weights
+// are BF16 values already; each FP32 activation is split exactly into three
+// BF16 parts (hi = its top 8 significant bits, mid = the next 8 of the
+// remainder, lo = the rest, which fits BF16 exactly since 24 = 3 x 8), so
+// every product is exact and only the FP32 accumulation rounds: FP32
+// arithmetic on the matrix cores.
+//
+// Per 16-node row of the tile's halo-1 region (four rows per wave):
+//   first layer  D1[c][node] = sum_t W1[c][t] F[t][node], t = 3 tap + ci
+//     (27 of 32 K slots; the rest have zero weights), with the features F
+//     read from LDS already split (three MFMAs, one per part);
+//   H = max(D1, 0) on interior nodes, 0 elsewhere -- the lane holds
+//     channels 4g .. 4g+3 of its node, which is exactly the B operand the
+//     second layer needs, so H never leaves registers;
+//   second layer Z[tap][node] = sum_c W2[c][tap] H[c][node] (K slots
+//     8 g + e: hi / mid of channel 4 g + e % 4, then lo of channel 4 g + e
+//     and zeros: two MFMAs), written to LDS;
+// and after a barrier the output at a node is y = sum_k Z[k][node + o_k].
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-struct Split8 {  // eight activations as three BF16 vectors
-  bf16x8 hi, mid, lo;
+struct Parts {  // an FP32 value as three BF16 parts, in the upper halves of FP32 words
+  uint32_t hi, mid, lo;
 };
 
-// Exact three-way split of 8 FP32 values; the BF16 parts are the upper
-// halves of FP32 words whose lower halves are zero.
-__device__ __forceinline__ Split8 split8(const float (&v)[8]) {
-  uint32_t h[8], m[8], l[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t u = __float_as_uint(v[e]);
-    h[e] = u & 0xffff0000u;
-    const float r1 = v[e] - __uint_as_float(h[e]);
-    m[e] = __float_as_uint(r1) & 0xffff0000u;
-    l[e] = __float_as_uint(r1 - __uint_as_float(m[e]));
-  }
-  uint32_t ph[4], pm[4], pl[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    ph[k] = (h[2 * k] >> 16) | (h[2 * k + 1] & 0xffff0000u);
-    pm[k] = (m[2 * k] >> 16) | (m[2 * k + 1] & 0xffff0000u);
-    pl[k] = (l[2 * k] >> 16) | (l[2 * k + 1] & 0xffff0000u);
-  }
-  Split8 r;
-  r.hi = __builtin_bit_cast(bf16x8, ph);
-  r.mid = __builtin_bit_cast(bf16x8, pm);
-  r.lo = __builtin_bit_cast(bf16x8, pl);
-  return r;
+__device__ __forceinline__ Parts split3(float v) {
+  Parts p;
+  p.hi = __float_as_uint(v) & 0xffff0000u;
+  const float r1 = v - __uint_as_float(p.hi);
+  p.mid = __float_as_uint(r1) & 0xffff0000u;
+  p.lo = __float_as_uint(r1 - __uint_as_float(p.mid));
+  return p;
 }
 
-// Eight BF16-valued FP32 weights as a BF16 vector (exact).
+// Eight BF16-valued FP32 numbers as a BF16 vector (exact).
 __device__ __forceinline__ bf16x8 pack8(const float (&v)[8]) {
   uint32_t p[4];
 #pragma unroll
@@ -255,227 +244,235 @@ __device__ __forceinline__ bf16x8 pack8(const float (&v)[8]) {
   return __builtin_bit_cast(bf16x8, p);
 }
 
-// First layer over the halo-1 region (16 x 16 nodes: row-block jj = one
-// row of 16 nodes; wave w takes rows 4w .. 4w+3).  K index t = 3 tap + ci
-// (27 used of 32; the padding reads a zero word).  H = max(P, 0) on
-// interior nodes, 0 elsewhere, stored to L.h[node][c].
-// The lane's B operands of the two contractions (loaded once per workgroup).
-struct LearnedB {
-  bf16x8 b1, b20, b21;
+__device__ __forceinline__ uint32_t pair16(uint32_t lo_word, uint32_t hi_word) {
+  return (lo_word >> 16) | (hi_word & 0xffff0000u);
+}
+
+constexpr int ZS = 12;            // Z row stride in floats (taps 0..8, 16-byte rows)
+constexpr int FPART = 3 * FPL;    // one part of the three feature planes, in u16
+
+template <typename C>
+struct InferLds {
+  float z[NT * ZS];               // Z[node][tap] on the halo-1 region
+  C x[2][R3 * R3];                // x on the halo-3 region, two tiles in flight
+  float a[R3 * R3];               // coefficient on the halo-3 region
+  uint16_t fb[3 * FPART];         // features: part, channel plane, node
 };
 
-__device__ __forceinline__ LearnedB learned_b(const float* __restrict__ w) {
+// The lane's operands that do not change from tile to tile.
+struct LaneConst {
+  bf16x8 w1, w2a, w2b;  // A operands: first layer; second layer, both MFMAs
+  int lb[8];            // feature index of K slot e relative to the row's window
+};
+
+__device__ __forceinline__ LaneConst lane_const(const float* __restrict__ w) {
   const int lane = threadIdx.x & 63;
   const int ii = lane & 15, g = lane >> 4;
-  float wv[8], w0[8], w1[8];
-  const int c0 = 8 * (g & 1);
+  float v1[8], va[8], vb[8];
+  LaneConst k;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int t = 8 * g + e, tap = t / 3, ci = t % 3;
-    wv[e] = t < 27 ? w[ii * 27 + ci * 9 + tap] : 0.f;  // first layer: B[t][c = ii]
-    const float wt = ii < 9 ? w[NW1 + (c0 + e) * 9 + ii] : 0.f;  // second: B[t][tap = ii]
-    w0[e] = wt;
-    w1[e] = g < 2 ? wt : 0.f;
+    v1[e] = t < 27 ? w[ii * 27 + ci * 9 + tap] : 0.f;               // W1[c = ii][ci][tap]
+    const float w2 = ii < 9 ? w[NW1 + (4 * g + (e & 3)) * 9 + ii] : 0.f;  // W2[c][tap = ii]
+    va[e] = w2;
+    vb[e] = e < 4 ? w2 : 0.f;
+    // unused slots read a valid feature (their weights are zero)
+    k.lb[e] = t < 27 ? ii + ci * FPL + (tap / 3) * R2 + (tap % 3) : ii + R2 + 1;
   }
-  LearnedB b;
-  b.b1 = pack8(wv);
-  b.b20 = pack8(w0);
-  b.b21 = pack8(w1);
-  return b;
+  k.w1 = pack8(v1);
+  k.w2a = pack8(va);
+  k.w2b = pack8(vb);
+  return k;
 }
 
-template <typename C>
-__device__ __forceinline__ void mfma_hidden(TileLds<C, true>& L, const bf16x8& b, int nm, int J0,
-                                            int I0) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ii = lane & 15, g = lane >> 4;
-  int off[8];
-  bool use[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int t = 8 * g + e, tap = t / 3, ci = t % 3;
-    use[e] = t < 27;
-    off[e] = ci * FPL + (tap / 3 - 1) * R2 + (tap % 3 - 1);
-  }
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int jj = wave * 4 + rr;
-    const int base = (jj + 1) * R2 + (ii + 1);
-    float xv[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) xv[e] = L.f[use[e] ? base + off[e] : FZERO];
-    const Split8 a = split8(xv);
-    f32x4 d = {0.f, 0.f, 0.f, 0.f};
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.mid, b, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b, d, 0, 0, 0);
-    const int J = J0 - 1 + jj;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int node = 4 * g + r;  // column within the row
-      const int I = I0 - 1 + node;
-      const bool in = J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2;
-      L.h[(jj * R1 + node) * HP + ii] = in ? fmaxf(d[r], 0.f) : 0.f;  // channel c = ii
-    }
-  }
-}
-
-// Second layer as Z[node][tap] = sum_c H[node][c] W2[c][tap] over the same
-// rows: K index t = 16 part + c (first product: parts hi, mid; second: lo
-// and zero padding).  Z overwrites the first 9 entries of the node's row of
-// L.h (each wave reads and writes only its own rows).  After a block
-// barrier the output at a node is y = sum_k Z[node + o_k][k].
-template <typename C>
-__device__ __forceinline__ void mfma_output(TileLds<C, true>& L, const bf16x8& b0, const bf16x8& b1) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ii = lane & 15, g = lane >> 4;
-  const int c0 = 8 * (g & 1);  // first of the lane's 8 channels
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int jj = wave * 4 + rr;
-    const float* hrow = L.h + (jj * R1 + ii) * HP + c0;  // node ii of row jj
-    float hv[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) hv[e] = hrow[e];
-    const Split8 a = split8(hv);
-    const bf16x8 zero = {};
-    f32x4 d = {0.f, 0.f, 0.f, 0.f};
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g < 2 ? a.hi : a.mid, b0, d, 0, 0, 0);
-    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(g < 2 ? a.lo : zero, b1, d, 0, 0, 0);
-    if (ii < 9) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) L.h[(jj * R1 + 4 * g + r) * HP + ii] = d[r];  // Z[node][tap = ii]
-    }
-  }
-}
-
-template <typename C>
-__device__ __forceinline__ float mfma_sum_output(const TileLds<C, true>& L, int o) {
-  const int oj = o / TO, oi = o % TO;
-  float y = 0.f;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const int dy = k / 3 - 1, dx = k % 3 - 1;
-    y += L.h[((oj + 1 + dy) * R1 + (oi + 1 + dx)) * HP + k];
-  }
-  return y;
-}
-
-// ---------------------------------------------------------------- inference
-// One learned relaxation of every interior node of a compact level lattice:
-// xo = xi + y (or u += xi + y with ACCUM, the last iteration of a cycle).
-// ZERO: xi = 0 (the first iteration of a cycle; nothing is read from xi).
-//
-// A workgroup walks the tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the
-// global inputs of its next tile (x and a on the halo-3 region, r on the
-// halo-2 region: at most two values each per lane) are loaded into
-// registers while the current tile runs its contractions, so the memory
-// latency is hidden behind the matrix-core work.
+// Global inputs of one tile held in registers: x and a on the halo-3
+// region, r on the halo-2 region, at most two values each per lane.  They
+// are loaded while the previous tile runs its contractions.
 template <typename T, bool ZERO, bool VAR>
 struct TileInputs {
   using C = typename Acc<T>::C;
-  C x[2], a[2], r[2];
+  C x[2], r[2];
+  double a[2];  // converted when staged, so the load is not waited for here
 
-  __device__ __forceinline__ void load(const T* __restrict__ xi, int64_t xp, const T* __restrict__ rr,
-                                       int64_t rp, const double* __restrict__ aa, int64_t ap, int nm,
-                                       int J0, int I0) {
+  // Offsets are 32-bit: the launcher checks that every array of the call
+  // holds fewer than 2^31 elements.
+  __device__ __forceinline__ void load(const T* __restrict__ xi, int xp, const T* __restrict__ rr, int rp,
+                                       const double* __restrict__ aa, int ap, int nm, int J0, int I0) {
+    // Every lane loads from a clamped (in-bounds) position and then keeps or
+    // drops the value, so the loads carry no branches.
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int q = threadIdx.x + k * NT;
-      x[k] = C(0);
-      a[k] = C(1);
-      r[k] = C(0);
-      if (q < R3 * R3) {
+      {
         const int J = J0 - 3 + q / R3, I = I0 - 3 + q % R3;
-        if (J >= 0 && J < nm && I >= 0 && I < nm) {
-          if constexpr (!ZERO) x[k] = C(ldv(xi + int64_t(J) * xp + I));
-          if constexpr (VAR) a[k] = C(aa[int64_t(J) * ap + I]);
+        const bool in = (k == 0 || q < R3 * R3) && unsigned(J) < unsigned(nm) && unsigned(I) < unsigned(nm);
+        const int o = min(max(J, 0), nm - 1) * xp + min(max(I, 0), nm - 1);
+        if constexpr (!ZERO) {
+          const C v = C(ldv(xi + o));
+          x[k] = in ? v : C(0);
+        } else {
+          x[k] = C(0);
+        }
+        if constexpr (VAR) {
+          const double v = aa[min(max(J, 0), nm - 1) * ap + min(max(I, 0), nm - 1)];
+          a[k] = in ? v : 1.0;
+        } else {
+          a[k] = 1.0;
         }
       }
-      if (q < R2 * R2) {
+      {
         const int J = J0 - 2 + q / R2, I = I0 - 2 + q % R2;
-        if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) r[k] = C(ldv(rr + int64_t(J) * rp + I));
+        const bool in = (k == 0 || q < R2 * R2) && unsigned(J - 1) < unsigned(nm - 2) &&
+                        unsigned(I - 1) < unsigned(nm - 2);
+        const C v = C(ldv(rr + (min(max(J, 1), nm - 2) * rp + min(max(I, 1), nm - 2))));
+        r[k] = in ? v : C(0);
       }
     }
   }
 };
 
+__device__ __forceinline__ float frcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
+// Features at feature node q of the tile (halo-2 region), split and stored.
+// The residual part is formed in the cycle precision C; the coefficient
+// factors (face harmonic means, their sum and the two ratios) in FP32 with
+// the hardware reciprocal -- all of it is rounded to FP32 for the network.
+template <typename C, bool VAR>
+__device__ __forceinline__ void put_features(InferLds<C>& L, const C* X, int q, bool interior, C rv,
+                                             C hl2) {
+  float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+  if (interior) {
+    const int jj = q / R2, ii = q % R2;
+    const int c3 = (jj + 1) * R3 + (ii + 1);
+    const C xc = X[c3];
+    const C dw = xc - X[c3 - 1], de = xc - X[c3 + 1], ds = xc - X[c3 - R3], dn = xc - X[c3 + R3];
+    if constexpr (!VAR) {
+      f0 = float((hl2 * rv - (((dw + de) + ds) + dn)) * C(0.25));
+    } else {
+      const float ac = L.a[c3];
+      const float aw0 = L.a[c3 - 1], ae0 = L.a[c3 + 1], as0 = L.a[c3 - R3], an0 = L.a[c3 + R3];
+      const float aw = 2.f * ac * aw0 * frcp(ac + aw0), ae = 2.f * ac * ae0 * frcp(ac + ae0);
+      const float as = 2.f * ac * as0 * frcp(ac + as0), an = 2.f * ac * an0 * frcp(ac + an0);
+      const float sa = ((aw + ae) + as) + an;
+      const C flux = ((C(aw) * dw + C(ae) * de) + C(as) * ds) + C(an) * dn;
+      f0 = float((hl2 * rv - flux) * C(frcp(sa)));
+      f1 = f0 * ((ae - aw) * frcp(ae + aw));
+      f2 = f0 * ((an - as) * frcp(an + as));
+    }
+  }
+  const Parts p0 = split3(f0), p1 = split3(f1), p2 = split3(f2);
+  uint16_t* fb = L.fb + q;
+  fb[0] = uint16_t(p0.hi >> 16);
+  fb[FPL] = uint16_t(p1.hi >> 16);
+  fb[2 * FPL] = uint16_t(p2.hi >> 16);
+  fb[FPART] = uint16_t(p0.mid >> 16);
+  fb[FPART + FPL] = uint16_t(p1.mid >> 16);
+  fb[FPART + 2 * FPL] = uint16_t(p2.mid >> 16);
+  fb[2 * FPART] = uint16_t(p0.lo >> 16);
+  fb[2 * FPART + FPL] = uint16_t(p1.lo >> 16);
+  fb[2 * FPART + 2 * FPL] = uint16_t(p2.lo >> 16);
+}
+
+// Both layers for row jj of the halo-1 region (row J of the lattice); Z to LDS.
+template <typename C>
+__device__ __forceinline__ void row_contract(InferLds<C>& L, const LaneConst& k, int jj, bool row_in,
+                                             bool col_in) {
+  const int lane = threadIdx.x & 63;
+  const int ii = lane & 15, g = lane >> 4;
+  const uint16_t* fb = L.fb + jj * R2;
+  u16x8 fh, fm, fl;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    fh[e] = fb[k.lb[e]];
+    fm[e] = fb[k.lb[e] + FPART];
+    fl[e] = fb[k.lb[e] + 2 * FPART];
+  }
+  f32x4 d = {0.f, 0.f, 0.f, 0.f};
+  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1, __builtin_bit_cast(bf16x8, fh), d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1, __builtin_bit_cast(bf16x8, fm), d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1, __builtin_bit_cast(bf16x8, fl), d, 0, 0, 0);
+  const bool in = row_in && col_in;
+  Parts h[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) h[r] = split3((in & (d[r] > 0.f)) ? d[r] : 0.f);  // no short circuit: a select
+  const uint32_t ba[4] = {pair16(h[0].hi, h[1].hi), pair16(h[2].hi, h[3].hi), pair16(h[0].mid, h[1].mid),
+                          pair16(h[2].mid, h[3].mid)};
+  const uint32_t bb[4] = {pair16(h[0].lo, h[1].lo), pair16(h[2].lo, h[3].lo), 0u, 0u};
+  f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w2a, __builtin_bit_cast(bf16x8, ba), z, 0, 0, 0);
+  z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w2b, __builtin_bit_cast(bf16x8, bb), z, 0, 0, 0);
+  if (g < 3) *reinterpret_cast<f32x4*>(L.z + (jj * R1 + ii) * ZS + 4 * g) = z;  // taps 4g .. 4g+3
+}
+
 template <typename T, bool ZERO, bool ACCUM, bool VAR>
-__global__ __launch_bounds__(NT) void k_learned_iter(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_iter(
     const T* __restrict__ xi, int64_t xp, T* __restrict__ xo, const T* __restrict__ r, int64_t rp,
     const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up, int nm,
     typename Acc<T>::C hl2, const float* __restrict__ w, const int* __restrict__ done) {
   using C = typename Acc<T>::C;
   if (*done) return;
-  __shared__ TileLds<C, true> L;
+  __shared__ InferLds<C> L;
   const int tiles_x = (nm - 2 + TO - 1) / TO, tiles = tiles_x * tiles_x;
-  const LearnedB wb = learned_b(w);
+  const int t = threadIdx.x, wave = t >> 6, ii = t & 15;
+  const LaneConst kc = lane_const(w);
+  const int xp32 = int(xp), rp32 = int(rp), ap32 = int(ap);
   TileInputs<T, ZERO, VAR> in;
-  int tile = blockIdx.x;
-  if (tile < tiles) in.load(xi, xp, r, rp, a, ap, nm, 1 + (tile / tiles_x) * TO, 1 + (tile % tiles_x) * TO);
-  for (; tile < tiles; tile += gridDim.x) {
+  int tile = blockIdx.x, buf = 0;
+  if (tile < tiles)
+    in.load(xi, xp32, r, rp32, a, ap32, nm, 1 + (tile / tiles_x) * TO, 1 + (tile % tiles_x) * TO);
+  // Barriers per tile: after staging x and a, after the features, after Z.
+  // x is double-buffered, so the next tile may be staged while this one's
+  // outputs still read x; a, the features and Z are rewritten only after a
+  // barrier that follows their last reads.
+  for (; tile < tiles; tile += gridDim.x, buf ^= 1) {
     const int J0 = 1 + (tile / tiles_x) * TO, I0 = 1 + (tile % tiles_x) * TO;
+    C* X = L.x[buf];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int q = threadIdx.x + k * NT;
+      const int q = t + k * NT;
       if (q < R3 * R3) {
-        L.x[q] = in.x[k];
-        if constexpr (VAR) L.a[q] = in.a[k];
+        X[q] = in.x[k];
+        if constexpr (VAR) L.a[q] = float(in.a[k]);
       }
     }
     __syncthreads();
-    // features on the halo-2 region (0 off the interior), r from registers
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const int q = threadIdx.x + k * NT;
-      if (q >= R2 * R2) continue;
-      const int jj = q / R2, ii = q % R2;
-      const int J = J0 - 2 + jj, I = I0 - 2 + ii;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) {
-        const int c3 = (jj + 1) * R3 + (ii + 1);
-        const C xc = L.x[c3];
-        const C xw = L.x[c3 - 1], xe = L.x[c3 + 1], xs = L.x[c3 - R3], xn = L.x[c3 + R3];
-        const C rv = in.r[k];
-        if constexpr (!VAR) {
-          const C flux = (((xc - xw) + (xc - xe)) + (xc - xs)) + (xc - xn);
-          v.x = float((hl2 * rv - flux) / C(4));
-        } else {
-          const C ac = L.a[c3];
-          const C aw = hmean(ac, L.a[c3 - 1]), ae = hmean(ac, L.a[c3 + 1]);
-          const C as = hmean(ac, L.a[c3 - R3]), an = hmean(ac, L.a[c3 + R3]);
-          const C sa = ((aw + ae) + as) + an;
-          const C flux = ((aw * (xc - xw) + ae * (xc - xe)) + as * (xc - xs)) + an * (xc - xn);
-          const C rho = (hl2 * rv - flux) / sa;
-          v.x = float(rho);
-          v.y = float(rho * (ae - aw) / (ae + aw));
-          v.z = float(rho * (an - as) / (an + as));
-        }
+      const int q = t + k * NT;
+      if (q < R2 * R2) {
+        const int J = J0 - 2 + q / R2, I = I0 - 2 + q % R2;
+        put_features<C, VAR>(L, X, q, J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2, in.r[k], hl2);
       }
-      put_feature(L, q, v);
     }
     __syncthreads();
-    // the next tile's inputs travel while this one computes
     const int next = tile + gridDim.x;
-    if (next < tiles) in.load(xi, xp, r, rp, a, ap, nm, 1 + (next / tiles_x) * TO, 1 + (next % tiles_x) * TO);
-    mfma_hidden<C>(L, wb.b1, nm, J0, I0);
-    mfma_output<C>(L, wb.b20, wb.b21);
+    if (next < tiles)
+      in.load(xi, xp32, r, rp32, a, ap32, nm, 1 + (next / tiles_x) * TO, 1 + (next % tiles_x) * TO);
+    const int I = I0 - 1 + ii;
+    const bool col_in = I >= 1 && I <= nm - 2;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int jj = wave * 4 + rr, J = J0 - 1 + jj;
+      row_contract<C>(L, kc, jj, J >= 1 && J <= nm - 2, col_in);
+    }
     __syncthreads();
-    const int o = threadIdx.x;
-    if (o < NOWN) {
-      const int J = J0 + o / TO, I = I0 + o % TO;
+    if (t < NOWN) {
+      const int oj = t / TO, oi = t % TO;
+      const int J = J0 + oj, I = I0 + oi;
       if (J <= nm - 2 && I <= nm - 2) {
-        const float y = mfma_sum_output<C>(L, o);
-        const C xc = L.x[(o / TO + 3) * R3 + (o % TO + 3)];
-        const C v = xc + C(y);
+        float y = 0.f;
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          y += L.z[((oj + k / 3) * R1 + (oi + k % 3)) * ZS + k];
+        const C v = X[(oj + 3) * R3 + (oi + 3)] + C(y);
         if constexpr (ACCUM) {
-          u[int64_t(J) * up + I] += double(v);
+          u[J * int(up) + I] += double(v);
         } else {
-          stv(xo + int64_t(J) * xp + I, v);
+          stv(xo + (J * xp32 + I), v);
         }
       }
     }
-    __syncthreads();  // LDS is restaged for the next tile
   }
 }
 
@@ -493,9 +490,9 @@ __global__ __launch_bounds__(NT) void k_train_fwd(const float* __restrict__ x,
   __shared__ TileLds<float> L;
   const int J0 = 1 + blockIdx.y * TO, I0 = 1 + blockIdx.x * TO;
   if constexpr (VAR)
-    stage_features<float, false, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
+    stage_features<float, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
   else
-    stage_features<float, false, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
+    stage_features<float, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
   float P[HID];
   (void)stage_hidden<float>(L, w, nm, J0, I0, P);
   const int o = threadIdx.x;
@@ -534,9 +531,9 @@ __global__ __launch_bounds__(NT) void k_train_bwd(const float* __restrict__ x,
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int J0 = 1 + (tile / tiles_x) * TO, I0 = 1 + (tile % tiles_x) * TO;
     if constexpr (VAR)
-      stage_features<float, false, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
+      stage_features<float, float, float, float>(L, x, nm, r, nm, a, nm, nm, J0, I0, hl2);
     else
-      stage_features<float, false, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
+      stage_features<float, float, float, void>(L, x, nm, r, nm, nullptr, 0, nm, J0, I0, hl2);
     float P[HID];
     (void)stage_hidden<float>(L, w, nm, J0, I0, P);
     for (int q = t; q < R2 * R2; q += NT) {
@@ -775,6 +772,23 @@ static dim3 tile_grid(int nm) {
   return dim3(t, t);
 }
 
+// Workgroups of NT lanes the device holds at once for kernel k (asked once).
+static int resident_blocks(const void* k) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(k);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, NT, 0) != hipSuccess || per < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 1024;
+  }
+  return cache[k] = per * cus;
+}
+
 template <typename T, bool ZERO, bool ACCUM>
 static hipError_t learned_t(int nm, double hl, const void* xi, const Lay& xl, void* xo,
                             const void* r, const Lay& rl, const double* a, const Lay& al,
@@ -788,14 +802,23 @@ static hipError_t learned_t(int nm, double hl, const void* xi, const Lay& xl, vo
   const double* aa = a ? a + al.off : nullptr;
   double* uu = u ? u + ul.off : nullptr;
   const C hl2 = C(hl * hl);
-  // one workgroup per tile up to 1280 (five resident per CU), then they walk
+  // 32-bit element offsets inside the kernel
+  const int64_t lim = int64_t(1) << 31;
+  if ((x && xl.pitch * nm >= lim) || rl.pitch * nm >= lim || (aa && al.pitch * nm >= lim) ||
+      (uu && ul.pitch * nm >= lim))
+    return hipErrorInvalidValue;
+  // one workgroup per tile up to the resident count, then they walk
   const int tx = (nm - 2 + TO - 1) / TO, tiles = tx * tx;
-  const int blocks = tiles < 1280 ? tiles : 1280;
-  if (a)
-    LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, true>), dim3(blocks), dim3(NT), s, x, xl.pitch, y,
-              rr, rl.pitch, aa, al.pitch, uu, ul.pitch, nm, hl2, w, done);
-  LL_LAUNCH((k_learned_iter<S, ZERO, ACCUM, false>), dim3(blocks), dim3(NT), s, x, xl.pitch, y, rr,
-            rl.pitch, aa, al.pitch, uu, ul.pitch, nm, hl2, w, done);
+  if (a) {
+    auto k = k_learned_iter<S, ZERO, ACCUM, true>;
+    const int b = std::min(tiles, resident_blocks(reinterpret_cast<const void*>(k)));
+    LL_LAUNCH(k, dim3(b), dim3(NT), s, x, xl.pitch, y, rr, rl.pitch, aa, al.pitch, uu, ul.pitch, nm,
+              hl2, w, done);
+  }
+  auto k = k_learned_iter<S, ZERO, ACCUM, false>;
+  const int b = std::min(tiles, resident_blocks(reinterpret_cast<const void*>(k)));
+  LL_LAUNCH(k, dim3(b), dim3(NT), s, x, xl.pitch, y, rr, rl.pitch, aa, al.pitch, uu, ul.pitch, nm,
+            hl2, w, done);
 }
 
 template <typename T>
