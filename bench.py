@@ -68,6 +68,8 @@ def kernel_symbol(d, kind, level, mode):
         return "k_level_write_%dd<double, %d>" % (d, mode)
     if kind == "residual":
         return "k_residual_%dd<double%s>" % (d, var2)
+    if kind == "transfer":
+        return "k_level_transfer_%dd<double, %s>" % (d, "true" if mode & 1 else "false")
     return {"restrict": "k_restrict_%dd<double>" % d, "norm": "k_norm2_%dd" % d,
             "finalize": "k_finalize", "gather": "k_gather<double>"}[kind]
 

@@ -79,7 +79,11 @@ typedef struct homg_options {
     int precision;         /* homg_precision */
     int temporal_block;    /* 1 (default): level-blocked -- the iterations of a coarse level run on
                               its compact lattice and the whole grid is written once per level;
-                              0: one whole-grid launch per iteration.  Same results bit for bit. */
+                              0: one whole-grid launch per iteration;
+                              2: chained -- as 1, but a coarse level followed by another coarse
+                              level hands over only that level's lattice values, and the whole
+                              grid is written only before level 0 or the last level.
+                              All three give the same results bit for bit. */
     int reserved[7];       /* must be 0 */
 } homg_options;
 
@@ -187,7 +191,8 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   `level` to level+1, 4 whole-grid iteration at `level`, 5 sampling of the
  *   grid on the level lattice, 6 iterations on the compact lattice, 7
  *   whole-grid pass of a blocked level, 8 learned relaxation of the level
- *   lattice (level 0: of the whole grid).
+ *   lattice (level 0: of the whole grid), 9 hand-over of a finished coarse
+ *   level to the lattice of `level` (chained execution).
  *   mode (kinds 4, 6, 7): bit 0 = starts from e = 0, bit 1 = adds into u;
  *   bit 2 (kind 6) = the whole lattice held by one workgroup.
  * homg_get_profile synchronises outstanding events, then writes up to cap
