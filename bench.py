@@ -43,7 +43,8 @@ def sweep_bytes(d, n, level, mode, elem=8):
     iterate at the level-m lattice and of the level-m residual (each 1/l^d of
     N).  Level 0 reads e_old and r at every node.  The first iteration of a
     cycle does not read e_old; the last adds into u (read + write of FP64 u
-    instead of the store of e)."""
+    instead of the store of e).  A pass of several level-0 iterations
+    (mode bit 3) moves the same bytes once."""
     N = float(n) ** d
     l = 1 << level
     lat = N / float(l) ** d
@@ -57,6 +58,9 @@ def kernel_symbol(d, kind, level, mode):
     """The kernel's name as the profiler prints it (without the namespace and
     argument list), so the bench line and the rocprofv3 summary can be matched."""
     var2 = ", false" if d == 2 else ""
+    if kind == "sweep" and mode & 8:  # several level-0 iterations in one pass
+        return "k_sweep_2d_l0_tb<double, %s, %s, %d>" % (
+            "true" if mode & 1 else "false", "true" if mode & 2 else "false", ((mode >> 4) & 3) + 1)
     if kind == "sweep":
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
         return "%s<double, %d%s>" % (base, mode, var2)

@@ -193,8 +193,10 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   whole-grid pass of a blocked level, 8 learned relaxation of the level
  *   lattice (level 0: of the whole grid), 9 hand-over of a finished coarse
  *   level to the lattice of `level` (chained execution).
- *   mode (kinds 4, 6, 7): bit 0 = starts from e = 0, bit 1 = adds into u;
- *   bit 2 (kind 6) = the whole lattice held by one workgroup.
+ *   mode (kinds 4, 6, 7, 8): bit 0 = starts from e = 0, bit 1 = adds into u;
+ *   bit 2 (kinds 6, 8) = every iteration of the level in one workgroup that
+ *   holds the whole lattice; bit 3 (kind 4) = several level-0 iterations in
+ *   one temporally blocked pass, bits 4-5 their number minus one.
  * homg_get_profile synchronises outstanding events, then writes up to cap
  * entries and their count in *len.
  */

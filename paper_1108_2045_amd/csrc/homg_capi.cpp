@@ -229,6 +229,20 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
   // One launch per iteration: level 0 always (every node is a lattice
   // node), every level when blocking is off, and a coarse last level in
   // reduced precision (its iterate goes into u unrounded).
+  if (m == 0 && h->d == 2 && !am && h->temporal) {
+    // level 0 of a 2D constant-coefficient grid: up to TB_MAX_IT iterations
+    // per pass (temporally blocked), the same iterates bit for bit
+    for (int t0 = 0; t0 < it; t0 += TB_MAX_IT) {
+      const int g = std::min(TB_MAX_IT, it - t0);
+      const bool zero = first && t0 == 0, accum = last && t0 + g == it;
+      const int mode = SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | (accum ? SW_ACCUM : 0) | ((g - 1) << 4);
+      LAUNCH_K(h, s, K_SWEEP, 0, mode,
+               launch_sweep_2d_l0_tb(h->prec, h->n, g, h->omega, h->e[*cur], h->e[1 - *cur], h->el,
+                                     h->r[0], h->rl[0], acc, h->dl, zero, accum, done, s));
+      *cur = 1 - *cur;
+    }
+    return HOMG_OK;
+  }
   if (m == 0 || !h->temporal || (last && h->prec != PREC_F64)) {
     for (int t = 0; t < it; ++t) {
       int mode = 0;
@@ -327,6 +341,13 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
   void* X[2] = {h->xc[2 * m], h->xc[2 * m + 1]};
   const bool chained_in = !first && h->chain_ready == m;
   h->chain_ready = -1;
+  if (nm <= LEARNED_SMALL_NM) {  // one workgroup, every iteration, x_0 read in place
+    LAUNCH_K(h, s, K_LEARNED, m, 4 | (first ? 1 : 0),
+             launch_learned_small(h->prec, nm, chained_in ? 1 : l, it, hl, first,
+                                  chained_in ? X[0] : h->e[*cur], chained_in ? cl : h->el, h->r[m],
+                                  h->rl[m], am, alm, X[0], X[1], cl, h->w32, done, s));
+    return finish_level(h, m, last, next_m, last ? SW_ACCUM : 0, X[0], X[1], cur, acc, done, s);
+  }
   if (!first && !chained_in)
     LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X[0], cl, done, s));
   int src = 0;

@@ -37,7 +37,7 @@ struct DevState {
   double tol;
 };
 
-enum SweepMode { SW_ZERO_OLD = 1, SW_ACCUM = 2 };
+enum SweepMode { SW_ZERO_OLD = 1, SW_ACCUM = 2, SW_TBLOCK = 8 };
 
 // Upper bound on the number of per-block partial sums written by the norm /
 // residual launches for a grid of side n.
@@ -67,6 +67,13 @@ hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void*
 // with SW_ACCUM the iterate is added to u (FP64, layout ul) instead of
 // being stored in en.  compact: a level-0 iteration on the compact lattice
 // of a coarse level (same arithmetic, a kernel symbol of its own).
+// Level 0 of a 2D constant-coefficient grid: `it` (<= TB_MAX_IT) iterations
+// in one pass (temporal blocking), equal bit for bit to `it` launch_sweep
+// calls; reads e (unless zero) and r once, writes en or adds into u once.
+constexpr int TB_MAX_IT = 4;
+hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
+                                 const Lay& el, const void* rm, const Lay& rl, double* u,
+                                 const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s);
 hipError_t launch_sweep(int prec, int d, int n, int m, double omega, const void* eo, void* en,
                         const Lay& el, const void* rm, const Lay& rl, const double* am,
                         const Lay& al, double* u, const Lay& ul, int mode, const int* done,
@@ -159,6 +166,14 @@ constexpr int ENERGY_MAX_PARTS = 1024;  // workgroups of one energy launch
 // al for the FP64 nodal coefficient a (null: constant coefficient); mode
 // SW_ZERO_OLD (xi = 0, not read) / SW_ACCUM (u += xi + y instead of the store).
 // w: the 576 weights as FP32 values.
+// Lattices of side <= LEARNED_SMALL_NM: all `it` learned relaxations in one
+// workgroup (x_0 from e with stride l, or 0 when zero); writes x_{it-1} to
+// xprev and x_it to xcur.
+constexpr int LEARNED_SMALL_NM = 16;
+hipError_t launch_learned_small(int prec, int nm, int l, int it, double hl, bool zero, const void* e,
+                                const Lay& el, const void* r, const Lay& rl, const double* a,
+                                const Lay& al, void* xprev, void* xcur, const Lay& cl,
+                                const float* w, const int* done, hipStream_t s);
 hipError_t launch_learned_iter(int prec, int nm, double hl, const void* xi, const Lay& xl,
                                void* xo, const void* r, const Lay& rl, const double* a,
                                const Lay& al, double* u, const Lay& ul, const float* w, int mode,

@@ -565,6 +565,97 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
   tile_sweep_2d_l0<T, MODE, VAR>(eo, en, ep, r, rp, a, ap, u, up, n, len, w, hl2, int(lg % gx), int(lg / gx));
 }
 
+// Level 0, IT <= 4 iterations in one pass (temporal blocking).  Each wave
+// owns 64 consecutive columns and walks a band of TB_LEN rows; the
+// iterations form a pipeline down the band: iteration t is computed t rows
+// behind the row just loaded, from a three-row window of iteration t-1 in
+// registers (the y neighbours) and the neighbour lanes' values (the x
+// neighbours, by cross-lane shuffles).  A lane's value after t iterations is
+// only right if both neighbours' values after t-1 were, so the valid lanes
+// shrink by one per iteration at each wave edge: a wave emits its inner
+// 64 - 2 IT columns and waves overlap by 2 IT columns; the band is entered
+// IT rows early and left IT rows late for the same reason.  Every
+// intermediate iterate is rounded as a store would round it, and the last
+// one goes to memory exactly as the single-iteration kernel sends it, so
+// the result equals IT single sweeps bit for bit while e and r are read
+// once and the result written (or added into u) once.
+constexpr int TB_LEN = 64;  // emitted rows per wave
+
+template <typename T, bool ZERO, bool ACCUM, int IT, int U>
+__device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict__ en, int64_t ep,
+                                         const T* __restrict__ r, int64_t rp, double* __restrict__ u,
+                                         int64_t up, int n, int x, int xc, bool xin, bool emit, int Y0,
+                                         int Y1, int ys, typename Tr<T>::C w, typename Tr<T>::C hl2,
+                                         typename Tr<T>::C (&win)[IT][3], typename Tr<T>::C (&rw)[IT + 1]) {
+  using C = typename Tr<T>::C;
+  C xl[U], rl[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {  // rows past the grid read the boundary row (zero)
+    xl[k] = ZERO ? C(0) : ld(eo + int64_t(min(ys + k, n - 1)) * ep + xc);
+    rl[k] = ld(r + int64_t(min(max(ys + k - 1, 0), n - 1)) * rp + xc);
+  }
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const int y0 = ys + k;
+    win[0][0] = win[0][1];
+    win[0][1] = win[0][2];
+    win[0][2] = xl[k];
+#pragma unroll
+    for (int t = IT; t > 1; --t) rw[t] = rw[t - 1];
+    rw[1] = rl[k];
+#pragma unroll
+    for (int t = 1; t <= IT; ++t) {
+      const int y = y0 - t;
+      const C c = win[t - 1][1];
+      const C xm = __shfl_up(c, 1), xp = __shfl_down(c, 1);
+      const bool in = xin && y >= 1 && y <= n - 2;
+      C v = relax_const<C>(c, (xm + xp) + (win[t - 1][0] + win[t - 1][2]), rw[t], w, hl2, C(4));
+      if (t < IT) {
+        win[t][0] = win[t][1];
+        win[t][1] = win[t][2];
+        win[t][2] = in ? rnd<T>(v) : C(0);
+      } else if (emit && in && y >= Y0 && y < Y1) {
+        if (ACCUM)
+          add_to(u + int64_t(y) * up + x, double(v));
+        else
+          st(en + int64_t(y) * ep + x, v);
+      }
+    }
+  }
+}
+
+template <typename T, bool ZERO, bool ACCUM, int IT>
+__global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
+    const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r, int64_t rp,
+    double* __restrict__ u, int64_t up, int n, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  constexpr int VALID = 64 - 2 * IT;
+  const int lane = threadIdx.x & 63;
+  const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + TB_LEN - 1) / TB_LEN;
+  // XCD order: the waves of one XCD are neighbours (their overlapping
+  // columns and rows meet in that XCD's L2)
+  const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
+  if (wv >= gx * gy) return;  // the whole wave
+  const int x = 1 + (wv % gx) * VALID - IT + lane;
+  const int Y0 = 1 + (wv / gx) * TB_LEN, Y1 = min(n - 1, Y0 + TB_LEN);
+  const bool xin = x >= 1 && x <= n - 2;
+  const bool emit = lane >= IT && lane < 64 - IT;
+  const int xc = min(max(x, 0), n - 1);  // columns off the grid read the boundary (zero)
+  C win[IT][3], rw[IT + 1];
+#pragma unroll
+  for (int t = 0; t < IT; ++t) win[t][0] = win[t][1] = win[t][2] = C(0);
+#pragma unroll
+  for (int t = 0; t <= IT; ++t) rw[t] = C(0);
+  int ys = max(Y0 - IT, 0);
+  const int ye = Y1 + IT;  // one past the last row loaded
+  for (; ys + 4 <= ye; ys += 4)
+    tb_steps<T, ZERO, ACCUM, IT, 4>(eo, en, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w, hl2, win, rw);
+  for (; ys < ye; ++ys)
+    tb_steps<T, ZERO, ACCUM, IT, 1>(eo, en, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w, hl2, win, rw);
+}
+
 // Levels m >= 1: lattice nodes relax, the rest interpolate.  The lane keeps
 // the four corners of its current level-m cell; they change every l rows.
 template <typename T, int MODE, bool VAR>
@@ -1301,6 +1392,50 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
                 rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len0, w, hl2, done);
   HOMG_LAUNCH((k_sweep_3d_coarse<T, MODE>), g, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane,
               rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, m, w, hl2, done);
+}
+
+template <typename T, bool ZERO, bool ACCUM>
+static hipError_t tb_t(int n, int it, double omega, const void* eo_, void* en_, const Lay& el,
+                       const void* rm_, const Lay& rl, double* u, const Lay& ul, const int* done,
+                       hipStream_t s) {
+  using C = typename Tr<T>::C;
+  const T* eo = eo_ ? static_cast<const T*>(eo_) + el.off : nullptr;
+  T* en = en_ ? static_cast<T*>(en_) + el.off : nullptr;
+  const T* rm = static_cast<const T*>(rm_) + rl.off;
+  double* uu = u ? u + ul.off : nullptr;
+  const double h = 1.0 / double(n - 1);
+  const C w = C(omega / 4.0), hl2 = C(h * h);
+  const int valid = 64 - 2 * it;
+  const int waves = ((n - 2 + valid - 1) / valid) * ((n - 2 + TB_LEN - 1) / TB_LEN);
+  const dim3 g((waves + 3) / 4);
+  switch (it) {
+    case 1: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 1>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
+    case 2: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 2>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
+    case 3: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 3>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
+    default: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 4>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
+  }
+}
+
+template <typename T>
+static hipError_t tb_tz(int n, int it, double omega, const void* eo, void* en, const Lay& el,
+                        const void* rm, const Lay& rl, double* u, const Lay& ul, bool zero, bool accum,
+                        const int* done, hipStream_t s) {
+  if (zero)
+    return accum ? tb_t<T, true, true>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s)
+                 : tb_t<T, true, false>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s);
+  return accum ? tb_t<T, false, true>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s)
+               : tb_t<T, false, false>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s);
+}
+
+hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
+                                 const Lay& el, const void* rm, const Lay& rl, double* u,
+                                 const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s) {
+  if (n < 3 || it < 1 || it > TB_MAX_IT) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return tb_tz<double>(n, it, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+    case PREC_F32: return tb_tz<float>(n, it, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+    default: return tb_tz<bf16>(n, it, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+  }
 }
 
 template <typename T>

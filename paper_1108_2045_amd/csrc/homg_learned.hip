@@ -62,6 +62,12 @@ __device__ __forceinline__ uint16_t to_bf16_bits(float f) {
 __device__ __forceinline__ void stv(double* p, double v) { *p = v; }
 __device__ __forceinline__ void stv(float* p, float v) { *p = v; }
 __device__ __forceinline__ void stv(bf16s* p, float v) { p->bits = to_bf16_bits(v); }
+// v as it reads back after a store to T.
+template <typename T, typename C>
+__device__ __forceinline__ C stored(C v) {
+  if constexpr (std::is_same<T, bf16s>::value) return __uint_as_float(uint32_t(to_bf16_bits(v)) << 16);
+  else return v;
+}
 
 template <typename T> struct Acc { using C = float; };
 template <> struct Acc<double> { using C = double; };
@@ -73,6 +79,7 @@ constexpr int R1 = TO + 2;      // hidden layer (halo 1): 16 x 16 = one node per
 constexpr int NT = R1 * R1;     // 256 lanes
 constexpr int HP = HID + 4;     // padded hidden stride in floats (16-byte aligned)
 constexpr int NOWN = TO * TO;   // 196
+static_assert(LEARNED_SMALL_NM == TO + 2, "one tile covers the interior of the small lattices");
 
 template <typename C>
 __device__ __forceinline__ C hmean(C a, C b) { return C(2) * a * b / (a + b); }
@@ -405,6 +412,41 @@ __device__ __forceinline__ void row_contract(InferLds<C>& L, const LaneConst& k,
   if (g < 3) *reinterpret_cast<f32x4*>(L.z + (jj * R1 + ii) * ZS + 4 * g) = z;  // taps 4g .. 4g+3
 }
 
+// The three stages of one tile (owned block at (J0, I0)): features from
+// x and a in LDS (r of the lane's two halo-2 slots in registers), both
+// contractions into Z, and the output sum at owned node (oj, oi).
+template <typename C, bool VAR>
+__device__ __forceinline__ void tile_features(InferLds<C>& L, const C* X, int nm, int J0, int I0,
+                                              const C (&rv)[2], C hl2) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int q = threadIdx.x + k * NT;
+    if (q < R2 * R2) {
+      const int J = J0 - 2 + q / R2, I = I0 - 2 + q % R2;
+      put_features<C, VAR>(L, X, q, J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2, rv[k], hl2);
+    }
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ void tile_contract(InferLds<C>& L, const LaneConst& kc, int nm, int J0, int I0) {
+  const int wave = threadIdx.x >> 6, I = I0 - 1 + (threadIdx.x & 15);
+  const bool col_in = I >= 1 && I <= nm - 2;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int jj = wave * 4 + rr, J = J0 - 1 + jj;
+    row_contract<C>(L, kc, jj, J >= 1 && J <= nm - 2, col_in);
+  }
+}
+
+template <typename C>
+__device__ __forceinline__ float tile_y(const InferLds<C>& L, int oj, int oi) {
+  float y = 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) y += L.z[((oj + k / 3) * R1 + (oi + k % 3)) * ZS + k];
+  return y;
+}
+
 template <typename T, bool ZERO, bool ACCUM, bool VAR>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_iter(
     const T* __restrict__ xi, int64_t xp, T* __restrict__ xo, const T* __restrict__ r, int64_t rp,
@@ -414,7 +456,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   if (*done) return;
   __shared__ InferLds<C> L;
   const int tiles_x = (nm - 2 + TO - 1) / TO, tiles = tiles_x * tiles_x;
-  const int t = threadIdx.x, wave = t >> 6, ii = t & 15;
+  const int t = threadIdx.x;
   const LaneConst kc = lane_const(w);
   const int xp32 = int(xp), rp32 = int(rp), ap32 = int(ap);
   TileInputs<T, ZERO, VAR> in;
@@ -437,35 +479,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int q = t + k * NT;
-      if (q < R2 * R2) {
-        const int J = J0 - 2 + q / R2, I = I0 - 2 + q % R2;
-        put_features<C, VAR>(L, X, q, J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2, in.r[k], hl2);
-      }
-    }
+    tile_features<C, VAR>(L, X, nm, J0, I0, in.r, hl2);
     __syncthreads();
     const int next = tile + gridDim.x;
     if (next < tiles)
       in.load(xi, xp32, r, rp32, a, ap32, nm, 1 + (next / tiles_x) * TO, 1 + (next % tiles_x) * TO);
-    const int I = I0 - 1 + ii;
-    const bool col_in = I >= 1 && I <= nm - 2;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int jj = wave * 4 + rr, J = J0 - 1 + jj;
-      row_contract<C>(L, kc, jj, J >= 1 && J <= nm - 2, col_in);
-    }
+    tile_contract<C>(L, kc, nm, J0, I0);
     __syncthreads();
     if (t < NOWN) {
       const int oj = t / TO, oi = t % TO;
       const int J = J0 + oj, I = I0 + oi;
       if (J <= nm - 2 && I <= nm - 2) {
-        float y = 0.f;
-#pragma unroll
-        for (int k = 0; k < 9; ++k)
-          y += L.z[((oj + k / 3) * R1 + (oi + k % 3)) * ZS + k];
-        const C v = X[(oj + 3) * R3 + (oi + 3)] + C(y);
+        const C v = X[(oj + 3) * R3 + (oi + 3)] + C(tile_y(L, oj, oi));
         if constexpr (ACCUM) {
           u[J * int(up) + I] += double(v);
         } else {
@@ -473,6 +498,69 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
       }
     }
+  }
+}
+
+// All `it` learned relaxations of a lattice with at most TO interior nodes
+// per side (one tile) in one workgroup, the iterates ping-ponging in LDS.
+// x_0 is read from e with stride l (the whole grid) or from the compact
+// array (l = 1, chained hand-over; e may then alias xprev), or is 0 (ZERO).
+// Writes x_{it-1} to xprev and x_it to xcur on the whole lattice.
+template <typename T, bool ZERO, bool VAR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_learned_small(
+    const T* e, int64_t ep, int l, const T* __restrict__ r, int64_t rp,
+    const double* __restrict__ a, int64_t ap, T* xprev, T* xcur, int64_t cp, int nm, int it,
+    typename Acc<T>::C hl2, const float* __restrict__ w, const int* __restrict__ done) {
+  using C = typename Acc<T>::C;
+  if (*done) return;
+  __shared__ InferLds<C> L;
+  const int t = threadIdx.x;
+  const LaneConst kc = lane_const(w);
+  // the tile's halo-3 region starts at lattice (-2, -2)
+  C rv[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int q = t + k * NT;
+    if (q < R3 * R3) {
+      const int J = q / R3 - 2, I = q % R3 - 2;
+      const bool in = J >= 0 && J < nm && I >= 0 && I < nm;
+      C xv = C(0);
+      if (!ZERO && in) xv = C(ldv(e + int64_t(J) * l * ep + int64_t(I) * l));
+      L.x[0][q] = xv;
+      L.x[1][q] = xv;
+      if constexpr (VAR) L.a[q] = in ? float(a[int64_t(J) * ap + I]) : 1.f;
+    }
+    rv[k] = C(0);
+    if (q < R2 * R2) {
+      const int J = q / R2 - 1, I = q % R2 - 1;
+      if (J >= 1 && J <= nm - 2 && I >= 1 && I <= nm - 2) rv[k] = C(ldv(r + int64_t(J) * rp + I));
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s <= it; ++s) {
+    const C* src = L.x[(s - 1) & 1];
+    C* dst = L.x[s & 1];
+    tile_features<C, VAR>(L, src, nm, 1, 1, rv, hl2);
+    __syncthreads();
+    tile_contract<C>(L, kc, nm, 1, 1);
+    __syncthreads();
+    if (t < NOWN) {
+      const int oj = t / TO, oi = t % TO;
+      if (oj + 1 <= nm - 2 && oi + 1 <= nm - 2) {
+        const int q = (oj + 3) * R3 + (oi + 3);
+        const C v = src[q] + C(tile_y(L, oj, oi));
+        dst[q] = stored<T>(v);  // each iterate rounded to the storage type, as stored by the multi-launch path
+      }
+    }
+    __syncthreads();
+  }
+  const C* xp_ = L.x[(it - 1) & 1];
+  const C* xc_ = L.x[it & 1];
+  for (int i = t; i < nm * nm; i += NT) {
+    const int J = i / nm, I = i - J * nm;
+    const int q = (J + 2) * R3 + (I + 2);
+    stv(xprev + int64_t(J) * cp + I, xp_[q]);
+    stv(xcur + int64_t(J) * cp + I, xc_[q]);
   }
 }
 
@@ -844,6 +932,40 @@ hipError_t launch_learned_iter(int prec, int nm, double hl, const void* xi, cons
     case PREC_F32: return learned_tm<float>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, mode, done, s);
     default: return learned_tm<bf16s>(nm, hl, xi, xl, xo, r, rl, a, al, u, ul, w, mode, done, s);
   }
+}
+
+template <typename T, bool ZERO>
+static hipError_t learned_small_t(int nm, int l, int it, double hl, const void* e, const Lay& el,
+                                  const void* r, const Lay& rl, const double* a, const Lay& al,
+                                  void* xprev, void* xcur, const Lay& cl, const float* w,
+                                  const int* done, hipStream_t s) {
+  using C = typename Acc<T>::C;
+  const T* ee = static_cast<const T*>(e) + el.off;
+  const T* rr = static_cast<const T*>(r) + rl.off;
+  T* xp = static_cast<T*>(xprev) + cl.off;
+  T* xc = static_cast<T*>(xcur) + cl.off;
+  const C hl2 = C(hl * hl);
+  if (a)
+    LL_LAUNCH((k_learned_small<T, ZERO, true>), dim3(1), dim3(NT), s, ee, el.pitch, l, rr, rl.pitch,
+              a + al.off, al.pitch, xp, xc, cl.pitch, nm, it, hl2, w, done);
+  LL_LAUNCH((k_learned_small<T, ZERO, false>), dim3(1), dim3(NT), s, ee, el.pitch, l, rr, rl.pitch,
+            (const double*)nullptr, int64_t(0), xp, xc, cl.pitch, nm, it, hl2, w, done);
+}
+
+hipError_t launch_learned_small(int prec, int nm, int l, int it, double hl, bool zero, const void* e,
+                                const Lay& el, const void* r, const Lay& rl, const double* a,
+                                const Lay& al, void* xprev, void* xcur, const Lay& cl,
+                                const float* w, const int* done, hipStream_t s) {
+  if (nm < 3 || nm > LEARNED_SMALL_NM || it < 1) return hipErrorInvalidValue;
+#define LS_CASE(T)                                                                                 \
+  return zero ? learned_small_t<T, true>(nm, l, it, hl, e, el, r, rl, a, al, xprev, xcur, cl, w, done, s) \
+              : learned_small_t<T, false>(nm, l, it, hl, e, el, r, rl, a, al, xprev, xcur, cl, w, done, s)
+  switch (prec) {
+    case PREC_F64: LS_CASE(double);
+    case PREC_F32: LS_CASE(float);
+    default: LS_CASE(bf16s);
+  }
+#undef LS_CASE
 }
 
 hipError_t launch_train_fwd(int nm, float hl2, const float* x, const float* r, const float* a,

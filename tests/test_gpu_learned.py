@@ -179,6 +179,79 @@ def test_solver_learned_iterations_match_oracle(B, torch_cuda, var):
             assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want)), (level, iters)
 
 
+def representable(torch, x, prec):
+    """Round x so the GPU's conversion to the storage type `prec` is exact."""
+    dt = torch.float32 if prec == "fp32" else torch.bfloat16
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dt).to(torch.float64).numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_solver_learned_iterations_reduced_precision(B, torch_cuda, prec):
+    """Learned iterations with FP32 / BF16 storage of the iterate and r_m:
+    every stored iterate is the FP64 oracle's step rounded to the storage
+    type, up to the FP32 network's rounding (FP32) or one BF16 ulp per
+    iteration (BF16)."""
+    torch = torch_cuda
+    n = 129
+    rng = np.random.default_rng(31)
+    k = O.check_side(n)
+    a = W.grf_problem(n, seed=5)[0]
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D, precision=prec)
+    s.set_coefficient(dev64(torch, a))
+    w = rand_weights(rng, 0.15)
+    s.set_smoother(B.LEARNED, dev32(torch, w))
+    for level in range(k):
+        nm = (n - 1) // (1 << level) + 1
+        for iters in (1, 3):
+            say("learned sweeps prec=%s level=%d iters=%d" % (prec, level, iters))
+            e0 = np.zeros((n, n))
+            e0[1:-1, 1:-1] = rng.standard_normal((n - 2, n - 2))
+            e0 = representable(torch, e0, prec)
+            rm = np.zeros((nm, nm))
+            rm[1:-1, 1:-1] = rng.standard_normal((nm - 2, nm - 2))
+            rm = representable(torch, rm, prec)
+            out = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+            s.step_sweeps(level, iters, dev64(torch, e0), dev64(torch, rm), out)
+            torch.cuda.synchronize()
+            want = e0
+            for _ in range(iters):
+                want = representable(torch, LO.sweep(n, level, rm, want, w, a), prec)
+            got = out.cpu().numpy()
+            mx = np.max(np.abs(want))
+            tol = (4e-5 * mx) if prec == "fp32" else (2.0 ** -7 * iters * mx)
+            assert np.max(np.abs(got - want)) <= tol, (level, iters, np.max(np.abs(got - want)) / mx)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_learned_solve_reduced_precision(B, torch_cuda, prec):
+    """FP32 / BF16 storage with the learned relaxation under the FP64
+    residual restart: the FP64 relative residual (recomputed by the oracle)
+    reaches 1e-10 and u lies within the rigorous bound of the oracle's
+    learned solve."""
+    torch = torch_cuda
+    n = 129
+    a, f = W.grf_problem(n, seed=12)
+    rng = np.random.default_rng(12)
+    w = LO.to_bf16(LO.jacobi_weights(0.7) + rng.standard_normal(LO.NW) * 0.01)
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D, precision=prec, max_cycles=200)
+    s.set_coefficient(dev64(torch, a))
+    s.set_smoother(B.LEARNED, dev32(torch, w))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    res = s.solve(dev64(torch, f), u, tol=1e-10, raise_on_status=False)
+    say("learned %s: status %d cycles %d final %.3e fell_back %s" % (
+        prec, res["status"], res["cycles"], res["final_relres"], res["smoother_fell_back"]))
+    assert res["status"] == 0 and res["converged"]
+    ug = u.cpu().numpy()
+    _, s2 = O.residual(2, n, f, ug, a)
+    fn = np.sqrt(O.norm2_interior(2, n, f))
+    assert np.sqrt(s2) / fn <= 1e-10 * (1 + 1e-6) + 1e-14
+    uo, _ = LO.solve(n, f, w, a, tol=1e-10)
+    _, so = O.residual(2, n, f, uo, a)
+    h = 1.0 / (n - 1)
+    lam = np.min(a) * (8 / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    assert np.linalg.norm(ug - uo) <= (np.sqrt(s2) + np.sqrt(so)) / lam * (1 + 1e-6)
+
+
 def test_jacobi_weights_reproduce_plain_homg(B, torch_cuda):
     """The Jacobi-equivalent weights (omega = 0.8 rounds to 0.80078125 in
     BF16) give the residual history of plain HOMG with that omega."""

@@ -286,6 +286,34 @@ def test_chained_path_with_revisits_and_coarse_end(B, torch_cuda, prec):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,sched", [
+    (5, [(1, 2), (0, 1)]),
+    (9, [(0, 3), (2, 1), (1, 2), (0, 5)]),
+    (17, [(0, 4), (3, 2), (0, 2)]),
+    (65, [(5, 2), (0, 2), (3, 2), (0, 9)]),
+    (2049, [(9, 2), (4, 1), (0, 7)]),
+    (1025, None),
+])
+def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, prec):
+    """2D level 0 with several iterations per pass (level-blocked and chained
+    paths) against one launch per iteration: level 0 first (from e = 0), in
+    the middle (stored) and last (added into u), 1 to 9 iterations, grids
+    narrower than one wave and row counts that are not multiples of the
+    band."""
+    torch = torch_cuda
+    say("level-0 pass n=%d sched=%s prec=%s" % (n, sched, prec))
+    f = dev(torch, W.uniform(2, n, seed=19))
+    outs = []
+    for blocked in (0, 1, 2):
+        s = B.Solver(2, n, schedule=sched, precision=prec, temporal_block=blocked)
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        s.solve_cycles(f, u, 2)
+        outs.append(host(u))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
 @pytest.mark.parametrize("n", [129, 257])
 def test_variable_coefficient_fp64(B, torch_cuda, n):
     a, f = W.grf_problem(n, seed=9)
