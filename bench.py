@@ -64,6 +64,9 @@ def kernel_symbol(d, kind, level, mode):
     if kind == "sweep":
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
         return "%s<double, %d%s>" % (base, mode, var2)
+    if kind == "lattice" and mode & 8:  # several compact-lattice iterations in one pass
+        return "k_lattice_2d_tb<double, %s, %s, %d>" % (
+            "true" if mode & 1 else "false", "true" if mode & 64 else "false", ((mode >> 4) & 3) + 1)
     if kind == "lattice":
         if mode & 4:
             return "k_lattice_small_%dd<double, %s%s>" % (d, "true" if mode & 1 else "false", var2)
@@ -94,6 +97,8 @@ def kernel_bytes(d, n, entry):
     lat = N / float(1 << level) ** d
     if kind == "gather":
         return 16 * lat * entry["launches"]
+    if kind == "lattice" and mode & 8:  # one pass: read x_0, r; write x_it (and x_{it-1})
+        return ((0 if mode & 1 else 8) + 8 + 8 + (8 if mode & 64 else 0)) * lat * entry["launches"]
     if kind == "lattice":
         if mode & 4:  # whole lattice in one workgroup: read x_0, r; write two iterates
             return ((0 if mode & 1 else 8) + 8 + 16) * lat * entry["launches"]

@@ -195,8 +195,9 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   level to the lattice of `level` (chained execution).
  *   mode (kinds 4, 6, 7, 8): bit 0 = starts from e = 0, bit 1 = adds into u;
  *   bit 2 (kinds 6, 8) = every iteration of the level in one workgroup that
- *   holds the whole lattice; bit 3 (kind 4) = several level-0 iterations in
- *   one temporally blocked pass, bits 4-5 their number minus one.
+ *   holds the whole lattice; bit 3 (kinds 4, 6) = several iterations in one
+ *   temporally blocked pass, bits 4-5 their number minus one, bit 6 (kind
+ *   6) = the pass also stores the iterate before its last.
  * homg_get_profile synchronises outstanding events, then writes up to cap
  * entries and their count in *len.
  */

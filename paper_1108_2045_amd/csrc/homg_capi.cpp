@@ -73,6 +73,7 @@ struct homg_ctx {
   std::vector<void*> r;
   std::vector<double*> a;
   std::vector<void*> xc;   // level-blocked path: compact x_{t-1}, x_t pairs per level (2m, 2m+1)
+  std::vector<void*> xp3;  // 2D Laplacian: third compact array per level (x_{it-1} of a blocked pass)
   size_t lds_limit = 65536;
   bool has_coef = false;
   double* partials = nullptr;
@@ -191,6 +192,7 @@ void free_ctx(homg_ctx* h) {
   for (void* p : h->r) (void)hipFree(p);
   for (double* p : h->a) (void)hipFree(p);
   for (void* p : h->xc) (void)hipFree(p);
+  for (void* p : h->xp3) (void)hipFree(p);
   (void)hipFree(h->partials);
   (void)hipFree(h->st);
   (void)hipFree(h->hist);
@@ -273,6 +275,25 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
                                   h->r[m], h->rl[m], am, alm, X0, X1, cl, done, s));
     xprev = X0;
     xcur = X1;
+  } else if (h->d == 2 && !am && m < int(h->xp3.size()) && h->xp3[m]) {
+    // 2D Laplacian: up to TB_MAX_IT iterations per pass over the lattice
+    if (!first && !chained_in)
+      LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X0, cl, done, s));
+    void* X[2] = {X0, X1};
+    int src = 0;
+    xprev = nullptr;
+    for (int t0 = 0; t0 < it; t0 += TB_MAX_IT) {
+      const int g = std::min(TB_MAX_IT, it - t0);
+      const bool zero = first && t0 == 0, lastg = t0 + g == it;
+      void* pv = (lastg && g > 1) ? h->xp3[m] : nullptr;
+      LAUNCH_K(h, s, K_LATTICE, m, SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | ((g - 1) << 4) | (pv ? 64 : 0),
+               launch_lattice_2d_tb(h->prec, nm, g, h->omega, X[src], X[1 - src], pv, cl, h->r[m],
+                                    h->rl[m], zero, done, s));
+      if (lastg) xprev = pv ? pv : X[src];
+      src = 1 - src;
+    }
+    xcur = X[src];
+    if (first && it == 1) wmode |= SW_ZERO_OLD;  // x_0 = 0 was never stored
   } else {
     if (!first && !chained_in)
       LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X0, cl, done, s));
@@ -628,6 +649,14 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
     for (int m = 1; m < levels && !stt; ++m)
       for (int b = 0; b < 2 && !stt; ++b)
         stt = dev_alloc(h, &h->xc[2 * m + b], size_t(h->rl[m].alloc) * eb);
+    if (ndim == 2 && h->stencil != HOMG_DIFFUSION_5PT_2D) {
+      h->xp3.assign(levels, nullptr);
+      for (int m = 1; m < levels && !stt; ++m) {
+        const int nm = (h->n - 1) / (1 << m) + 1;
+        if (nm >= 65)  // lattices that may be too large for one workgroup's LDS
+          stt = dev_alloc(h, &h->xp3[m], size_t(h->rl[m].alloc) * eb);
+      }
+    }
   }
   h->npart = partials_bound(ndim, h->n);
   if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->partials), sizeof(double) * h->npart);
@@ -649,6 +678,8 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   // compact lattices: boundary nodes are read as 0 and never written
   for (int m = 1; m < levels && ok && h->temporal; ++m)
     for (int b = 0; b < 2 && ok; ++b) ok = hipMemset(h->xc[2 * m + b], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  for (size_t m = 0; m < h->xp3.size() && ok; ++m)
+    if (h->xp3[m]) ok = hipMemset(h->xp3[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
   if (ok) {
     int optin = 0, base = 0;
     (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, h->device);

@@ -67,17 +67,31 @@ hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void*
 // with SW_ACCUM the iterate is added to u (FP64, layout ul) instead of
 // being stored in en.  compact: a level-0 iteration on the compact lattice
 // of a coarse level (same arithmetic, a kernel symbol of its own).
-// Level 0 of a 2D constant-coefficient grid: `it` (<= TB_MAX_IT) iterations
-// in one pass (temporal blocking), equal bit for bit to `it` launch_sweep
-// calls; reads e (unless zero) and r once, writes en or adds into u once.
-constexpr int TB_MAX_IT = 4;
-hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
-                                 const Lay& el, const void* rm, const Lay& rl, double* u,
-                                 const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s);
 hipError_t launch_sweep(int prec, int d, int n, int m, double omega, const void* eo, void* en,
                         const Lay& el, const void* rm, const Lay& rl, const double* am,
                         const Lay& al, double* u, const Lay& ul, int mode, const int* done,
                         hipStream_t s, bool compact = false);
+// Level 0 of a 2D constant-coefficient grid: `it` (<= TB_MAX_IT) iterations
+// in one pass (temporal blocking), equal bit for bit to `it` launch_sweep
+// calls; reads e (unless zero) and r once, writes en or adds into u once.
+// A wave walks a band of `len` rows (0: tb_band's choice).  Short bands
+// re-read more halo rows (from L2) but put more waves in flight: tb_band
+// returns the longest band (64, 32 or 16 rows) that still gives
+// TB_MIN_WAVES waves, else 8 (measured on MI355X, FP64: the pass beats the
+// single-iteration kernels from 129^2 up, 1.4-2.8x).
+constexpr int TB_MAX_IT = 4;
+constexpr int TB_MIN_WAVES = 4096;
+int tb_waves(int n, int it, int len);
+int tb_band(int n, int it);
+hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
+                                 const Lay& el, const void* rm, const Lay& rl, double* u,
+                                 const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s,
+                                 int len = 0);
+// The same on the compact lattice of a coarse level (side nm): x_it into en
+// and, when eprev is not null, x_{it-1} into eprev (layout cl).
+hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const void* eo, void* en,
+                                void* eprev, const Lay& cl, const void* rm, const Lay& rl, bool zero,
+                                const int* done, hipStream_t s, int len = 0);
 // Convert between a dense FP64 array and an internal array of `prec`.
 hipError_t launch_pack(int prec, int d, const double* src, const Lay& sl, void* dst,
                        const Lay& dl, hipStream_t s);

@@ -566,7 +566,7 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
 }
 
 // Level 0, IT <= 4 iterations in one pass (temporal blocking).  Each wave
-// owns 64 consecutive columns and walks a band of TB_LEN rows; the
+// owns 64 consecutive columns and walks a band of rows; the
 // iterations form a pipeline down the band: iteration t is computed t rows
 // behind the row just loaded, from a three-row window of iteration t-1 in
 // registers (the y neighbours) and the neighbour lanes' values (the x
@@ -579,10 +579,10 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
 // one goes to memory exactly as the single-iteration kernel sends it, so
 // the result equals IT single sweeps bit for bit while e and r are read
 // once and the result written (or added into u) once.
-constexpr int TB_LEN = 64;  // emitted rows per wave
 
-template <typename T, bool ZERO, bool ACCUM, int IT, int U>
-__device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict__ en, int64_t ep,
+template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT, int U>
+__device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict__ en,
+                                         T* __restrict__ eprev, int64_t ep,
                                          const T* __restrict__ r, int64_t rp, double* __restrict__ u,
                                          int64_t up, int n, int x, int xc, bool xin, bool emit, int Y0,
                                          int Y1, int ys, typename Tr<T>::C w, typename Tr<T>::C hl2,
@@ -619,27 +619,27 @@ __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict
           add_to(u + int64_t(y) * up + x, double(v));
         else
           st(en + int64_t(y) * ep + x, v);
+        if (PREV) st(eprev + int64_t(y) * ep + x, c);  // the iterate before the last
       }
     }
   }
 }
 
-template <typename T, bool ZERO, bool ACCUM, int IT>
-__global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
-    const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r, int64_t rp,
-    double* __restrict__ u, int64_t up, int n, typename Tr<T>::C w, typename Tr<T>::C hl2,
-    const int* __restrict__ done) {
+template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT>
+__device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict__ en,
+                                        T* __restrict__ eprev, int64_t ep, const T* __restrict__ r,
+                                        int64_t rp, double* __restrict__ u, int64_t up, int n, int len,
+                                        typename Tr<T>::C w, typename Tr<T>::C hl2) {
   using C = typename Tr<T>::C;
-  if (*done) return;
   constexpr int VALID = 64 - 2 * IT;
   const int lane = threadIdx.x & 63;
-  const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + TB_LEN - 1) / TB_LEN;
+  const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + len - 1) / len;
   // XCD order: the waves of one XCD are neighbours (their overlapping
   // columns and rows meet in that XCD's L2)
   const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
   if (wv >= gx * gy) return;  // the whole wave
   const int x = 1 + (wv % gx) * VALID - IT + lane;
-  const int Y0 = 1 + (wv / gx) * TB_LEN, Y1 = min(n - 1, Y0 + TB_LEN);
+  const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);
   const bool xin = x >= 1 && x <= n - 2;
   const bool emit = lane >= IT && lane < 64 - IT;
   const int xc = min(max(x, 0), n - 1);  // columns off the grid read the boundary (zero)
@@ -651,9 +651,32 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
   int ys = max(Y0 - IT, 0);
   const int ye = Y1 + IT;  // one past the last row loaded
   for (; ys + 4 <= ye; ys += 4)
-    tb_steps<T, ZERO, ACCUM, IT, 4>(eo, en, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w, hl2, win, rw);
+    tb_steps<T, ZERO, ACCUM, PREV, IT, 4>(eo, en, eprev, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w,
+                                          hl2, win, rw);
   for (; ys < ye; ++ys)
-    tb_steps<T, ZERO, ACCUM, IT, 1>(eo, en, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w, hl2, win, rw);
+    tb_steps<T, ZERO, ACCUM, PREV, IT, 1>(eo, en, eprev, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w,
+                                          hl2, win, rw);
+}
+
+template <typename T, bool ZERO, bool ACCUM, int IT>
+__global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
+    const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r, int64_t rp,
+    double* __restrict__ u, int64_t up, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    const int* __restrict__ done) {
+  if (*done) return;
+  tb_body<T, ZERO, ACCUM, false, IT>(eo, en, nullptr, ep, r, rp, u, up, n, len, w, hl2);
+}
+
+// The same pass over the compact lattice of a coarse level (n = its side),
+// optionally also storing the iterate before the last (PREV), which the
+// level's whole-grid pass interpolates.
+template <typename T, bool ZERO, bool PREV, int IT>
+__global__ __launch_bounds__(256) void k_lattice_2d_tb(
+    const T* __restrict__ eo, T* __restrict__ en, T* __restrict__ eprev, int64_t ep,
+    const T* __restrict__ r, int64_t rp, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    const int* __restrict__ done) {
+  if (*done) return;
+  tb_body<T, ZERO, false, PREV, IT>(eo, en, eprev, ep, r, rp, nullptr, 0, n, len, w, hl2);
 }
 
 // Levels m >= 1: lattice nodes relax, the rest interpolate.  The lane keeps
@@ -1395,7 +1418,7 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
 }
 
 template <typename T, bool ZERO, bool ACCUM>
-static hipError_t tb_t(int n, int it, double omega, const void* eo_, void* en_, const Lay& el,
+static hipError_t tb_t(int n, int it, int len, double omega, const void* eo_, void* en_, const Lay& el,
                        const void* rm_, const Lay& rl, double* u, const Lay& ul, const int* done,
                        hipStream_t s) {
   using C = typename Tr<T>::C;
@@ -1405,37 +1428,90 @@ static hipError_t tb_t(int n, int it, double omega, const void* eo_, void* en_, 
   double* uu = u ? u + ul.off : nullptr;
   const double h = 1.0 / double(n - 1);
   const C w = C(omega / 4.0), hl2 = C(h * h);
-  const int valid = 64 - 2 * it;
-  const int waves = ((n - 2 + valid - 1) / valid) * ((n - 2 + TB_LEN - 1) / TB_LEN);
-  const dim3 g((waves + 3) / 4);
+  const dim3 g((tb_waves(n, it, len) + 3) / 4);
   switch (it) {
-    case 1: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 1>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
-    case 2: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 2>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
-    case 3: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 3>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
-    default: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 4>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, w, hl2, done);
+    case 1: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 1>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
+    case 2: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 2>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
+    case 3: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 3>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
+    default: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 4>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
   }
 }
 
 template <typename T>
-static hipError_t tb_tz(int n, int it, double omega, const void* eo, void* en, const Lay& el,
+static hipError_t tb_tz(int n, int it, int len, double omega, const void* eo, void* en, const Lay& el,
                         const void* rm, const Lay& rl, double* u, const Lay& ul, bool zero, bool accum,
                         const int* done, hipStream_t s) {
   if (zero)
-    return accum ? tb_t<T, true, true>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s)
-                 : tb_t<T, true, false>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s);
-  return accum ? tb_t<T, false, true>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s)
-               : tb_t<T, false, false>(n, it, omega, eo, en, el, rm, rl, u, ul, done, s);
+    return accum ? tb_t<T, true, true>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s)
+                 : tb_t<T, true, false>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s);
+  return accum ? tb_t<T, false, true>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s)
+               : tb_t<T, false, false>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s);
+}
+
+template <typename T, bool ZERO, bool PREV>
+static hipError_t ltb_t(int nm, int it, int len, double omega, const void* eo_, void* en_, void* ep_,
+                        const Lay& cl, const void* rm_, const Lay& rl, const int* done, hipStream_t s) {
+  using C = typename Tr<T>::C;
+  const T* eo = eo_ ? static_cast<const T*>(eo_) + cl.off : nullptr;
+  T* en = static_cast<T*>(en_) + cl.off;
+  T* epv = ep_ ? static_cast<T*>(ep_) + cl.off : nullptr;
+  const T* rm = static_cast<const T*>(rm_) + rl.off;
+  const double h = 1.0 / double(nm - 1);
+  const C w = C(omega / 4.0), hl2 = C(h * h);
+  const dim3 g((tb_waves(nm, it, len) + 3) / 4);
+  switch (it) {
+    case 1: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 1>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
+    case 2: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 2>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
+    case 3: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 3>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
+    default: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 4>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
+  }
+}
+
+template <typename T>
+static hipError_t ltb_tz(int nm, int it, int len, double omega, const void* eo, void* en, void* eprev,
+                         const Lay& cl, const void* rm, const Lay& rl, bool zero, const int* done,
+                         hipStream_t s) {
+  if (zero)
+    return eprev ? ltb_t<T, true, true>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s)
+                 : ltb_t<T, true, false>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s);
+  return eprev ? ltb_t<T, false, true>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s)
+               : ltb_t<T, false, false>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s);
+}
+
+hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const void* eo, void* en,
+                                void* eprev, const Lay& cl, const void* rm, const Lay& rl, bool zero,
+                                const int* done, hipStream_t s, int len) {
+  if (len == 0) len = tb_band(nm, it);
+  if (nm < 3 || it < 1 || it > TB_MAX_IT || len < 1) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return ltb_tz<double>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, done, s);
+    case PREC_F32: return ltb_tz<float>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, done, s);
+    default: return ltb_tz<bf16>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, done, s);
+  }
 }
 
 hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
                                  const Lay& el, const void* rm, const Lay& rl, double* u,
-                                 const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s) {
-  if (n < 3 || it < 1 || it > TB_MAX_IT) return hipErrorInvalidValue;
+                                 const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s,
+                                 int len) {
+  if (len == 0) len = tb_band(n, it);
+  if (n < 3 || it < 1 || it > TB_MAX_IT || len < 1) return hipErrorInvalidValue;
   switch (prec) {
-    case PREC_F64: return tb_tz<double>(n, it, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
-    case PREC_F32: return tb_tz<float>(n, it, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
-    default: return tb_tz<bf16>(n, it, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+    case PREC_F64: return tb_tz<double>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+    case PREC_F32: return tb_tz<float>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+    default: return tb_tz<bf16>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
   }
+}
+
+int tb_waves(int n, int it, int len) {
+  const int valid = 64 - 2 * it;
+  return ((n - 2 + valid - 1) / valid) * ((n - 2 + len - 1) / len);
+}
+
+int tb_band(int n, int it) {
+  for (int len : {64, 32, 16})
+    if (tb_waves(n, it, len) >= TB_MIN_WAVES) return len;
+  return 8;
 }
 
 template <typename T>
