@@ -77,13 +77,15 @@ typedef struct homg_options {
                               iterations min(2^(M-m+1), MaxI)) */
     int schedule_len;
     int precision;         /* homg_precision */
-    int temporal_block;    /* 1 (default): level-blocked -- the iterations of a coarse level run on
-                              its compact lattice and the whole grid is written once per level;
-                              0: one whole-grid launch per iteration;
-                              2: chained -- as 1, but a coarse level followed by another coarse
-                              level hands over only that level's lattice values, and the whole
-                              grid is written only before level 0 or the last level.
-                              All three give the same results bit for bit. */
+    int temporal_block;    /* 2 (default): chained -- the iterations of a coarse level run on its
+                              compact lattice, a coarse level followed by another coarse level
+                              hands over only that level's lattice values, and the whole grid is
+                              written only before level 0 or the last level;
+                              1: level-blocked -- as 2, but the whole grid is written after every
+                              level;
+                              0: one whole-grid launch per iteration.
+                              With 1 or 2, several level-0 iterations (2D Laplacian) run in one
+                              pass.  All three give the same results bit for bit. */
     int reserved[7];       /* must be 0 */
 } homg_options;
 
@@ -183,10 +185,11 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
 
 /*
  * Per-launch device timing (measurement support).  With profiling enabled,
- * every kernel the handle launches is bracketed by a pair of HIP events on
- * the launch's stream, and the elapsed times are accumulated per kernel
- * class (kind, level, mode) whenever the handle synchronises.  Enabling or
- * disabling clears the accumulated times.
+ * every kernel the handle launches is stamped with its own start and end
+ * events (recorded by the dispatch on the launch's stream), and the elapsed
+ * times are accumulated per kernel class (kind, level, mode) at the end of
+ * every solve and by homg_get_profile.  Enabling or disabling clears the
+ * accumulated times.
  *   kind: 0 norm of f, 1 residual, 2 norm finalisation, 3 restriction from
  *   `level` to level+1, 4 whole-grid iteration at `level`, 5 sampling of the
  *   grid on the level lattice, 6 iterations on the compact lattice, 7

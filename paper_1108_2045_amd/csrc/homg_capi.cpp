@@ -44,7 +44,7 @@ enum Kind {
   K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7, K_LEARNED = 8, K_TRANSFER = 9
 };
 
-// Event-pair timing of individual launches, harvested at synchronisation.
+// Event-pair timing of individual launches, harvested at the end of a solve.
 struct Profiler {
   using Key = std::tuple<int, int, int>;  // kind, level, mode
   bool on = false;
@@ -465,8 +465,6 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
                              hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     ++syncs;
-    if (h->prof.on)
-      if (homg_status pe = prof_harvest(h)) return pe;
     if (h->h_st->done || enqueued >= limit) break;
     const int c = h->h_st->cycles;
     // learned relaxation: fall back to damped Jacobi for the rest of the solve
@@ -486,6 +484,10 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
     const double need = std::log(tol / h->h_hist[c]) / std::log(q);
     batch = int(std::ceil(std::max(1.0, std::min(need, 16.0))));
   }
+  // launch times are read once per solve, so timing adds no host work
+  // between the batches of cycles
+  if (h->prof.on)
+    if (homg_status pe = prof_harvest(h)) return pe;
   const int cycles = std::max(h->h_st->cycles, 0);
   const double final_rel = h->h_hist[cycles];
   if (info) {
@@ -542,7 +544,7 @@ void homg_options_init(homg_options* opt) {
   opt->max_i = 4;
   opt->max_cycles = 200;
   opt->precision = HOMG_FP64;
-  opt->temporal_block = 1;
+  opt->temporal_block = 2;
 }
 
 homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int levels,

@@ -159,7 +159,7 @@ class Solver:
     """One HOMG solver for a d-dimensional grid of side n = 2^k + 1."""
 
     def __init__(self, ndim, n, levels=0, stencil=None, omega=0.0, max_i=4, max_cycles=200,
-                 schedule=None, precision="fp64", temporal_block=1):
+                 schedule=None, precision="fp64", temporal_block=2):
         L = lib()
         if stencil is None:
             stencil = LAPLACE_5PT_2D if ndim == 2 else LAPLACE_7PT_3D
