@@ -65,14 +65,14 @@ def kernel_symbol(d, kind, level, mode):
     argument list), so the bench line and the rocprofv3 summary can be matched."""
     var2 = ", false" if d == 2 else ""
     if kind == "sweep" and mode & 8:  # several level-0 iterations in one pass
-        return "k_sweep_2d_l0_tb<double, %s, %s, %d>" % (
-            "true" if mode & 1 else "false", "true" if mode & 2 else "false", ((mode >> 4) & 3) + 1)
+        return "k_sweep_%dd_l0_tb<double, %s, %s, %d>" % (
+            d, "true" if mode & 1 else "false", "true" if mode & 2 else "false", ((mode >> 4) & 3) + 1)
     if kind == "sweep":
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
         return "%s<double, %d%s>" % (base, mode, var2)
     if kind == "lattice" and mode & 8:  # several compact-lattice iterations in one pass
-        return "k_lattice_2d_tb<double, %s, %s, %d>" % (
-            "true" if mode & 1 else "false", "true" if mode & 64 else "false", ((mode >> 4) & 3) + 1)
+        return "k_lattice_%dd_tb<double, %s, %s, %d>" % (
+            d, "true" if mode & 1 else "false", "true" if mode & 64 else "false", ((mode >> 4) & 3) + 1)
     if kind == "lattice":
         if mode & 4:
             return "k_lattice_small_%dd<double, %s%s>" % (d, "true" if mode & 1 else "false", var2)

@@ -73,7 +73,7 @@ struct homg_ctx {
   std::vector<void*> r;
   std::vector<double*> a;
   std::vector<void*> xc;   // level-blocked path: compact x_{t-1}, x_t pairs per level (2m, 2m+1)
-  std::vector<void*> xp3;  // 2D Laplacian: third compact array per level (x_{it-1} of a blocked pass)
+  std::vector<void*> xp3;  // Laplacian: third compact array per level (x_{it-1} of a multi-iteration pass)
   size_t lds_limit = 65536;
   bool has_coef = false;
   double* partials = nullptr;
@@ -231,6 +231,19 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
   // One launch per iteration: level 0 always (every node is a lattice
   // node), every level when blocking is off, and a coarse last level in
   // reduced precision (its iterate goes into u unrounded).
+  if (m == 0 && h->d == 3 && h->temporal) {
+    // level 0 in 3D: up to TB3_MAX_IT iterations per pass, same iterates
+    for (int t0 = 0; t0 < it; t0 += TB3_MAX_IT) {
+      const int g = std::min(TB3_MAX_IT, it - t0);
+      const bool zero = first && t0 == 0, accum = last && t0 + g == it;
+      const int mode = SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | (accum ? SW_ACCUM : 0) | ((g - 1) << 4);
+      LAUNCH_K(h, s, K_SWEEP, 0, mode,
+               launch_tb_3d(h->prec, h->n, g, h->omega, h->e[*cur], h->e[1 - *cur], nullptr, h->el,
+                            h->r[0], h->rl[0], acc, h->dl, zero, accum, false, done, s));
+      *cur = 1 - *cur;
+    }
+    return HOMG_OK;
+  }
   if (m == 0 && h->d == 2 && !am && h->temporal) {
     // level 0 of a 2D constant-coefficient grid: up to TB_MAX_IT iterations
     // per pass (temporally blocked), the same iterates bit for bit
@@ -275,20 +288,24 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
                                   h->r[m], h->rl[m], am, alm, X0, X1, cl, done, s));
     xprev = X0;
     xcur = X1;
-  } else if (h->d == 2 && !am && m < int(h->xp3.size()) && h->xp3[m]) {
-    // 2D Laplacian: up to TB_MAX_IT iterations per pass over the lattice
+  } else if (!am && m < int(h->xp3.size()) && h->xp3[m]) {
+    // Laplacian: several iterations per pass over the lattice
     if (!first && !chained_in)
       LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X0, cl, done, s));
     void* X[2] = {X0, X1};
     int src = 0;
     xprev = nullptr;
-    for (int t0 = 0; t0 < it; t0 += TB_MAX_IT) {
-      const int g = std::min(TB_MAX_IT, it - t0);
+    const int gmax = h->d == 2 ? TB_MAX_IT : TB3_MAX_IT;
+    for (int t0 = 0; t0 < it; t0 += gmax) {
+      const int g = std::min(gmax, it - t0);
       const bool zero = first && t0 == 0, lastg = t0 + g == it;
       void* pv = (lastg && g > 1) ? h->xp3[m] : nullptr;
+      const Lay none;
       LAUNCH_K(h, s, K_LATTICE, m, SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | ((g - 1) << 4) | (pv ? 64 : 0),
-               launch_lattice_2d_tb(h->prec, nm, g, h->omega, X[src], X[1 - src], pv, cl, h->r[m],
-                                    h->rl[m], zero, done, s));
+               h->d == 2 ? launch_lattice_2d_tb(h->prec, nm, g, h->omega, X[src], X[1 - src], pv, cl,
+                                                h->r[m], h->rl[m], zero, done, s)
+                         : launch_tb_3d(h->prec, nm, g, h->omega, X[src], X[1 - src], pv, cl, h->r[m],
+                                        h->rl[m], nullptr, none, zero, false, true, done, s));
       if (lastg) xprev = pv ? pv : X[src];
       src = 1 - src;
     }
@@ -651,11 +668,11 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
     for (int m = 1; m < levels && !stt; ++m)
       for (int b = 0; b < 2 && !stt; ++b)
         stt = dev_alloc(h, &h->xc[2 * m + b], size_t(h->rl[m].alloc) * eb);
-    if (ndim == 2 && h->stencil != HOMG_DIFFUSION_5PT_2D) {
+    if (h->stencil != HOMG_DIFFUSION_5PT_2D) {
       h->xp3.assign(levels, nullptr);
       for (int m = 1; m < levels && !stt; ++m) {
         const int nm = (h->n - 1) / (1 << m) + 1;
-        if (nm >= 65)  // lattices that may be too large for one workgroup's LDS
+        if (nm >= (ndim == 2 ? 65 : 33))  // lattices that may be too large for one workgroup's LDS
           stt = dev_alloc(h, &h->xp3[m], size_t(h->rl[m].alloc) * eb);
       }
     }

@@ -92,6 +92,20 @@ hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const vo
 hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const void* eo, void* en,
                                 void* eprev, const Lay& cl, const void* rm, const Lay& rl, bool zero,
                                 const int* done, hipStream_t s, int len = 0);
+// 3D (7-point Laplacian) counterpart: `it` (<= TB3_MAX_IT) iterations in one
+// pass over the level-0 grid or (compact) a coarse level's lattice of side
+// n (layout el for eo, en, eprev; r in rl); accum (level 0 only): add x_it
+// into u (dense FP64, ul) instead of storing it; eprev (compact only): also
+// store x_{it-1}.  A block walks
+// `len` planes (0: tb3_band's choice: the longest of 32, 16, 8 planes that
+// still gives TB3_MIN_BLOCKS blocks, else 4).
+constexpr int TB3_MAX_IT = 2;
+constexpr int TB3_MIN_BLOCKS = 1024;
+int tb3_blocks(int n, int it, int len);
+int tb3_band(int n, int it);
+hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, void* en, void* eprev,
+                        const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
+                        bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len = 0);
 // Convert between a dense FP64 array and an internal array of `prec`.
 hipError_t launch_pack(int prec, int d, const double* src, const Lay& sl, void* dst,
                        const Lay& dl, hipStream_t s);

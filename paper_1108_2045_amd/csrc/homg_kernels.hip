@@ -832,6 +832,135 @@ __global__ __launch_bounds__(256) void k_sweep_3d_l0(
   tile_sweep_3d_l0<T, MODE>(eo, en, ep, epl, r, rp, rpl, u, up, upl, n, len, w, hl2);
 }
 
+// 3D level 0, IT <= 2 iterations in one pass.  A block of 64 x 4 lanes owns
+// a 64 x 16 tile of (x, y) columns (four consecutive rows per lane) and
+// walks z; iteration t is computed t planes behind the plane just loaded.
+// A lane keeps, per iteration level, its four rows of the last three planes
+// (the z neighbours, and the y neighbours of its inner rows); the current
+// centre plane of each level is also put in LDS, where the x neighbours and
+// the y neighbours across lanes are read (double-buffered: one barrier per
+// plane).  The tile's outer IT columns and rows only feed the inner ones,
+// so a block emits (64 - 2 IT) x (16 - 2 IT) columns and the band of planes
+// is entered IT planes early and left IT planes late.  Every intermediate
+// iterate is rounded as a store would round it, so the result equals IT
+// single sweeps bit for bit.
+constexpr int TB3_R = 4;                 // rows per lane
+constexpr int TB3_TY = BY3 * TB3_R;      // tile rows (16)
+
+template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT>
+__device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict__ en,
+                                         T* __restrict__ eprev, int64_t ep, int64_t epl,
+                                         const T* __restrict__ r, int64_t rp, int64_t rpl,
+                                         double* __restrict__ u, int64_t up, int64_t upl, int n,
+                                         int len, typename Tr<T>::C w, typename Tr<T>::C hl2) {
+  using C = typename Tr<T>::C;
+  constexpr int VX = BX3 - 2 * IT, VY = TB3_TY - 2 * IT;
+  __shared__ C P[IT][2][TB3_TY][BX3];
+  const int gx = (n - 2 + VX - 1) / VX, gy = (n - 2 + VY - 1) / VY;
+  const int lg = int(xcd_order(blockIdx.x, gridDim.x));
+  const int bx = lg % gx, by = (lg / gx) % gy, bz = lg / (gx * gy);
+  const int lx = threadIdx.x, row0 = threadIdx.y * TB3_R;
+  const int x = 1 + bx * VX - IT + lx;
+  const int yb = 1 + by * VY - IT + row0;  // first of the lane's rows
+  const int Z0 = 1 + bz * len, Z1 = min(n - 1, Z0 + len);
+  const int xc = min(max(x, 0), n - 1);
+  const bool xin = x >= 1 && x <= n - 2;
+  const bool emit_x = lx >= IT && lx < BX3 - IT;
+  // clamped (y, x) offsets in e and r: positions off the grid read the boundary (zero)
+  int64_t col[TB3_R], rcol[TB3_R];
+  bool yin[TB3_R], emit[TB3_R];
+#pragma unroll
+  for (int k = 0; k < TB3_R; ++k) {
+    const int y = yb + k, ycl = min(max(y, 0), n - 1);
+    col[k] = int64_t(ycl) * ep + xc;
+    rcol[k] = int64_t(ycl) * rp + xc;
+    yin[k] = xin && y >= 1 && y <= n - 2;
+    emit[k] = emit_x && row0 + k >= IT && row0 + k < TB3_TY - IT && yin[k];
+  }
+  C win[IT][3][TB3_R], rr[IT][TB3_R];
+#pragma unroll
+  for (int t = 0; t < IT; ++t)
+#pragma unroll
+    for (int k = 0; k < TB3_R; ++k) {
+      win[t][0][k] = win[t][1][k] = win[t][2][k] = C(0);
+      rr[t][k] = C(0);
+    }
+  const int xm_i = max(lx - 1, 0), xp_i = min(lx + 1, BX3 - 1);
+  const int ym_row = max(row0 - 1, 0), yp_row = min(row0 + TB3_R, TB3_TY - 1);
+  int b = 0;
+  for (int zl = max(Z0 - IT, 0); zl < Z1 + IT; ++zl, b ^= 1) {
+    const int zlc = min(zl, n - 1), zr = min(max(zl - 1, 0), n - 1);
+#pragma unroll
+    for (int k = 0; k < TB3_R; ++k) {
+      const C v0 = ZERO ? C(0) : ld(eo + int64_t(zlc) * epl + col[k]);
+      const C rv = ld(r + int64_t(zr) * rpl + rcol[k]);
+      win[0][0][k] = win[0][1][k];
+      win[0][1][k] = win[0][2][k];
+      win[0][2][k] = v0;
+#pragma unroll
+      for (int t = IT - 1; t > 0; --t) rr[t][k] = rr[t - 1][k];
+      rr[0][k] = rv;
+      P[0][b][row0 + k][lx] = win[0][1][k];
+#pragma unroll
+      for (int t = 1; t < IT; ++t) P[t][b][row0 + k][lx] = win[t][2][k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 1; t <= IT; ++t) {
+      const int zc = zl - t;
+      const bool zin = zc >= 1 && zc <= n - 2;
+      const C(&pl)[TB3_TY][BX3] = P[t - 1][b];
+      C v[TB3_R];
+#pragma unroll
+      for (int k = 0; k < TB3_R; ++k) {
+        const C c = win[t - 1][1][k];
+        const C xm = pl[row0 + k][xm_i], xp = pl[row0 + k][xp_i];
+        const C ym = k == 0 ? pl[ym_row][lx] : win[t - 1][1][k - 1];
+        const C yp = k == TB3_R - 1 ? pl[yp_row][lx] : win[t - 1][1][k + 1];
+        v[k] = relax_const<C>(c, ((xm + xp) + (ym + yp)) + (win[t - 1][0][k] + win[t - 1][2][k]),
+                              rr[t - 1][k], w, hl2, C(6));
+      }
+      if (t < IT) {
+#pragma unroll
+        for (int k = 0; k < TB3_R; ++k) {
+          win[t][0][k] = win[t][1][k];
+          win[t][1][k] = win[t][2][k];
+          win[t][2][k] = (yin[k] && zin) ? rnd<T>(v[k]) : C(0);
+        }
+      } else if (zc >= Z0 && zc < Z1) {
+#pragma unroll
+        for (int k = 0; k < TB3_R; ++k) {
+          if (!emit[k]) continue;
+          const int y = yb + k;
+          if (ACCUM)
+            add_to(u + int64_t(zc) * upl + int64_t(y) * up + x, double(v[k]));
+          else
+            st(en + int64_t(zc) * epl + int64_t(y) * ep + x, v[k]);
+          if (PREV) st(eprev + int64_t(zc) * epl + int64_t(y) * ep + x, win[t - 1][1][k]);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, bool ZERO, bool ACCUM, int IT>
+__global__ __launch_bounds__(256) void k_sweep_3d_l0_tb(
+    const T* __restrict__ eo, T* __restrict__ en, int64_t ep, int64_t epl, const T* __restrict__ r,
+    int64_t rp, int64_t rpl, double* __restrict__ u, int64_t up, int64_t upl, int n, int len,
+    typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done) {
+  if (*done) return;
+  tb3_body<T, ZERO, ACCUM, false, IT>(eo, en, nullptr, ep, epl, r, rp, rpl, u, up, upl, n, len, w, hl2);
+}
+
+template <typename T, bool ZERO, bool PREV, int IT>
+__global__ __launch_bounds__(256) void k_lattice_3d_tb(
+    const T* __restrict__ eo, T* __restrict__ en, T* __restrict__ eprev, int64_t ep, int64_t epl,
+    const T* __restrict__ r, int64_t rp, int64_t rpl, int n, int len, typename Tr<T>::C w,
+    typename Tr<T>::C hl2, const int* __restrict__ done) {
+  if (*done) return;
+  tb3_body<T, ZERO, false, PREV, IT>(eo, en, eprev, ep, epl, r, rp, rpl, nullptr, 0, 0, n, len, w, hl2);
+}
+
 // The same iteration on the compact lattice of a coarse level (the
 // level-blocked path): a kernel of its own so that profiles separate it
 // from the whole-grid level-0 iteration.
@@ -1512,6 +1641,70 @@ int tb_band(int n, int it) {
   for (int len : {64, 32, 16})
     if (tb_waves(n, it, len) >= TB_MIN_WAVES) return len;
   return 8;
+}
+
+int tb3_blocks(int n, int it, int len) {
+  const int vx = BX3 - 2 * it, vy = TB3_TY - 2 * it;
+  return ((n - 2 + vx - 1) / vx) * ((n - 2 + vy - 1) / vy) * ((n - 2 + len - 1) / len);
+}
+
+int tb3_band(int n, int it) {
+  for (int len : {32, 16, 8})
+    if (tb3_blocks(n, it, len) >= TB3_MIN_BLOCKS) return len;
+  return 4;
+}
+
+template <typename T, bool ZERO, bool ACCUM, bool PREV>
+static hipError_t tb3_t(int n, int it, int len, double omega, const void* eo_, void* en_, void* ep_,
+                        const Lay& el, const void* rm_, const Lay& rl, double* u, const Lay& ul,
+                        bool compact, const int* done, hipStream_t s) {
+  using C = typename Tr<T>::C;
+  const T* eo = eo_ ? static_cast<const T*>(eo_) + el.off : nullptr;
+  T* en = en_ ? static_cast<T*>(en_) + el.off : nullptr;
+  T* epv = ep_ ? static_cast<T*>(ep_) + el.off : nullptr;
+  const T* rm = static_cast<const T*>(rm_) + rl.off;
+  double* uu = u ? u + ul.off : nullptr;
+  const double h = 1.0 / double(n - 1);
+  const C w = C(omega / 6.0), hl2 = C(h * h);
+  const dim3 g(tb3_blocks(n, it, len)), blk(BX3, BY3);
+  if (compact && !ACCUM) {  // compact lattice of a coarse level
+    if (it == 1)
+      HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 1>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
+                  rl.pitch, rl.plane, n, len, w, hl2, done);
+    HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 2>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
+                rl.pitch, rl.plane, n, len, w, hl2, done);
+  }
+  if (it == 1)
+    HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 1>), g, blk, s, eo, en, el.pitch, el.plane, rm, rl.pitch,
+                rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done);
+  HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 2>), g, blk, s, eo, en, el.pitch, el.plane, rm, rl.pitch,
+              rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done);
+}
+
+template <typename T>
+static hipError_t tb3_tz(int n, int it, int len, double omega, const void* eo, void* en, void* eprev,
+                         const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
+                         bool zero, bool accum, bool compact, const int* done, hipStream_t s) {
+#define TB3_ARGS n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, compact, done, s
+  if (accum)
+    return zero ? tb3_t<T, true, true, false>(TB3_ARGS) : tb3_t<T, false, true, false>(TB3_ARGS);
+  if (eprev)
+    return zero ? tb3_t<T, true, false, true>(TB3_ARGS) : tb3_t<T, false, false, true>(TB3_ARGS);
+  return zero ? tb3_t<T, true, false, false>(TB3_ARGS) : tb3_t<T, false, false, false>(TB3_ARGS);
+#undef TB3_ARGS
+}
+
+hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, void* en, void* eprev,
+                        const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
+                        bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len) {
+  if (len == 0) len = tb3_band(n, it);
+  if (n < 3 || it < 1 || it > TB3_MAX_IT || len < 1 || (accum && (eprev || compact)))
+    return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return tb3_tz<double>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, done, s);
+    case PREC_F32: return tb3_tz<float>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, done, s);
+    default: return tb3_tz<bf16>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, done, s);
+  }
 }
 
 template <typename T>

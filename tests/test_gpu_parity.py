@@ -314,6 +314,32 @@ def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sche
     assert np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n,sched", [
+    (5, [(1, 2), (0, 1)]),
+    (9, [(0, 3), (2, 1), (1, 2), (0, 5)]),
+    (33, [(4, 2), (0, 2), (3, 3), (1, 5), (0, 4)]),
+    (65, [(5, 2), (2, 3), (1, 1), (0, 9)]),
+    (129, None),
+])
+def test_3d_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, prec):
+    """3D level 0 and the compact lattices with two iterations per pass
+    (level-blocked and chained paths) against one launch per iteration:
+    level 0 first, in the middle and last, odd and even iteration counts,
+    grids smaller than one tile."""
+    torch = torch_cuda
+    say("3D pass n=%d sched=%s prec=%s" % (n, sched, prec))
+    f = dev(torch, W.uniform(3, n, seed=20))
+    outs = []
+    for blocked in (0, 1, 2):
+        s = B.Solver(3, n, schedule=sched, precision=prec, temporal_block=blocked)
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        s.solve_cycles(f, u, 2)
+        outs.append(host(u))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
 @pytest.mark.parametrize("n", [129, 257])
 def test_variable_coefficient_fp64(B, torch_cuda, n):
     a, f = W.grf_problem(n, seed=9)
