@@ -81,6 +81,8 @@ def kernel_symbol(d, kind, level, mode):
         return "k_level_write_%dd<double, %d>" % (d, mode)
     if kind == "residual":
         return "k_residual_%dd<double%s>" % (d, var2)
+    if kind == "tail":
+        return "k_coarse_tail<double, %d>" % d
     if kind == "transfer":
         return "k_level_transfer_%dd<double, %s>" % (d, "true" if mode & 1 else "false")
     return {"restrict": "k_restrict_%dd<double>" % d, "norm": "k_norm2_%dd" % d,

@@ -195,7 +195,8 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   grid on the level lattice, 6 iterations on the compact lattice, 7
  *   whole-grid pass of a blocked level, 8 learned relaxation of the level
  *   lattice (level 0: of the whole grid), 9 hand-over of a finished coarse
- *   level to the lattice of `level` (chained execution).
+ *   level to the lattice of `level` (chained execution), 10 the leading
+ *   coarse levels down to `level` in one workgroup (chained execution).
  *   mode (kinds 4, 6, 7, 8): bit 0 = starts from e = 0, bit 1 = adds into u;
  *   bit 2 (kinds 6, 8) = every iteration of the level in one workgroup that
  *   holds the whole lattice; bit 3 (kinds 4, 6) = several iterations in one

@@ -41,7 +41,7 @@ namespace {
 
 enum Kind {
   K_NORM = 0, K_RESIDUAL = 1, K_FINALIZE = 2, K_RESTRICT = 3, K_SWEEP = 4,
-  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7, K_LEARNED = 8, K_TRANSFER = 9
+  K_GATHER = 5, K_LATTICE = 6, K_LEVEL_WRITE = 7, K_LEARNED = 8, K_TRANSFER = 9, K_TAIL = 10
 };
 
 // Event-pair timing of individual launches, harvested at the end of a solve.
@@ -401,19 +401,62 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
   return finish_level(h, m, last, next_m, wmode, X[1 - src], X[src], cur, acc, done, s);
 }
 
+// Number of leading schedule entries the coarse tail runs (0: none) and
+// the finest of their levels.  They must start at the coarsest level,
+// descend one level at a time, fit one workgroup's LDS, not be visited
+// again, and hand over to level ms - 1 >= 1 (chained execution, Laplacian,
+// damped Jacobi).
+int tail_levels(const homg_ctx* h, int* ms) {
+  const int np = int(h->sched.size() / 2);
+  if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || np < 3) return 0;
+  if (h->sched[0] != h->top_level) return 0;
+  int cnt = 0;
+  for (int p = 0; p + 1 < np; ++p) {
+    const int m = h->sched[2 * p];
+    if (m != h->top_level - p || m < 2) break;
+    const int nm = (h->n - 1) / (1 << m) + 1;
+    if (coarse_tail_lds(h->prec, h->d, nm, p + 1) > h->lds_limit) break;
+    if (h->sched[2 * (p + 1)] != m - 1) {  // the next entry must receive the hand-over
+      cnt = p + 1;
+      break;
+    }
+    cnt = p + 1;
+  }
+  // the last fused level must be followed by level ms - 1
+  while (cnt >= 2 && h->sched[2 * cnt] != h->sched[2 * (cnt - 1)] - 1) --cnt;
+  if (cnt < 2) return 0;
+  *ms = h->sched[2 * (cnt - 1)];
+  for (int p = cnt; p < np; ++p)
+    if (h->sched[2 * p] > *ms) return 0;  // a fused level is visited again
+  return cnt;
+}
+
 // Enqueue one MFMG cycle (Sec. 2): restriction pyramid of r_0, the
 // schedule's whole-grid iterations with the last one adding e into acc,
 // then (if f != null) the new residual and its norm as history[cycle].
 homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, const int* done,
                           hipStream_t s) {
-  for (int m = 0; m < h->top_level; ++m)
+  int ms = 0;
+  const int ntail = tail_levels(h, &ms);
+  for (int m = 0; m < (ntail ? ms : h->top_level); ++m)
     LAUNCH_K(h, s, K_RESTRICT, m, 0,
              launch_restrict(h->prec, h->d, h->r[m], h->rl[m], h->r[m + 1], h->rl[m + 1], done, s));
   int cur = 0;
   const Lay none;
   const size_t np = h->sched.size() / 2;
   h->chain_ready = -1;
-  for (size_t p = 0; p < np; ++p) {
+  size_t p0 = 0;
+  if (ntail) {
+    int its[BATCH_MAX_LEVELS];
+    for (int k = 0; k < ntail; ++k) its[k] = h->sched[2 * (ntail - 1 - k) + 1];
+    const int nms = (h->n - 1) / (1 << ms) + 1;
+    LAUNCH_K(h, s, K_TAIL, ms, 0,
+             launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms],
+                                h->xc[2 * (ms - 1)], h->rl[ms - 1], done, s));
+    h->chain_ready = ms - 1;
+    p0 = size_t(ntail);
+  }
+  for (size_t p = p0; p < np; ++p) {
     const int m = h->sched[2 * p], it = h->sched[2 * p + 1];
     // the next level, if it starts from a compact x_0 (blocked coarse level)
     int next_m = -1;

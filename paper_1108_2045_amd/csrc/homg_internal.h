@@ -129,6 +129,16 @@ hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double o
                                 const void* e, const Lay& el, const void* rm, const Lay& rl,
                                 const double* am, const Lay& al, void* xprev, void* xcur,
                                 const Lay& cl, const int* done, hipStream_t s);
+// Coarse tail (chained execution, Laplacian, damped Jacobi): levels ms ..
+// ms + nlev - 1 of a schedule that starts at the coarsest of them and
+// descends one level at a time, run by one workgroup in LDS: restriction
+// of r_ms (side nms, layout rl) to the coarser levels, its[k] iterations of
+// level ms + k, and the hand-over of level ms's final state to the compact
+// x_0 of level ms - 1 (dst, layout tl).  coarse_tail_lds: its LDS bytes.
+size_t coarse_tail_lds(int prec, int d, int nms, int nlev);
+hipError_t launch_coarse_tail(int prec, int d, int nms, int nlev, const int* its, double omega,
+                              const void* rms, const Lay& rl, void* dst, const Lay& tl,
+                              const int* done, hipStream_t s);
 // LDS bytes of the whole-grid pass of level m.
 size_t level_write_lds(int prec, int d, int n, int m);
 // Whole-grid pass of level m from compact x_{it-1} (xprev) and x_it (xcur):

@@ -1349,6 +1349,167 @@ __global__ __launch_bounds__(256) void k_level_transfer_3d(
   st(dst + int64_t(K) * dpl + int64_t(J) * dp + I, v);
 }
 
+// ------------------------------------------------------------ coarse tail
+// The schedule's leading coarse levels ms .. M (descending one level at a
+// time, each visited once) in one workgroup, everything in LDS: the
+// restriction of r_ms to the coarser levels, each level's iterations from
+// the state the previous level hands over (0 on the coarsest), and the
+// hand-over itself -- the values the level's whole-grid pass would leave at
+// the lattice nodes of the next finer level.  The last hand-over goes to
+// the compact x_0 of level ms - 1 in memory.  The node formulas and the
+// rounding points are those of the restriction, small-lattice and transfer
+// kernels, so the result is theirs bit for bit.  Level ms + k has side
+// nk = ((nms - 1) >> k) + 1; LDS holds, per level, r and two iterates.
+struct TailIts {
+  int it[BATCH_MAX_LEVELS];  // iterations of level ms + k
+};
+
+template <int D>
+__device__ __forceinline__ int tail_count(int nk) { return D == 2 ? nk * nk : nk * nk * nk; }
+
+// i -> (I, J, K) in a box of side s (x fastest); a single-precision
+// reciprocal is exact here: i < 2^24 and (i + 1/2) / s stays at least
+// 1/(2 s) away from an integer.
+template <int D>
+__device__ __forceinline__ void tail_split(int i, int s, float inv_s, int& I, int& J, int& K) {
+  const int q = int((float(i) + 0.5f) * inv_s);
+  I = i - q * s;
+  if (D == 2) {
+    J = q;
+    K = 0;
+  } else {
+    K = int((float(q) + 0.5f) * inv_s);
+    J = q - K * s;
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
+    const T* __restrict__ rms, int64_t rp, int64_t rpl, T* __restrict__ dst, int64_t dp, int64_t dpl,
+    int nms, int nlev, TailIts its, typename Tr<T>::C w, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* base = reinterpret_cast<C*>(smem);
+  auto side = [&](int k) { return ((nms - 1) >> k) + 1; };
+  // per level: R (r), P (x_0 and odd-numbered iterates' sources), Q
+  auto lvl = [&](int k, int which) {
+    C* p = base;
+    for (int j = 0; j < k; ++j) p += 3 * tail_count<D>(side(j));
+    return p + which * tail_count<D>(side(k));
+  };
+  for (int k = 0; k < nlev; ++k) {
+    const int cnt = tail_count<D>(side(k));
+    C* R = lvl(k, 0);
+    C* P = lvl(k, 1);
+    C* Q = lvl(k, 2);
+    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) R[i] = P[i] = Q[i] = C(0);
+  }
+  __syncthreads();
+  {
+    C* R = lvl(0, 0);
+    const int cnt = tail_count<D>(nms);
+    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+      const int I = i % nms, J = (i / nms) % nms, K = D == 3 ? i / (nms * nms) : 0;
+      const bool inner = I > 0 && I < nms - 1 && J > 0 && J < nms - 1 && (D == 2 || (K > 0 && K < nms - 1));
+      R[i] = inner ? ld(rms + int64_t(K) * rpl + int64_t(J) * rp + I) : C(0);
+    }
+  }
+  __syncthreads();
+  // restriction pyramid (full weighting, as k_restrict_*)
+  for (int k = 1; k < nlev; ++k) {
+    const int nf = side(k - 1), nc = side(k), ni = nc - 2, cnt = tail_count<D>(ni);
+    const float inv = 1.0f / float(ni);
+    const C* F = lvl(k - 1, 0);
+    C* R = lvl(k, 0);  // boundary nodes stay 0
+    const int fp = nf, fpl = nf * nf;
+    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
+      int I, J, K;
+      tail_split<D>(i, ni, inv, I, J, K);
+      ++I, ++J, K += D == 3;
+      auto rs = [&](int q) { return fmac(C(2), F[q], F[q - 1] + F[q + 1]); };
+      C v;
+      if (D == 2) {
+        const int q = 2 * J * fp + 2 * I;
+        const C top = rs(q - fp), mid = rs(q), bot = rs(q + fp);
+        v = fmac(C(2), mid, top + bot) * C(0.0625);
+      } else {
+        auto ps = [&](int q) { return fmac(C(2), rs(q), rs(q - fp) + rs(q + fp)); };
+        const int q = 2 * K * fpl + 2 * J * fp + 2 * I;
+        const C top = ps(q - fpl), mid = ps(q), bot = ps(q + fpl);
+        v = fmac(C(2), mid, top + bot) * C(0.015625);
+      }
+      R[(D == 3 ? K * nc * nc : 0) + J * nc + I] = rnd<T>(v);
+    }
+    __syncthreads();
+  }
+  // levels from the coarsest down
+  for (int k = nlev - 1; k >= 0; --k) {
+    const int nk = side(k), pl = nk * nk;
+    const double h = 1.0 / double(nk - 1);
+    const C hl2 = C(h * h);
+    const C* R = lvl(k, 0);
+    C* xa = lvl(k, 1);
+    C* xb = lvl(k, 2);
+    const int it = its.it[k];
+    const int ni = nk - 2, icnt = tail_count<D>(ni);
+    const float inv = 1.0f / float(ni);
+    for (int t = 1; t <= it; ++t) {
+      const C* src = (t & 1) ? xa : xb;
+      C* dstl = (t & 1) ? xb : xa;
+      for (int j = threadIdx.x; j < icnt; j += SMALL_NT) {
+        int I, J, K;
+        tail_split<D>(j, ni, inv, I, J, K);
+        const int i = (D == 3 ? (K + 1) * pl : 0) + (J + 1) * nk + (I + 1);
+        const C c = src[i];
+        C v;
+        if (D == 2)
+          v = relax_const<C>(c, (src[i - 1] + src[i + 1]) + (src[i - nk] + src[i + nk]), R[i], w, hl2, C(4));
+        else
+          v = relax_const<C>(c, ((src[i - 1] + src[i + 1]) + (src[i - nk] + src[i + nk])) + (src[i - pl] + src[i + pl]),
+                             R[i], w, hl2, C(6));
+        dstl[i] = rnd<T>(v);
+      }
+      __syncthreads();
+    }
+    const C* cur = (it & 1) ? xb : xa;
+    const C* prv = (it & 1) ? xa : xb;
+    // hand-over to level ms + k - 1 (side nt = 2 nk - 1): lattice nodes of
+    // this level take x_it, the others the interpolant of x_{it-1}
+    const int nt = 2 * nk - 1, ptl = nt * nt, nti = nt - 2;
+    C* tgt = k > 0 ? lvl(k - 1, 1) : nullptr;
+    const int tcnt = tail_count<D>(nti);
+    const float tinv = 1.0f / float(nti);
+    for (int j = threadIdx.x; j < tcnt; j += SMALL_NT) {
+      int I, J, K;
+      tail_split<D>(j, nti, tinv, I, J, K);
+      ++I, ++J, K += D == 3;
+      const int i = (D == 3 ? K * ptl : 0) + J * nt + I;
+      const int xi = I >> 1, yj = J >> 1, zk = K >> 1;
+      const C tx = C(I & 1) * C(0.5), ty = C(J & 1) * C(0.5), tz = C(K & 1) * C(0.5);
+      const int c0 = (D == 3 ? zk * pl : 0) + yj * nk + xi;
+      C v;
+      if (!(I & 1) && !(J & 1) && !(K & 1)) {
+        v = cur[c0];
+      } else if (D == 2) {
+        const C top = lerp(prv[c0], prv[c0 + 1], tx), bot = lerp(prv[c0 + nk], prv[c0 + nk + 1], tx);
+        v = lerp(top, bot, ty);
+      } else {
+        const C* p = prv + c0;
+        const C* q = p + pl;
+        const C top = lerp(lerp(p[0], p[1], tx), lerp(p[nk], p[nk + 1], tx), ty);
+        const C bot = lerp(lerp(q[0], q[1], tx), lerp(q[nk], q[nk + 1], tx), ty);
+        v = lerp(top, bot, tz);
+      }
+      if (k > 0)
+        tgt[i] = rnd<T>(v);
+      else
+        st(dst + int64_t(K) * dpl + int64_t(J) * dp + I, v);
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ pack / unpack
 
 template <typename T>
@@ -1842,6 +2003,49 @@ static hipError_t small_tz(int d, int nm, int l, int it, double omega, const voi
   HOMG_LAUNCH_SMEM((k_lattice_small_3d<T, ZERO>), dim3(1), dim3(SMALL_NT), lds, s, ee, el.pitch,
                    el.plane, l, r, rl.pitch, rl.plane, xp, xc, cl.pitch, cl.plane, nm, it,
                    C(omega / 6.0), hl2, done);
+}
+
+size_t coarse_tail_lds(int prec, int d, int nms, int nlev) {
+  const size_t cs = prec == PREC_F64 ? 8 : 4;
+  size_t cnt = 0;
+  for (int k = 0; k < nlev; ++k) {
+    const size_t nk = size_t((nms - 1) >> k) + 1;
+    cnt += 3 * (d == 2 ? nk * nk : nk * nk * nk);
+  }
+  return cnt * cs;
+}
+
+template <typename T>
+static hipError_t tail_t(int d, int nms, int nlev, const int* its, double omega, const void* rms,
+                         const Lay& rl, void* dst, const Lay& tl, const int* done, hipStream_t s) {
+  using C = typename Tr<T>::C;
+  TailIts ti{};
+  for (int k = 0; k < nlev; ++k) ti.it[k] = its[k];
+  const size_t lds = coarse_tail_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, nms, nlev);
+  const T* r = static_cast<const T*>(rms) + rl.off;
+  T* o = static_cast<T*>(dst) + tl.off;
+  if (d == 2) {
+    hipError_t a = allow_lds(k_coarse_tail<T, 2>, lds);
+    if (a != hipSuccess) return a;
+    HOMG_LAUNCH_SMEM((k_coarse_tail<T, 2>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
+                     tl.pitch, tl.plane, nms, nlev, ti, C(omega / 4.0), done);
+  }
+  hipError_t a = allow_lds(k_coarse_tail<T, 3>, lds);
+  if (a != hipSuccess) return a;
+  HOMG_LAUNCH_SMEM((k_coarse_tail<T, 3>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
+                   tl.pitch, tl.plane, nms, nlev, ti, C(omega / 6.0), done);
+}
+
+hipError_t launch_coarse_tail(int prec, int d, int nms, int nlev, const int* its, double omega,
+                              const void* rms, const Lay& rl, void* dst, const Lay& tl,
+                              const int* done, hipStream_t s) {
+  if (nms < 5 || nlev < 1 || nlev > BATCH_MAX_LEVELS || ((nms - 1) >> (nlev - 1)) + 1 < 3)
+    return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return tail_t<double>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s);
+    case PREC_F32: return tail_t<float>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s);
+    default: return tail_t<bf16>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s);
+  }
 }
 
 hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double omega, bool zero,

@@ -58,7 +58,7 @@ class KernelTime(ctypes.Structure):
 
 
 KIND_NAMES = {0: "norm", 1: "residual", 2: "finalize", 3: "restrict", 4: "sweep",
-              5: "gather", 6: "lattice", 7: "level_write", 8: "learned", 9: "transfer"}
+              5: "gather", 6: "lattice", 7: "level_write", 8: "learned", 9: "transfer", 10: "tail"}
 
 
 def load_library(path=LIB_PATH):
