@@ -92,6 +92,24 @@ void free_batch(homg_batch_ctx* b) {
 }
 
 // Tile rows (the walked length of a tile) of the fine-grid stages.
+// The iteration stages of one cycle (levels M .. 0, n_m = min(2^(M-m+1),
+// MaxI) iterations each): one stage per coarse iteration, level 0 in stages
+// of up to TB_MAX_IT iterations (a multi-iteration pass).  Each entry is
+// level | iterations << 8.
+std::vector<int> stage_codes(int L, int max_i) {
+  std::vector<int> codes;
+  const int M = L - 1;
+  for (int m = M; m >= 0; --m) {
+    const int it = std::min(1 << std::min(M - m + 1, 30), max_i);
+    if (m == 0) {
+      for (int t0 = 0; t0 < it; t0 += TB_MAX_IT) codes.push_back(std::min(TB_MAX_IT, it - t0) << 8);
+    } else {
+      for (int t = 0; t < it; ++t) codes.push_back(m | (1 << 8));
+    }
+  }
+  return codes;
+}
+
 int rows_for(const homg_batch_ctx* b, int side) {
   auto it = b->tile_rows.find(side);
   if (it != b->tile_rows.end() && it->second > 0) return std::min(it->second, side - 2);
@@ -196,9 +214,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     p.part = take(sizeof(double) * size_t(batch_tiles(n, 1)));
     p.hist = take(sizeof(double) * size_t(b->max_cycles + 1));
     const int M = L - 1;
-    int sweeps = 0;
-    for (int m = M; m >= 0; --m) sweeps += std::min(1 << std::min(M - m + 1, 30), b->max_i);
-    max_cycle_len = std::max(max_cycle_len, M + sweeps + 2);
+    max_cycle_len = std::max(max_cycle_len, M + int(stage_codes(L, b->max_i).size()) + 2);
   }
   b->max_steps = 4 + (b->max_cycles + 1) * max_cycle_len;
   homg_status st = HOMG_OK;
@@ -243,14 +259,9 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     q.levels = L;
     q.top = L - 1;
     q.sched_off = int(b->sweep_levels.size());
-    const int M = L - 1;
-    int sw = 0;
-    for (int m = M; m >= 0; --m) {
-      const int it = std::min(1 << std::min(M - m + 1, 30), b->max_i);
-      for (int t = 0; t < it; ++t) b->sweep_levels.push_back(m);
-      sw += it;
-    }
-    q.sweeps = sw;
+    const std::vector<int> codes = stage_codes(L, b->max_i);
+    b->sweep_levels.insert(b->sweep_levels.end(), codes.begin(), codes.end());
+    q.sweeps = int(codes.size());
     q.id = i;
   }
   if (hipMalloc(reinterpret_cast<void**>(&b->d_sweep_levels), sizeof(int) * b->sweep_levels.size()) != hipSuccess ||

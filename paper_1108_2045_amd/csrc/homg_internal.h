@@ -81,7 +81,10 @@ hipError_t launch_sweep(int prec, int d, int n, int m, double omega, const void*
 // single-iteration kernels from 129^2 up, 1.4-2.8x).
 constexpr int TB_MAX_IT = 4;
 constexpr int TB_MIN_WAVES = 4096;
-int tb_waves(int n, int it, int len);
+__host__ __device__ inline int tb_waves(int n, int it, int len) {
+  const int valid = 64 - 2 * it;
+  return ((n - 2 + valid - 1) / valid) * ((n - 2 + len - 1) / len);
+}
 int tb_band(int n, int it);
 hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
                                  const Lay& el, const void* rm, const Lay& rl, double* u,

@@ -625,18 +625,16 @@ __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict
   }
 }
 
+// Wave wv of the pass (waves numbered x-band fastest).
 template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT>
 __device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict__ en,
                                         T* __restrict__ eprev, int64_t ep, const T* __restrict__ r,
                                         int64_t rp, double* __restrict__ u, int64_t up, int n, int len,
-                                        typename Tr<T>::C w, typename Tr<T>::C hl2) {
+                                        typename Tr<T>::C w, typename Tr<T>::C hl2, int wv) {
   using C = typename Tr<T>::C;
   constexpr int VALID = 64 - 2 * IT;
   const int lane = threadIdx.x & 63;
   const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + len - 1) / len;
-  // XCD order: the waves of one XCD are neighbours (their overlapping
-  // columns and rows meet in that XCD's L2)
-  const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
   if (wv >= gx * gy) return;  // the whole wave
   const int x = 1 + (wv % gx) * VALID - IT + lane;
   const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);
@@ -664,7 +662,10 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
     double* __restrict__ u, int64_t up, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
     const int* __restrict__ done) {
   if (*done) return;
-  tb_body<T, ZERO, ACCUM, false, IT>(eo, en, nullptr, ep, r, rp, u, up, n, len, w, hl2);
+  // XCD order: the waves of one XCD are neighbours (their overlapping
+  // columns and rows meet in that XCD's L2)
+  const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
+  tb_body<T, ZERO, ACCUM, false, IT>(eo, en, nullptr, ep, r, rp, u, up, n, len, w, hl2, wv);
 }
 
 // The same pass over the compact lattice of a coarse level (n = its side),
@@ -676,7 +677,8 @@ __global__ __launch_bounds__(256) void k_lattice_2d_tb(
     const T* __restrict__ r, int64_t rp, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
     const int* __restrict__ done) {
   if (*done) return;
-  tb_body<T, ZERO, false, PREV, IT>(eo, en, eprev, ep, r, rp, nullptr, 0, n, len, w, hl2);
+  const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
+  tb_body<T, ZERO, false, PREV, IT>(eo, en, eprev, ep, r, rp, nullptr, 0, n, len, w, hl2, wv);
 }
 
 // Levels m >= 1: lattice nodes relax, the rest interpolate.  The lane keeps
@@ -1793,11 +1795,6 @@ hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const vo
   }
 }
 
-int tb_waves(int n, int it, int len) {
-  const int valid = 64 - 2 * it;
-  return ((n - 2 + valid - 1) / valid) * ((n - 2 + len - 1) / len);
-}
-
 int tb_band(int n, int it) {
   for (int len : {64, 32, 16})
     if (tb_waves(n, it, len) >= TB_MIN_WAVES) return len;
@@ -2171,11 +2168,12 @@ struct StageInfo {
   int sweep;  // sweep index within the cycle
   int cycle;
   int step;   // step of the persistent loop
+  int count;  // sweep: iterations in the stage (several: a multi-iteration level-0 pass)
 };
 enum { BK_NONE = 0, BK_NORM = 1, BK_FNORM = 2, BK_RES = 3, BK_FIN = 4, BK_RESTRICT = 5, BK_SWEEP = 6 };
 
 __device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* __restrict__ levels_of_sweep, int k) {
-  StageInfo si{BK_NONE, 0, 0, 0, 0, 0};
+  StageInfo si{BK_NONE, 0, 0, 0, 0, 0, 1};
   if (k == 0) { si.kind = BK_NORM; return si; }
   if (k == 1) { si.kind = BK_FNORM; return si; }
   if (k == 2) { si.kind = BK_RES; return si; }
@@ -2187,7 +2185,9 @@ __device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* 
   if (j < p.top + p.sweeps) {
     si.kind = BK_SWEEP;
     si.sweep = j - p.top;
-    si.level = levels_of_sweep[p.sched_off + si.sweep];
+    const int code = levels_of_sweep[p.sched_off + si.sweep];
+    si.level = code & 0xff;
+    si.count = code >> 8;
     si.mode = (si.sweep == 0 ? SW_ZERO_OLD : 0) | (si.sweep == p.sweeps - 1 ? SW_ACCUM : 0);
     return si;
   }
@@ -2195,11 +2195,17 @@ __device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* 
   return si;
 }
 
+// Band length of a problem's multi-iteration level-0 stage: its tuned walk
+// length, at least 16 rows (shorter bands re-read too many halo rows).
+__host__ __device__ __forceinline__ int batch_tb_len(const BatchProblem& p) { return p.len[0] < 16 ? 16 : p.len[0]; }
+
 __device__ __forceinline__ int stage_tiles(const BatchProblem& p, const StageInfo& si) {
   switch (si.kind) {
+    case BK_SWEEP:
+      if (si.count > 1) return (tb_waves(p.n, si.count, batch_tb_len(p)) + 3) / 4;
+      return tiles_of(p.n, p.len[0]);
     case BK_NORM:
-    case BK_RES:
-    case BK_SWEEP: return tiles_of(p.n, p.len[0]);
+    case BK_RES: return tiles_of(p.n, p.len[0]);
     case BK_RESTRICT: {
       const int nc = (p.n - 1) / (2 << si.level) + 1;
       return nc >= 3 ? tiles_of(nc, p.len[si.level + 1]) : 0;
@@ -2275,6 +2281,26 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
       const double hl = double(1 << m) / double(n - 1);
       const C hl2 = C(hl * hl), w = C(run.omega / 4.0);
       const T* rm = static_cast<const T*>(p.r[m]);
+      if (si.count > 1) {  // several level-0 iterations in one stage (multi-iteration pass)
+        const int len = batch_tb_len(p), wv = t * 4 + int(threadIdx.x >> 6);
+#define BATCH_TB(Z, A, IT)                                                                      \
+  tb_body<T, Z, A, false, IT>(eo, en, nullptr, p.ep, rm, p.rp[0], p.u, n, n, len, w, hl2, wv)
+#define BATCH_TB_IT(Z, A)                                               \
+  switch (si.count) {                                                   \
+    case 2: BATCH_TB(Z, A, 2); break;                                   \
+    case 3: BATCH_TB(Z, A, 3); break;                                   \
+    default: BATCH_TB(Z, A, 4); break;                                  \
+  }
+        switch (si.mode) {
+          case 0: BATCH_TB_IT(false, false); break;
+          case 1: BATCH_TB_IT(true, false); break;
+          case 2: BATCH_TB_IT(false, true); break;
+          default: BATCH_TB_IT(true, true); break;
+        }
+#undef BATCH_TB_IT
+#undef BATCH_TB
+        break;
+      }
 #define BATCH_SWEEP(MODE)                                                                          \
   if (m == 0)                                                                                      \
     tile_sweep_2d_l0<T, MODE, false>(eo, en, p.ep, rm, p.rp[m], nullptr, 0, p.u, n, n, p.len[0], w, \
