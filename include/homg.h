@@ -219,12 +219,13 @@ homg_status homg_get_profile(homg_handle h, homg_kernel_time *out, int cap, int 
 
 /*
  * Batched solver: many independent 2D Poisson problems (5-point, zero
- * Dirichlet) of uneven sides, solved in ONE persistent kernel launch
- * (captured once in a HIP graph and replayed).  All problems advance in
- * lockstep steps of their own MFMG sequence (Sec. 2); each retires when
- * its relative residual reaches tol.  Precision, omega, MaxI and
- * max_cycles come from opt (schedule and temporal_block are ignored: one
- * whole-grid kernel tile per iteration).
+ * Dirichlet) of uneven sides, solved together.  All problems advance in
+ * lockstep steps of their own MFMG sequence (Sec. 2), one kernel launch per
+ * step for all of them (the launches captured once in a HIP graph of 64
+ * steps, replayed until every problem has retired); each retires when its
+ * relative residual reaches tol.  Precision, omega, MaxI and max_cycles
+ * come from opt (schedule and temporal_block are ignored: coarse levels one
+ * whole-grid pass per iteration, level 0 in multi-iteration passes).
  *
  * homg_batch_create: count >= 1 problems with sides[i] = 2^k + 1, 3 <= side
  *   <= 32769 and at most 16 levels; allocates one device arena for all of
@@ -235,8 +236,7 @@ homg_status homg_get_profile(homg_handle h, homg_kernel_time *out, int cap, int 
  *   `count` entries each, may be NULL) receive each problem's final relative
  *   residual, cycles and homg_status.  Returns HOMG_OK if every problem
  *   converged, HOMG_ERR_NOT_CONVERGED / HOMG_ERR_NUMERICAL if any did not,
- *   HOMG_ERR_HIP if the persistent launch had to abort (a grid barrier
- *   outwaited its time limit).  Synchronises the stream.
+ *   HOMG_ERR_HIP on a runtime failure.  Synchronises the stream.
  * homg_batch_set_tile_rows: rows per tile (the tile shape of the
  *   fine-grid stages) for all problems of side `side`; 0 restores the
  *   default.  homg_batch_tune picks them by timing candidate shapes on the

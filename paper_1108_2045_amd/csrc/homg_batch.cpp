@@ -1,14 +1,16 @@
-// homg_batch.cpp -- batched persistent HOMG solver: C ABI, arena, graph.
+// homg_batch.cpp -- batched HOMG solver: C ABI, arena, graph.
 //
-// Many independent 2D problems of uneven size are solved by one persistent
-// kernel (k_batched_2d): every problem walks its own MFMG sequence (Sec. 2
-// of arXiv:1108.2045: residual, restriction pyramid, fused relax+interpolate
-// iterations, restart) in lockstep steps separated by a grid barrier.  The
-// launch (state reset + persistent kernel) is captured once into a HIP
-// graph on an internal stream and replayed on the caller's stream; the
+// Many independent 2D problems of uneven size advance together: every
+// problem walks its own MFMG sequence (Sec. 2 of arXiv:1108.2045: residual,
+// restriction pyramid, fused relax+interpolate iterations, restart) one
+// stage per step, and one launch runs a step for all problems at once (the
+// tiles of every active problem's stage, one workgroup each).  A HIP graph
+// of 64 step launches and the advance of the step counter is built once
+// and replayed on the caller's stream until no problem is active; the
 // per-call inputs (array pointers, tolerance) live in device descriptors
-// uploaded before each replay, so the graph never changes.  The persistent
-// node is a cooperative launch, so all its workgroups are resident at once.
+// uploaded before each solve, so the graph never changes.  (A persistent
+// kernel with a grid barrier per step was measured slower on MI355X: one
+// barrier costs 40-170 us against a few us per graph node.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,7 +47,6 @@ struct homg_batch_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int grid = 0, device = 0;
-  uint64_t barrier_ticks = 0;
   int max_steps = 0;
   std::string err;
 };
@@ -127,7 +128,7 @@ homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u
     b->h_probs[i].f = f[i];
     b->h_probs[i].u = u[i];
   }
-  *b->h_run = BatchRun{tol, b->omega, b->count, b->max_cycles, b->max_steps, 0, b->barrier_ticks};
+  *b->h_run = BatchRun{tol, b->omega, b->count, b->max_cycles, b->max_steps, 0};
   BHIP(b, hipMemcpyAsync(b->d_probs, b->h_probs, sizeof(BatchProblem) * b->count,
                          hipMemcpyHostToDevice, s));
   BHIP(b, hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
@@ -140,14 +141,18 @@ homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u
     b->graph = g;
     BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
-  BHIP(b, hipGraphLaunch(b->exec, s));
+  BHIP(b, launch_batch_init(b->count, b->d_state, b->d_done, b->d_sync, s));
+  // replays of 64 steps until a step finds no active problem (or the step
+  // bound of max_cycles is reached)
+  for (int done_steps = 0; done_steps < b->max_steps; done_steps += BATCH_STEPS_PER_REPLAY) {
+    BHIP(b, hipGraphLaunch(b->exec, s));
+    BHIP(b, hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, s));
+    BHIP(b, hipStreamSynchronize(s));
+    if (b->h_sync->idle) break;
+  }
   BHIP(b, hipMemcpyAsync(b->h_state, b->d_state, sizeof(BatchState) * b->count, hipMemcpyDeviceToHost, s));
   BHIP(b, hipMemcpyAsync(b->h_done, b->d_done, sizeof(int) * b->count, hipMemcpyDeviceToHost, s));
-  BHIP(b, hipMemcpyAsync(b->h_sync, b->d_sync, sizeof(BatchSync), hipMemcpyDeviceToHost, s));
   BHIP(b, hipStreamSynchronize(s));
-  if (b->h_sync->abort)
-    return bfail(b, HOMG_ERR_HIP, "persistent batched launch aborted: a grid barrier exceeded its time limit (grid " +
-                                      std::to_string(b->grid) + " workgroups, step " + std::to_string(b->h_sync->steps) + ")");
   return HOMG_OK;
 }
 
@@ -271,24 +276,17 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     free_batch(b);
     return bfail(nullptr, HOMG_ERR_OOM, "schedule table allocation failed");
   }
-  int per_cu = 0, cus = 0, clock_khz = 0;
+  int per_cu = 0, cus = 0;
   size_t lds = 0;
   if (batch_occupancy(b->prec, count, &per_cu, &lds) != hipSuccess || per_cu < 1 ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
-      hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, b->device) != hipSuccess) {
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
     (void)hipGetLastError();
     free_batch(b);
-    return bfail(nullptr, HOMG_ERR_HIP, "cannot size the persistent launch");
+    return bfail(nullptr, HOMG_ERR_HIP, "cannot size the step launches");
   }
-  // Every workgroup must be resident for the grid barrier.  The kernel's
-  // scalar registers (106 per wave) already hold it to 7 workgroups of 4
-  // waves per CU, and a grid of the full occupancy answer was seen to stall
-  // at the barrier; half of it keeps every workgroup resident with room to
-  // spare (tiles are taken round-robin, so fewer workgroups only lengthen
-  // their walks).
-  b->grid = std::max(1, per_cu / 2) * cus;
-  // one barrier wait may not exceed 5 s of wall clock
-  b->barrier_ticks = uint64_t(std::max(clock_khz, 1)) * 1000ull * 5ull;
+  // one resident wave of workgroups per step launch; they take the step's
+  // tiles round-robin
+  b->grid = per_cu * cus;
   (void)st;
   if (hipDeviceSynchronize() != hipSuccess) {
     free_batch(b);
@@ -381,7 +379,7 @@ homg_status homg_batch_tune(homg_batch b, const double* const* f, double* const*
     const int side = *it;
     const int keep = rows_for(b, side);
     int best_rows = keep;
-    for (int rows : {4, 8, 16, 32, 64}) {
+    for (int rows : {4, 8, 16, 32, 64, 128}) {
       if (rows == keep || rows > side - 2) continue;
       b->tile_rows[side] = rows;
       float ms = 0.f;

@@ -179,18 +179,23 @@ struct BatchState {
 struct BatchRun {
   double tol, omega;
   int count, max_cycles, max_steps, pad;
-  uint64_t barrier_ticks;     // wall-clock limit of one barrier wait (100 MHz ticks)
 };
+// Step counter of a batched solve: step kernel j of a replay runs step
+// base + j; the replay's last node advances base.  idle: a step found no
+// active problem (every later step returns at once).
 struct BatchSync {
-  unsigned count, gen;
-  int abort, steps;
+  int base, steps, idle, pad;
 };
+// Workgroups of one step launch; graph nodes (steps) per replay.
+constexpr int BATCH_STEPS_PER_REPLAY = 64;
 hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds);
 int default_walk_len(int d, int n);
 int batch_tiles(int side, int len);
-hipError_t launch_batch(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs, int* done,
-                        const int* levels_of_sweep, const BatchRun* run, BatchSync* sync,
-                        hipStream_t s);
+// Reset of the per-solve state (problem states, done flags, step counter).
+hipError_t launch_batch_init(int P, BatchState* bs, int* done, BatchSync* sync, hipStream_t s);
+// Graph of BATCH_STEPS_PER_REPLAY step kernels (steps base .. base + S - 1 of
+// every problem's sequence, each tile of a step one workgroup) and the
+// advance of base.
 hipError_t build_batch_graph(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs,
                              int* done, const int* levels_of_sweep, const BatchRun* run,
                              BatchSync* sync, hipGraph_t* out);

@@ -2322,97 +2322,74 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
   }
 }
 
-// Grid-wide barrier for co-resident workgroups (sense by generation count).
-// Returns false if the launch was aborted (a wait exceeded its time limit).
-__device__ bool grid_barrier(unsigned* count, unsigned* gen, unsigned nblocks, int* abort,
-                             uint64_t limit_ticks) {
-  __shared__ int ok;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (wall_clock64() - t0 > limit_ticks) {
-          __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(4);
-      }
-    }
-    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-  }
-  __syncthreads();
-  __threadfence();
-  return ok != 0;
-}
-
+// One step of every active problem's sequence: k = base + j.  Every
+// workgroup builds the same tile map (prefix sums of the active problems'
+// tile counts for their stage at step k) and takes the tiles g = blockIdx.x,
+// blockIdx.x + gridDim.x, ...  A problem is active in step k unless it
+// retired in an earlier step; the step that retires it is written by its
+// finalize tile while other workgroups may be building this step's map,
+// and either value they read keeps it in this step, so all maps agree.
 template <typename T>
-__global__ __launch_bounds__(256) void k_batched_2d(const BatchProblem* __restrict__ probs,
-                                                    BatchState* __restrict__ bs,
-                                                    int* __restrict__ done,
-                                                    const int* __restrict__ levels_of_sweep,
-                                                    const BatchRun* __restrict__ runp,
-                                                    BatchSync* __restrict__ sync) {
+__global__ __launch_bounds__(256) void k_batched_step(const BatchProblem* __restrict__ probs,
+                                                      BatchState* __restrict__ bs,
+                                                      int* __restrict__ done,
+                                                      const int* __restrict__ levels_of_sweep,
+                                                      const BatchRun* __restrict__ runp,
+                                                      BatchSync* __restrict__ sync, int j) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (sync->idle) return;
   const BatchRun run = *runp;
+  const int k = sync->base + j;
+  if (k >= run.max_steps) return;
   const int P = run.count;
   int* pref = reinterpret_cast<int*>(smem);  // P + 1 prefix sums of tile counts
-  for (int k = 0; k < run.max_steps; ++k) {
-    // tile counts of this step, then an inclusive scan (fixed order)
-    // A problem belongs to step k's tile map unless it retired in an
-    // earlier step.  Its retiring step is written while other workgroups
-    // build the map of that step, and either value they may read keeps it
-    // in; after the barrier every workgroup sees it, so all maps agree.
-    for (int i = threadIdx.x; i < P; i += 256) {
-      const BatchProblem& p = probs[i];
-      const int ret = __hip_atomic_load(&bs[i].retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      pref[i + 1] = ret < k ? 0 : stage_tiles(p, stage_of(p, levels_of_sweep, k));
-    }
-    if (threadIdx.x == 0) pref[0] = 0;
-    __syncthreads();
-    // serial scan by chunks: each thread scans its chunk, then offsets
-    const int chunk = (P + 255) / 256;
-    const int lo = threadIdx.x * chunk + 1, hi = min(P, lo + chunk - 1);
-    int acc = 0;
-    for (int i = lo; i <= hi; ++i) { acc += pref[i]; pref[i] = acc; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int off = 0;
-      for (int c = 0; c < 256; ++c) {
-        const int clo = c * chunk + 1, chi = min(P, clo + chunk - 1);
-        if (clo > P) break;
-        const int last = pref[chi];
-        for (int i = clo; i <= chi; ++i) pref[i] += off;
-        off += last;
-      }
-    }
-    __syncthreads();
-    const int total = pref[P];
-    if (total == 0) break;
-    for (int g = blockIdx.x; g < total; g += gridDim.x) {
-      // problem owning global tile g: last i with pref[i] <= g
-      int a = 0, b = P;
-      while (b - a > 1) {
-        const int mid = (a + b) >> 1;
-        if (pref[mid] <= g) a = mid; else b = mid;
-      }
-      const BatchProblem& p = probs[a];
-      StageInfo si = stage_of(p, levels_of_sweep, k);
-      si.step = k;
-      batch_tile<T>(p, bs, done, si, g - pref[a], run);
-      __syncthreads();
-    }
-    if (!grid_barrier(&sync->count, &sync->gen, gridDim.x, &sync->abort, run.barrier_ticks)) break;
-    if (threadIdx.x == 0 && blockIdx.x == 0) sync->steps = k + 1;
+  for (int i = threadIdx.x; i < P; i += 256) {
+    const BatchProblem& p = probs[i];
+    const int ret = __hip_atomic_load(&bs[i].retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pref[i + 1] = ret < k ? 0 : stage_tiles(p, stage_of(p, levels_of_sweep, k));
   }
+  if (threadIdx.x == 0) pref[0] = 0;
+  __syncthreads();
+  // serial scan by chunks: each thread scans its chunk, then offsets
+  const int chunk = (P + 255) / 256;
+  const int lo = threadIdx.x * chunk + 1, hi = min(P, lo + chunk - 1);
+  int acc = 0;
+  for (int i = lo; i <= hi; ++i) { acc += pref[i]; pref[i] = acc; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int c = 0; c < 256; ++c) {
+      const int clo = c * chunk + 1, chi = min(P, clo + chunk - 1);
+      if (clo > P) break;
+      const int last = pref[chi];
+      for (int i = clo; i <= chi; ++i) pref[i] += off;
+      off += last;
+    }
+  }
+  __syncthreads();
+  const int total = pref[P];
+  if (total == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sync->idle = 1;
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) sync->steps = k + 1;
+  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+    // problem owning global tile g: last i with pref[i] <= g
+    int a = 0, b = P;
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (pref[mid] <= g) a = mid; else b = mid;
+    }
+    const BatchProblem& p = probs[a];
+    StageInfo si = stage_of(p, levels_of_sweep, k);
+    si.step = k;
+    batch_tile<T>(p, bs, done, si, g - pref[a], run);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void k_batch_advance(BatchSync* sync, int steps) {
+  if (threadIdx.x == 0) sync->base += steps;
 }
 
 __global__ __launch_bounds__(256) void k_batch_init(BatchState* bs, int* done, int P, BatchSync* sync) {
@@ -2425,10 +2402,9 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchState* bs, int* done, i
     done[i] = 0;
   }
   if (i == 0) {
-    sync->count = 0;
-    sync->gen = 0;
-    sync->abort = 0;
+    sync->base = 0;
     sync->steps = 0;
+    sync->idle = 0;
   }
 }
 
@@ -2442,9 +2418,9 @@ int batch_tiles(int side, int len) {
 hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds) {
   *lds = size_t(P + 1) * sizeof(int);
   switch (prec) {
-    case PREC_F64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_2d<double>, 256, *lds);
-    case PREC_F32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_2d<float>, 256, *lds);
-    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_2d<bf16>, 256, *lds);
+    case PREC_F64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_step<double>, 256, *lds);
+    case PREC_F32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_step<float>, 256, *lds);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_step<bf16>, 256, *lds);
   }
 }
 
@@ -2452,6 +2428,11 @@ hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds) {
 // persistent kernel).  The persistent node carries the cooperative launch
 // attribute: the runtime then places all `grid` workgroups at once (or
 // refuses the launch), which the grid barrier between steps relies on.
+hipError_t launch_batch_init(int P, BatchState* bs, int* done, BatchSync* sync, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init, dim3((P + 255) / 256), dim3(256), 0, s, bs, done, P, sync);
+  return hipGetLastError();
+}
+
 hipError_t build_batch_graph(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs,
                              int* done, const int* levels_of_sweep, const BatchRun* run,
                              BatchSync* sync, hipGraph_t* out) {
@@ -2459,31 +2440,38 @@ hipError_t build_batch_graph(int prec, int P, int grid, const BatchProblem* prob
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
-  void* a0[] = {&bs, &done, &P, &sync};
-  hipKernelNodeParams k0{};
-  k0.func = reinterpret_cast<void*>(k_batch_init);
-  k0.gridDim = dim3((P + 255) / 256);
-  k0.blockDim = dim3(256);
-  k0.sharedMemBytes = 0;
-  k0.kernelParams = a0;
-  hipGraphNode_t n0 = nullptr, n1 = nullptr;
-  e = hipGraphAddKernelNode(&n0, g, nullptr, 0, &k0);
-  void* a1[] = {&probs, &bs, &done, &levels_of_sweep, &run, &sync};
-  hipKernelNodeParams k1{};
+  void* fn = nullptr;
   switch (prec) {
-    case PREC_F64: k1.func = reinterpret_cast<void*>(k_batched_2d<double>); break;
-    case PREC_F32: k1.func = reinterpret_cast<void*>(k_batched_2d<float>); break;
-    default: k1.func = reinterpret_cast<void*>(k_batched_2d<bf16>); break;
+    case PREC_F64: fn = reinterpret_cast<void*>(k_batched_step<double>); break;
+    case PREC_F32: fn = reinterpret_cast<void*>(k_batched_step<float>); break;
+    default: fn = reinterpret_cast<void*>(k_batched_step<bf16>); break;
   }
-  k1.gridDim = dim3(grid);
-  k1.blockDim = dim3(256);
-  k1.sharedMemBytes = unsigned(size_t(P + 1) * sizeof(int));
-  k1.kernelParams = a1;
-  if (e == hipSuccess) e = hipGraphAddKernelNode(&n1, g, &n0, 1, &k1);
+  int js[BATCH_STEPS_PER_REPLAY];
+  hipGraphNode_t prev = nullptr;
+  for (int j = 0; j < BATCH_STEPS_PER_REPLAY && e == hipSuccess; ++j) {
+    js[j] = j;
+    void* args[] = {&probs, &bs, &done, &levels_of_sweep, &run, &sync, &js[j]};
+    hipKernelNodeParams kp{};
+    kp.func = fn;
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = unsigned(size_t(P + 1) * sizeof(int));
+    kp.kernelParams = args;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
   if (e == hipSuccess) {
-    hipKernelNodeAttrValue v{};
-    v.cooperative = 1;
-    e = hipGraphKernelNodeSetAttribute(n1, hipKernelNodeAttributeCooperative, &v);
+    int steps = BATCH_STEPS_PER_REPLAY;
+    void* args[] = {&sync, &steps};
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void*>(k_batch_advance);
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, &prev, 1, &kp);
   }
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
@@ -2491,27 +2479,6 @@ hipError_t build_batch_graph(int prec, int P, int grid, const BatchProblem* prob
   }
   *out = g;
   return hipSuccess;
-}
-
-hipError_t launch_batch(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs, int* done,
-                        const int* levels_of_sweep, const BatchRun* run, BatchSync* sync,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_init, dim3((P + 255) / 256), dim3(256), 0, s, bs, done, P, sync);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t lds = size_t(P + 1) * sizeof(int);
-  switch (prec) {
-    case PREC_F64:
-      hipLaunchKernelGGL((k_batched_2d<double>), dim3(grid), dim3(256), lds, s, probs, bs, done, levels_of_sweep, run, sync);
-      break;
-    case PREC_F32:
-      hipLaunchKernelGGL((k_batched_2d<float>), dim3(grid), dim3(256), lds, s, probs, bs, done, levels_of_sweep, run, sync);
-      break;
-    default:
-      hipLaunchKernelGGL((k_batched_2d<bf16>), dim3(grid), dim3(256), lds, s, probs, bs, done, levels_of_sweep, run, sync);
-      break;
-  }
-  return hipGetLastError();
 }
 
 }  // namespace homg
