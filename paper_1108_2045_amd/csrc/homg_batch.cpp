@@ -94,19 +94,24 @@ void free_batch(homg_batch_ctx* b) {
 
 // Tile rows (the walked length of a tile) of the fine-grid stages.
 // The iteration stages of one cycle (levels M .. 0, n_m = min(2^(M-m+1),
-// MaxI) iterations each): one stage per coarse iteration, level 0 in stages
-// of up to TB_MAX_IT iterations (a multi-iteration pass).  Each entry is
-// level | iterations << 8.
+// MaxI) iterations each, chained as in the single-problem solver): each
+// coarse level's iterations on its compact lattice and its hand-over to
+// the next finer level's lattice (to the whole grid before level 0), then
+// level 0 in passes of up to TB_MAX_IT iterations, the last adding into u.
 std::vector<int> stage_codes(int L, int max_i) {
   std::vector<int> codes;
   const int M = L - 1;
-  for (int m = M; m >= 0; --m) {
-    const int it = std::min(1 << std::min(M - m + 1, 30), max_i);
-    if (m == 0) {
-      for (int t0 = 0; t0 < it; t0 += TB_MAX_IT) codes.push_back(std::min(TB_MAX_IT, it - t0) << 8);
-    } else {
-      for (int t = 0; t < it; ++t) codes.push_back(m | (1 << 8));
-    }
+  auto iters = [&](int m) { return std::min(1 << std::min(M - m + 1, 30), max_i); };
+  for (int m = M; m >= 1; --m) {
+    const int it = iters(m);
+    for (int t = 1; t <= it; ++t) codes.push_back(bst_code(BST_SWEEP, m, 1, t, m == M && t == 1, false));
+    codes.push_back(bst_code(BST_XFER, m, it, 0, m == M && it == 1, false));
+  }
+  const int it0 = iters(0);
+  int q = 0;
+  for (int t0 = 0; t0 < it0; t0 += TB_MAX_IT, ++q) {
+    const int g = std::min(TB_MAX_IT, it0 - t0);
+    codes.push_back(bst_code(BST_L0, 0, g, q, M == 0 && t0 == 0, t0 + g == it0));
   }
   return codes;
 }
@@ -200,7 +205,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     total += (bytes + 255) & ~size_t(255);
     return o2;
   };
-  struct Plan { size_t e[2], r[BATCH_MAX_LEVELS], part, hist; Lay el, rl[BATCH_MAX_LEVELS]; };
+  struct Plan { size_t e[2], r[BATCH_MAX_LEVELS], x[BATCH_MAX_LEVELS][2], part, hist; Lay el, rl[BATCH_MAX_LEVELS]; };
   std::vector<Plan> plans(count);
   int max_cycle_len = 0;
   for (int i = 0; i < count; ++i) {
@@ -215,6 +220,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     for (int m = 0; m < L; ++m) {
       p.rl[m] = padded_layout(2, (n - 1) / (1 << m) + 1, eb);
       p.r[m] = take(size_t(p.rl[m].alloc) * eb);
+      for (int c = 0; c < 2 && m >= 1; ++c) p.x[m][c] = take(size_t(p.rl[m].alloc) * eb);
     }
     p.part = take(sizeof(double) * size_t(batch_tiles(n, 1)));
     p.hist = take(sizeof(double) * size_t(b->max_cycles + 1));
@@ -255,6 +261,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     q.ep = p.el.pitch;
     for (int m = 0; m < L; ++m) {
       q.r[m] = base + p.r[m] + size_t(p.rl[m].off) * eb;
+      for (int c = 0; c < 2 && m >= 1; ++c) q.x[m][c] = base + p.x[m][c] + size_t(p.rl[m].off) * eb;
       q.rp[m] = p.rl[m].pitch;
       q.len[m] = default_walk_len(2, (n - 1) / (1 << m) + 1);
     }

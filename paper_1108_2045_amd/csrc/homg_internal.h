@@ -157,17 +157,39 @@ hipError_t launch_level_transfer(int prec, int d, int m, const void* xprev, cons
                                  const int* done, hipStream_t s);
 // ---- batched persistent solver (2D, constant coefficient)
 constexpr int BATCH_MAX_LEVELS = 16;
-struct BatchProblem {         // one problem, read by the persistent kernel
+// Iteration stages of a batched cycle, one int each in the schedule table:
+// kind (bits 0-3), level (4-8), iterations (9-12), index (13-20), zero
+// (21: the stage starts from e = 0, or a hand-over of a level whose
+// x_{it-1} = 0 was never stored), accum (22: the pass adds into u).
+//   BST_SWEEP: iteration `index` (1-based) of coarse level m on its compact
+//              lattice (ping-pong x[m][0] -> x[m][1] -> ...);
+//   BST_XFER:  hand-over of level m after `iterations` iterations to the
+//              compact x_0 of level m - 1 (to the whole grid e[0] if m = 1);
+//   BST_L0:    level-0 pass `index` of `iterations` iterations (e[index & 1]
+//              -> e[1 - index & 1]).
+enum { BST_SWEEP = 1, BST_XFER = 2, BST_L0 = 3 };
+__host__ __device__ inline int bst_code(int kind, int level, int count, int index, bool zero, bool accum) {
+  return kind | (level << 4) | (count << 9) | (index << 13) | (zero ? 1 << 21 : 0) | (accum ? 1 << 22 : 0);
+}
+__host__ __device__ inline int bst_kind(int c) { return c & 15; }
+__host__ __device__ inline int bst_level(int c) { return (c >> 4) & 31; }
+__host__ __device__ inline int bst_count(int c) { return (c >> 9) & 15; }
+__host__ __device__ inline int bst_index(int c) { return (c >> 13) & 255; }
+__host__ __device__ inline bool bst_zero(int c) { return (c >> 21) & 1; }
+__host__ __device__ inline bool bst_accum(int c) { return (c >> 22) & 1; }
+
+struct BatchProblem {         // one problem, read by the step kernels
   const double* f;            // caller arrays, dense side n
   double* u;
   void* e[2];                 // internal e ping-pong, pointer at node (0,0)
   void* r[BATCH_MAX_LEVELS];  // residual pyramid, pointer at node (0,0) of each level
+  void* x[BATCH_MAX_LEVELS][2];  // compact iterate pair of each coarse level (layout of r)
   int64_t ep;                 // pitch of e
   int64_t rp[BATCH_MAX_LEVELS];
   int len[BATCH_MAX_LEVELS];  // rows walked per tile on level-m grids (tile shape)
   double* partials;           // per-tile norm sums
   double* history;            // relres after cycles 0..max_cycles
-  int n, levels, top, sweeps; // side, levels, coarsest level visited, iterations per cycle
+  int n, levels, top, sweeps; // side, levels, coarsest level visited, iteration stages per cycle
   int sched_off, id, pad0, pad1;
 };
 struct BatchState {

@@ -1289,14 +1289,13 @@ __global__ __launch_bounds__(256) void k_level_write_3d(
 // node formula and its rounding are those of the level write above, so the
 // chained path matches the whole-grid path bit for bit.  Boundary nodes of
 // the target are never written (they stay 0).
+// Interior node (I, J) of the level-mt lattice (compact, pitch dp): the
+// value the level-m whole-grid pass would leave there.
 template <typename T, bool ZERO>
-__global__ __launch_bounds__(256) void k_level_transfer_2d(
-    const T* __restrict__ xprev, const T* __restrict__ xcur, int64_t cp, int m,
-    T* __restrict__ dst, int64_t dp, int nt, int mt, const int* __restrict__ done) {
+__device__ __forceinline__ void transfer_node_2d(const T* __restrict__ xprev, const T* __restrict__ xcur,
+                                                 int64_t cp, int m, T* __restrict__ dst, int64_t dp,
+                                                 int mt, int I, int J) {
   using C = typename Tr<T>::C;
-  if (*done) return;
-  const int I = 1 + blockIdx.x * 256 + threadIdx.x, J = 1 + blockIdx.y;
-  if (I > nt - 2) return;
   const int x = I << mt, y = J << mt;
   const int l = 1 << m, mask = l - 1;
   const C inv_l = C(1) / C(l);
@@ -1318,6 +1317,16 @@ __global__ __launch_bounds__(256) void k_level_transfer_2d(
     v = lerp(top, bot, C(y & mask) * inv_l);
   }
   st(dst + int64_t(J) * dp + I, v);
+}
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(256) void k_level_transfer_2d(
+    const T* __restrict__ xprev, const T* __restrict__ xcur, int64_t cp, int m,
+    T* __restrict__ dst, int64_t dp, int nt, int mt, const int* __restrict__ done) {
+  if (*done) return;
+  const int I = 1 + blockIdx.x * 256 + threadIdx.x, J = 1 + blockIdx.y;
+  if (I > nt - 2) return;
+  transfer_node_2d<T, ZERO>(xprev, xcur, cp, m, dst, dp, mt, I, J);
 }
 
 template <typename T, bool ZERO>
@@ -2163,17 +2172,15 @@ __device__ __forceinline__ int tiles_of(int side, int len) {
 
 struct StageInfo {
   int kind;   // BK_* below
-  int level;  // restriction: fine level; sweep: level
-  int mode;   // sweep mode bits
-  int sweep;  // sweep index within the cycle
+  int level;  // restriction: fine level; iteration stages: level
+  int code;   // iteration stages: the stage's entry of the schedule table
   int cycle;
-  int step;   // step of the persistent loop
-  int count;  // sweep: iterations in the stage (several: a multi-iteration level-0 pass)
+  int step;   // step of the sequence
 };
-enum { BK_NONE = 0, BK_NORM = 1, BK_FNORM = 2, BK_RES = 3, BK_FIN = 4, BK_RESTRICT = 5, BK_SWEEP = 6 };
+enum { BK_NONE = 0, BK_NORM = 1, BK_FNORM = 2, BK_RES = 3, BK_FIN = 4, BK_RESTRICT = 5, BK_STAGE = 6 };
 
-__device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* __restrict__ levels_of_sweep, int k) {
-  StageInfo si{BK_NONE, 0, 0, 0, 0, 0, 1};
+__device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* __restrict__ table, int k) {
+  StageInfo si{BK_NONE, 0, 0, 0, 0};
   if (k == 0) { si.kind = BK_NORM; return si; }
   if (k == 1) { si.kind = BK_FNORM; return si; }
   if (k == 2) { si.kind = BK_RES; return si; }
@@ -2183,12 +2190,9 @@ __device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* 
   si.cycle = (k - 4) / L + 1;
   if (j < p.top) { si.kind = BK_RESTRICT; si.level = j; return si; }
   if (j < p.top + p.sweeps) {
-    si.kind = BK_SWEEP;
-    si.sweep = j - p.top;
-    const int code = levels_of_sweep[p.sched_off + si.sweep];
-    si.level = code & 0xff;
-    si.count = code >> 8;
-    si.mode = (si.sweep == 0 ? SW_ZERO_OLD : 0) | (si.sweep == p.sweeps - 1 ? SW_ACCUM : 0);
+    si.kind = BK_STAGE;
+    si.code = table[p.sched_off + j - p.top];
+    si.level = bst_level(si.code);
     return si;
   }
   si.kind = (j == p.top + p.sweeps) ? BK_RES : BK_FIN;
@@ -2198,12 +2202,19 @@ __device__ __forceinline__ StageInfo stage_of(const BatchProblem& p, const int* 
 // Band length of a problem's multi-iteration level-0 stage: its tuned walk
 // length, at least 16 rows (shorter bands re-read too many halo rows).
 __host__ __device__ __forceinline__ int batch_tb_len(const BatchProblem& p) { return p.len[0] < 16 ? 16 : p.len[0]; }
+constexpr int BATCH_XF_ROWS = 8;  // rows of a hand-over tile
+
+__device__ __forceinline__ int level_side(const BatchProblem& p, int m) { return (p.n - 1) / (1 << m) + 1; }
 
 __device__ __forceinline__ int stage_tiles(const BatchProblem& p, const StageInfo& si) {
   switch (si.kind) {
-    case BK_SWEEP:
-      if (si.count > 1) return (tb_waves(p.n, si.count, batch_tb_len(p)) + 3) / 4;
-      return tiles_of(p.n, p.len[0]);
+    case BK_STAGE: {
+      const int c = si.code;
+      if (bst_kind(c) == BST_L0) return (tb_waves(p.n, bst_count(c), batch_tb_len(p)) + 3) / 4;
+      if (bst_kind(c) == BST_SWEEP) return tiles_of(level_side(p, si.level), p.len[si.level]);
+      const int nt = level_side(p, si.level - 1);  // hand-over target
+      return nt >= 3 ? ((nt - 2 + BX2 - 1) / BX2) * ((nt - 2 + BATCH_XF_ROWS - 1) / BATCH_XF_ROWS) : 0;
+    }
     case BK_NORM:
     case BK_RES: return tiles_of(p.n, p.len[0]);
     case BK_RESTRICT: {
@@ -2274,47 +2285,65 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
                           p.len[si.level + 1], t % gxc, t / gxc);
       break;
     }
-    case BK_SWEEP: {
-      const T* eo = (si.sweep & 1) ? e1 : e0;
-      T* en = (si.sweep & 1) ? e0 : e1;
-      const int m = si.level;
-      const double hl = double(1 << m) / double(n - 1);
-      const C hl2 = C(hl * hl), w = C(run.omega / 4.0);
-      const T* rm = static_cast<const T*>(p.r[m]);
-      if (si.count > 1) {  // several level-0 iterations in one stage (multi-iteration pass)
+    case BK_STAGE: {
+      const int c = si.code, m = si.level, kind = bst_kind(c);
+      const bool zero = bst_zero(c);
+      if (kind == BST_SWEEP) {  // iteration bst_index of level m >= 1 on its compact lattice
+        const int nm = level_side(p, m), it = bst_index(c);
+        const T* xo = static_cast<const T*>(p.x[m][(it - 1) & 1]);
+        T* xn = static_cast<T*>(p.x[m][it & 1]);
+        const double hl = 1.0 / double(nm - 1);
+        const C hl2 = C(hl * hl), w = C(run.omega / 4.0);
+        const int gxm = (nm - 2 + BX2 - 1) / BX2;
+        const T* rm = static_cast<const T*>(p.r[m]);
+        if (zero)
+          tile_sweep_2d_l0<T, SW_ZERO_OLD, false>(xo, xn, p.rp[m], rm, p.rp[m], nullptr, 0, nullptr, 0, nm,
+                                                  p.len[m], w, hl2, t % gxm, t / gxm);
+        else
+          tile_sweep_2d_l0<T, 0, false>(xo, xn, p.rp[m], rm, p.rp[m], nullptr, 0, nullptr, 0, nm, p.len[m],
+                                        w, hl2, t % gxm, t / gxm);
+      } else if (kind == BST_XFER) {  // level m's final state to the lattice of level m - 1
+        const int it = bst_count(c), mt = m - 1, nt = level_side(p, mt);
+        const T* xc = static_cast<const T*>(p.x[m][it & 1]);
+        const T* xp = static_cast<const T*>(p.x[m][(it - 1) & 1]);
+        T* dst = mt > 0 ? static_cast<T*>(p.x[mt][0]) : e0;
+        const int64_t dp = mt > 0 ? p.rp[mt] : p.ep;
+        const int gxt = (nt - 2 + BX2 - 1) / BX2;
+        const int I = 1 + (t % gxt) * BX2 + threadIdx.x;
+        const int J0 = 1 + (t / gxt) * BATCH_XF_ROWS, J1 = min(nt - 1, J0 + BATCH_XF_ROWS);
+        if (I <= nt - 2)
+          for (int J = J0; J < J1; ++J) {
+            if (zero)
+              transfer_node_2d<T, true>(xp, xc, p.rp[m], m, dst, dp, mt, I, J);
+            else
+              transfer_node_2d<T, false>(xp, xc, p.rp[m], m, dst, dp, mt, I, J);
+          }
+      } else {  // level-0 pass bst_index of bst_count iterations
+        const int q = bst_index(c), cnt = bst_count(c);
+        const T* eo = (q & 1) ? e1 : e0;
+        T* en = (q & 1) ? e0 : e1;
+        const double h = 1.0 / double(n - 1);
+        const C hl2 = C(h * h), w = C(run.omega / 4.0);
+        const T* rm = static_cast<const T*>(p.r[0]);
         const int len = batch_tb_len(p), wv = t * 4 + int(threadIdx.x >> 6);
-#define BATCH_TB(Z, A, IT)                                                                      \
+        const bool accum = bst_accum(c);
+#define BATCH_TB(Z, A, IT) \
   tb_body<T, Z, A, false, IT>(eo, en, nullptr, p.ep, rm, p.rp[0], p.u, n, n, len, w, hl2, wv)
-#define BATCH_TB_IT(Z, A)                                               \
-  switch (si.count) {                                                   \
-    case 2: BATCH_TB(Z, A, 2); break;                                   \
-    case 3: BATCH_TB(Z, A, 3); break;                                   \
-    default: BATCH_TB(Z, A, 4); break;                                  \
+#define BATCH_TB_IT(Z, A)             \
+  switch (cnt) {                      \
+    case 1: BATCH_TB(Z, A, 1); break; \
+    case 2: BATCH_TB(Z, A, 2); break; \
+    case 3: BATCH_TB(Z, A, 3); break; \
+    default: BATCH_TB(Z, A, 4); break; \
   }
-        switch (si.mode) {
-          case 0: BATCH_TB_IT(false, false); break;
-          case 1: BATCH_TB_IT(true, false); break;
-          case 2: BATCH_TB_IT(false, true); break;
-          default: BATCH_TB_IT(true, true); break;
+        if (zero) {
+          if (accum) { BATCH_TB_IT(true, true); } else { BATCH_TB_IT(true, false); }
+        } else {
+          if (accum) { BATCH_TB_IT(false, true); } else { BATCH_TB_IT(false, false); }
         }
 #undef BATCH_TB_IT
 #undef BATCH_TB
-        break;
       }
-#define BATCH_SWEEP(MODE)                                                                          \
-  if (m == 0)                                                                                      \
-    tile_sweep_2d_l0<T, MODE, false>(eo, en, p.ep, rm, p.rp[m], nullptr, 0, p.u, n, n, p.len[0], w, \
-                                     hl2, bx, by);                                                 \
-  else                                                                                             \
-    tile_sweep_2d_coarse<T, MODE, false>(eo, en, p.ep, rm, p.rp[m], nullptr, 0, p.u, n, n,          \
-                                         p.len[0], m, w, hl2, bx, by);
-      switch (si.mode) {
-        case 0: BATCH_SWEEP(0); break;
-        case 1: BATCH_SWEEP(1); break;
-        case 2: BATCH_SWEEP(2); break;
-        default: BATCH_SWEEP(3); break;
-      }
-#undef BATCH_SWEEP
       break;
     }
     default:
