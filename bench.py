@@ -217,8 +217,8 @@ def mixed_precision_section(P, W, torch, dev, reps=3):
 def batched_section(P, W, torch, dev, count=512, reps=3):
     """512 independent 2D Poisson problems, sides drawn uniformly from
     {65, 129, 257, 513, 1025} (seed 0), f ~ U[-1, 1]: FP32 sweeps under FP64
-    residual/update, all problems in one persistent launch (a HIP graph
-    replayed per solve), tile rows tuned per side; every problem to 1e-10.
+    residual/update, all problems advanced together (one launch per step,
+    a HIP graph of steps replayed per solve), tile rows tuned per side; every problem to 1e-10.
     Beside it: the same problems solved one after another by the
     single-problem solver in the same precision."""
     sides, fnp = W.batch2d(count, seed=0)
