@@ -400,7 +400,7 @@ def learn_adam(theta, m1, m2, grad, t, lr, w_out, beta1=0.9, beta2=0.999, eps=1e
 
 
 class BatchSolver:
-    """Many independent 2D Poisson problems solved in one persistent launch."""
+    """Many independent 2D Poisson problems advanced together (one launch per step for all)."""
 
     def __init__(self, sides, precision="fp32", omega=0.0, max_i=4, max_cycles=200):
         L = lib()

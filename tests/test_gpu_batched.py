@@ -1,4 +1,4 @@
-"""GPU tests of the batched persistent solver (one launch for many problems).
+"""GPU tests of the batched solver (many problems advanced together, one launch per step).
 
 Every problem of a batch must end exactly where the one-problem solver
 (one launch per iteration, same precision) ends: the batched kernel runs the
