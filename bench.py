@@ -50,11 +50,16 @@ def sweep_bytes(d, n, level, mode, elem=8):
     N).  Level 0 reads e_old and r at every node.  The first iteration of a
     cycle does not read e_old; the last adds into u (read + write of FP64 u
     instead of the store of e).  A pass of several level-0 iterations
-    (mode bit 3) moves the same bytes once."""
+    (mode bit 3) moves the same bytes once; one that takes its first iterate
+    from level 1's compact x_{it-1} and x_it (mode bit 7) reads those two
+    arrays (N / 2^d nodes each) instead of e_old."""
     N = float(n) ** d
     l = 1 << level
     lat = N / float(l) ** d
-    reads = (0.0 if mode & 1 else lat * elem) + lat * elem
+    if mode & 128:
+        reads = 2.0 * elem * N / 2.0 ** d + lat * elem
+    else:
+        reads = (0.0 if mode & 1 else lat * elem) + lat * elem
     if mode & 2:
         return reads + 16.0 * N
     return reads + N * elem
@@ -65,8 +70,9 @@ def kernel_symbol(d, kind, level, mode):
     argument list), so the bench line and the rocprofv3 summary can be matched."""
     var2 = ", false" if d == 2 else ""
     if kind == "sweep" and mode & 8:  # several level-0 iterations in one pass
-        return "k_sweep_%dd_l0_tb<double, %s, %s, %d>" % (
-            d, "true" if mode & 1 else "false", "true" if mode & 2 else "false", ((mode >> 4) & 3) + 1)
+        return "k_sweep_%dd_l0_tb<double, %s, %s, %d, %s>" % (
+            d, "true" if mode & 1 else "false", "true" if mode & 2 else "false", ((mode >> 4) & 3) + 1,
+            "true" if mode & 128 else "false")
     if kind == "sweep":
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
         return "%s<double, %d%s>" % (base, mode, var2)

@@ -80,7 +80,9 @@ typedef struct homg_options {
     int temporal_block;    /* 2 (default): chained -- the iterations of a coarse level run on its
                               compact lattice, a coarse level followed by another coarse level
                               hands over only that level's lattice values, and the whole grid is
-                              written only before level 0 or the last level;
+                              written only before level 0 or the last level (before level 0 of a
+                              Laplacian with damped Jacobi not at all: level 0's first pass
+                              interpolates level 1's lattice values itself);
                               1: level-blocked -- as 2, but the whole grid is written after every
                               level;
                               0: one whole-grid launch per iteration.
@@ -201,7 +203,9 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   bit 2 (kinds 6, 8) = every iteration of the level in one workgroup that
  *   holds the whole lattice; bit 3 (kinds 4, 6) = several iterations in one
  *   temporally blocked pass, bits 4-5 their number minus one, bit 6 (kind
- *   6) = the pass also stores the iterate before its last.
+ *   6) = the pass also stores the iterate before its last, bit 7 (kind 4,
+ *   level 0) = the pass takes its first iterate from level 1's compact
+ *   lattice state (chained execution: no whole-grid write before level 0).
  * homg_get_profile synchronises outstanding events, then writes up to cap
  * entries and their count in *len.
  */

@@ -89,6 +89,10 @@ struct homg_ctx {
   Profiler prof;
   // learned relaxation (2D): 0 damped Jacobi, 1 the network with weights w
   int chain_ready = -1;        // chained path: level whose x_0 the previous level already wrote
+  // chained path: level 1's compact final state, which the first level-0
+  // pass interpolates itself (no whole-grid write in between)
+  bool l1_pending = false;
+  L1State l1;
   int smoother = 0;
   int active_smoother = 0;     // smoother of the solve in progress (after any fallback)
   double fallback_ratio = 1.0; // per-cycle contraction at which a solve falls back to Jacobi
@@ -231,15 +235,20 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
   // One launch per iteration: level 0 always (every node is a lattice
   // node), every level when blocking is off, and a coarse last level in
   // reduced precision (its iterate goes into u unrounded).
+  // chained path: the first level-0 pass reads level 1's compact state
+  const L1State* l1 = (m == 0 && h->l1_pending) ? &h->l1 : nullptr;
+  if (m == 0) h->l1_pending = false;
   if (m == 0 && h->d == 3 && h->temporal) {
     // level 0 in 3D: up to TB3_MAX_IT iterations per pass, same iterates
     for (int t0 = 0; t0 < it; t0 += TB3_MAX_IT) {
       const int g = std::min(TB3_MAX_IT, it - t0);
       const bool zero = first && t0 == 0, accum = last && t0 + g == it;
-      const int mode = SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | (accum ? SW_ACCUM : 0) | ((g - 1) << 4);
+      const L1State* src = t0 == 0 ? l1 : nullptr;
+      const int mode = SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | (accum ? SW_ACCUM : 0) | ((g - 1) << 4) |
+                       (src ? 128 : 0);
       LAUNCH_K(h, s, K_SWEEP, 0, mode,
                launch_tb_3d(h->prec, h->n, g, h->omega, h->e[*cur], h->e[1 - *cur], nullptr, h->el,
-                            h->r[0], h->rl[0], acc, h->dl, zero, accum, false, done, s));
+                            h->r[0], h->rl[0], acc, h->dl, zero, accum, false, done, s, 0, src));
       *cur = 1 - *cur;
     }
     return HOMG_OK;
@@ -250,14 +259,17 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
     for (int t0 = 0; t0 < it; t0 += TB_MAX_IT) {
       const int g = std::min(TB_MAX_IT, it - t0);
       const bool zero = first && t0 == 0, accum = last && t0 + g == it;
-      const int mode = SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | (accum ? SW_ACCUM : 0) | ((g - 1) << 4);
+      const L1State* src = t0 == 0 ? l1 : nullptr;
+      const int mode = SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | (accum ? SW_ACCUM : 0) | ((g - 1) << 4) |
+                       (src ? 128 : 0);
       LAUNCH_K(h, s, K_SWEEP, 0, mode,
                launch_sweep_2d_l0_tb(h->prec, h->n, g, h->omega, h->e[*cur], h->e[1 - *cur], h->el,
-                                     h->r[0], h->rl[0], acc, h->dl, zero, accum, done, s));
+                                     h->r[0], h->rl[0], acc, h->dl, zero, accum, done, s, 0, src));
       *cur = 1 - *cur;
     }
     return HOMG_OK;
   }
+  if (l1) return fail(h, HOMG_ERR_UNSUPPORTED, "level 1 left no whole-grid state for level 0");
   if (m == 0 || !h->temporal || (last && h->prec != PREC_F64)) {
     for (int t = 0; t < it; ++t) {
       int mode = 0;
@@ -337,6 +349,17 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
 // always whole-grid.
 homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, void* xprev,
                          void* xcur, int* cur, double* acc, const int* done, hipStream_t s) {
+  // chained path into a temporally blocked level 0 (Laplacian, damped
+  // Jacobi): its first pass interpolates level 1's compact state itself
+  if (h->temporal == 2 && !last && m == 1 && next_m == 0 && h->active_smoother == 0 && !h->has_coef &&
+      h->n >= 5) {
+    h->l1.prev = (wmode & SW_ZERO_OLD) ? nullptr : xprev;
+    h->l1.cur = xcur;
+    h->l1.cl = h->rl[1];
+    h->l1.zero_old = (wmode & SW_ZERO_OLD) != 0;
+    h->l1_pending = true;
+    return HOMG_OK;
+  }
   if (h->temporal == 2 && !last && next_m >= 1 && next_m != m) {
     LAUNCH_K(h, s, K_TRANSFER, next_m, wmode & SW_ZERO_OLD,
              launch_level_transfer(h->prec, h->d, m, xprev, xcur, h->rl[m], next_m, h->xc[2 * next_m],
@@ -445,6 +468,7 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   const Lay none;
   const size_t np = h->sched.size() / 2;
   h->chain_ready = -1;
+  h->l1_pending = false;
   size_t p0 = 0;
   if (ntail) {
     int its[BATCH_MAX_LEVELS];
@@ -463,7 +487,10 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
     if (p + 1 < np) {
       const int mn = h->sched[2 * (p + 1)];
       const bool next_last = p + 2 == np;
-      if (mn != 0 && (h->active_smoother == 1 || !(next_last && h->prec != PREC_F64))) next_m = mn;
+      if (mn == 0)
+        next_m = 0;
+      else if (h->active_smoother == 1 || !(next_last && h->prec != PREC_F64))
+        next_m = mn;
     }
     if (homg_status e = run_level(h, m, it, p == 0, p + 1 == np, next_m, &cur, acc, done, s)) return e;
   }

@@ -86,10 +86,21 @@ __host__ __device__ inline int tb_waves(int n, int it, int len) {
   return ((n - 2 + valid - 1) / valid) * ((n - 2 + len - 1) / len);
 }
 int tb_band(int n, int it);
+// Level 1's final compact state (layout cl, side (n-1)/2+1): x_it in cur and
+// x_{it-1} in prev (unread when zero_old: x_{it-1} = 0).  A level-0 pass
+// given one takes its input e from it -- lattice nodes x_it, every other
+// interior node the multilinear interpolant of x_{it-1}, exactly as the
+// level-1 whole-grid write would have stored them -- instead of reading eo.
+struct L1State {
+  const void* prev = nullptr;
+  const void* cur = nullptr;
+  Lay cl;
+  bool zero_old = false;
+};
 hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
                                  const Lay& el, const void* rm, const Lay& rl, double* u,
                                  const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s,
-                                 int len = 0);
+                                 int len = 0, const L1State* l1 = nullptr);
 // The same on the compact lattice of a coarse level (side nm): x_it into en
 // and, when eprev is not null, x_{it-1} into eprev (layout cl).
 hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const void* eo, void* en,
@@ -108,7 +119,8 @@ int tb3_blocks(int n, int it, int len);
 int tb3_band(int n, int it);
 hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, void* en, void* eprev,
                         const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
-                        bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len = 0);
+                        bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len = 0,
+                        const L1State* l1 = nullptr);
 // Convert between a dense FP64 array and an internal array of `prec`.
 hipError_t launch_pack(int prec, int d, const double* src, const Lay& sl, void* dst,
                        const Lay& dl, hipStream_t s);

@@ -565,6 +565,183 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
   tile_sweep_2d_l0<T, MODE, VAR>(eo, en, ep, r, rp, a, ap, u, up, n, len, w, hl2, int(lg % gx), int(lg / gx));
 }
 
+// Level 1's final state seen from level 0 (chained path): the value the
+// level-1 whole-grid write would leave at a level-0 node, computed from the
+// compact arrays instead of read back from a whole grid.  Lattice nodes
+// (every index even) take x_it, every other interior node the multilinear
+// interpolant of x_{it-1} over its level-1 cell, boundary nodes 0; the
+// formula, its order of operations and the rounding to T are those of the
+// whole-grid write (k_level_write_2d/3d with m = 1), so both give the same
+// bits.
+template <typename T>
+struct L1Src {
+  const T* prev;    // x_{it-1}, unread when zero_old
+  const T* cur;     // x_it
+  int64_t cp, cpl;  // compact row pitch, plane pitch
+  int zero_old;
+};
+
+// One lane's column (2D): node x, rows visited in increasing order.  The
+// x-interpolants of the two level-1 rows around the current row are kept
+// and shifted as the walk enters the next level-1 row.
+template <typename T>
+struct L1Col2 {
+  using C = typename Tr<T>::C;
+  const T* p;
+  const T* q;
+  int64_t cp;
+  int I, band;
+  C tx, top, bot;
+  bool live, latx, zold;
+  __device__ __forceinline__ void init(const L1Src<T>& s, int x, int n) {
+    live = x >= 1 && x <= n - 2;
+    latx = (x & 1) == 0;
+    I = live ? x >> 1 : 0;
+    tx = C(x & 1) * (C(1) / C(2));
+    p = s.prev;
+    q = s.cur;
+    cp = s.cp;
+    zold = s.zero_old != 0;
+    band = -2;
+    top = bot = C(0);
+  }
+  __device__ __forceinline__ C xl(int J) const {
+    if (zold) return lerp(C(0), C(0), tx);
+    const T* a = p + int64_t(J) * cp + I;
+    return lerp(ld(a), ld(a + 1), tx);
+  }
+  // Rows ys..ys+3 of a walk in steps of four rows (ys keeps its parity, so
+  // the level-1 rows advance by two per step): the x-interpolants of level-1
+  // rows j0, j0+1 come from the previous step (prime() before the first),
+  // rows j0+2, j0+3 are loaded, with no branch between the loads.
+  C w0, w1;
+  __device__ __forceinline__ void prime(int ys, int n) {
+    const int j0 = ys >> 1, nm1 = (n - 1) >> 1;
+    w0 = xl(min(j0, nm1));
+    w1 = xl(min(j0 + 1, nm1));
+  }
+  __device__ __forceinline__ void rows4(int ys, int n, C (&v)[4]) {
+    const int j0 = ys >> 1, nm1 = (n - 1) >> 1;
+    const bool odd = (ys & 1) != 0;
+    // rows past the lattice only feed rows off the grid
+    const C x2 = xl(min(j0 + 2, nm1)), x3 = xl(min(j0 + 3, nm1));
+    C qv[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) qv[e] = ld(q + int64_t(min(j0 + int(odd) + e, nm1)) * cp + I);
+    const C h = C(1) / C(2);
+    // row k lies in level-1 row j0 + (k + odd) / 2; its even rows are k = odd, odd + 2
+    const C t[4] = {lerp(w0, w1, C(ys & 1) * h),
+                    odd ? lerp(w1, x2, C((ys + 1) & 1) * h) : lerp(w0, w1, C((ys + 1) & 1) * h),
+                    lerp(w1, x2, C((ys + 2) & 1) * h),
+                    odd ? lerp(x2, x3, C((ys + 3) & 1) * h) : lerp(w1, x2, C((ys + 3) & 1) * h)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int y = ys + k;
+      const C val = (latx && (y & 1) == 0) ? qv[k >> 1] : t[k];
+      v[k] = (live && y >= 1 && y <= n - 2) ? rnd<T>(val) : C(0);
+    }
+    w0 = x2;
+    w1 = x3;
+  }
+  __device__ __forceinline__ C at(int y, int n) {
+    if (!live || y < 1 || y > n - 2) return C(0);
+    const int J = y >> 1;
+    if (J != band) {
+      top = J == band + 1 ? bot : xl(J);
+      bot = xl(J + 1);
+      band = J;
+    }
+    const C v = (latx && (y & 1) == 0) ? ld(q + int64_t(J) * cp + I)
+                                       : lerp(top, bot, C(y & 1) * (C(1) / C(2)));
+    return rnd<T>(v);
+  }
+};
+
+// One lane's R consecutive rows yb.. of one x (3D), planes visited in
+// increasing order.  Per level-1 plane the lane forms the x-interpolants of
+// the (at most four) level-1 rows its rows touch, then each row's
+// y-interpolant; the two planes around the current plane are kept.  yb is
+// the same for the whole wave, so everything derived from it stays scalar.
+template <typename T, int R>
+struct L1Col3 {
+  using C = typename Tr<T>::C;
+  const T* p;
+  const T* q;
+  int64_t cp, cpl;
+  int I, yb, n, band;
+  bool xin, xeven, zold;
+  C top[R], bot[R];
+  __device__ __forceinline__ void init(const L1Src<T>& s, int x, int yb_, int n_) {
+    static_assert(R == 4, "four rows per lane");
+    n = n_;
+    yb = __builtin_amdgcn_readfirstlane(yb_);
+    xin = x >= 1 && x <= n - 2;
+    xeven = (x & 1) == 0;
+    I = xin ? x >> 1 : 0;
+    p = s.prev;
+    q = s.cur;
+    cp = s.cp;
+    cpl = s.cpl;
+    zold = s.zero_old != 0;
+    band = -2;
+#pragma unroll
+    for (int k = 0; k < R; ++k) top[k] = bot[k] = C(0);
+  }
+  __device__ __forceinline__ C tx() const { return xeven ? C(0) : C(1) / C(2); }
+  // y-interpolants of the lane's rows on level-1 plane K
+  __device__ __forceinline__ void plane(int K, C (&out)[R]) const {
+    const int j0 = yb >> 1, nm1 = (n - 1) >> 1;  // arithmetic shift: yb may be -1
+    const bool odd = (yb & 1) != 0;
+    C xv[R];
+#pragma unroll
+    for (int d = 0; d < R; ++d) {
+      if (zold) {
+        xv[d] = lerp(C(0), C(0), tx());
+      } else {
+        // rows past the lattice only feed rows off the grid
+        const int J = min(max(j0 + d, 0), nm1);
+        const T* a = p + int64_t(K) * cpl + int64_t(J) * cp + I;
+        xv[d] = lerp(ld(a), ld(a + 1), tx());
+      }
+    }
+    // row k lies in level-1 row j0 + (k + odd) / 2
+    const C h = C(1) / C(2);
+    out[0] = lerp(xv[0], xv[1], C(yb & 1) * h);
+    out[1] = odd ? lerp(xv[1], xv[2], C((yb + 1) & 1) * h) : lerp(xv[0], xv[1], C((yb + 1) & 1) * h);
+    out[2] = lerp(xv[1], xv[2], C((yb + 2) & 1) * h);
+    out[3] = odd ? lerp(xv[2], xv[3], C((yb + 3) & 1) * h) : lerp(xv[1], xv[2], C((yb + 3) & 1) * h);
+  }
+  __device__ __forceinline__ void at(int z, C (&v)[R]) {
+    if (z < 1 || z > n - 2) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) v[k] = C(0);
+      return;
+    }
+    const int K = z >> 1;
+    if (K != band) {
+      if (K == band + 1) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) top[k] = bot[k];
+      } else {
+        plane(K, top);
+      }
+      plane(K + 1, bot);
+      band = K;
+    }
+    const C tz = C(z & 1) * (C(1) / C(2));
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int y = yb + k;
+      C t;
+      if (xeven && (y & 1) == 0 && (z & 1) == 0)  // a level-1 lattice node
+        t = ld(q + int64_t(K) * cpl + int64_t(min(max(y >> 1, 0), (n - 1) >> 1)) * cp + I);
+      else
+        t = lerp(top[k], bot[k], tz);
+      v[k] = (xin && y >= 1 && y <= n - 2) ? rnd<T>(t) : C(0);
+    }
+  }
+};
+
 // Level 0, IT <= 4 iterations in one pass (temporal blocking).  Each wave
 // owns 64 consecutive columns and walks a band of rows; the
 // iterations form a pipeline down the band: iteration t is computed t rows
@@ -580,19 +757,28 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
 // the result equals IT single sweeps bit for bit while e and r are read
 // once and the result written (or added into u) once.
 
-template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT, int U>
+template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT, int U, bool LAT>
 __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict__ en,
                                          T* __restrict__ eprev, int64_t ep,
                                          const T* __restrict__ r, int64_t rp, double* __restrict__ u,
                                          int64_t up, int n, int x, int xc, bool xin, bool emit, int Y0,
                                          int Y1, int ys, typename Tr<T>::C w, typename Tr<T>::C hl2,
-                                         typename Tr<T>::C (&win)[IT][3], typename Tr<T>::C (&rw)[IT + 1]) {
+                                         typename Tr<T>::C (&win)[IT][3], typename Tr<T>::C (&rw)[IT + 1],
+                                         L1Col2<T>& lc) {
   using C = typename Tr<T>::C;
   C xl[U], rl[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {  // rows past the grid read the boundary row (zero)
-    xl[k] = ZERO ? C(0) : ld(eo + int64_t(min(ys + k, n - 1)) * ep + xc);
     rl[k] = ld(r + int64_t(min(max(ys + k - 1, 0), n - 1)) * rp + xc);
+    if (!LAT) xl[k] = ZERO ? C(0) : ld(eo + int64_t(min(ys + k, n - 1)) * ep + xc);
+  }
+  if (LAT) {
+    if constexpr (U == 4) {
+      lc.rows4(ys, n, xl);
+    } else {
+#pragma unroll
+      for (int k = 0; k < U; ++k) xl[k] = lc.at(min(ys + k, n - 1), n);
+    }
   }
 #pragma unroll
   for (int k = 0; k < U; ++k) {
@@ -625,16 +811,19 @@ __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict
   }
 }
 
-// Wave wv of the pass (waves numbered x-band fastest).
-template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT>
+// Wave wv of the pass (waves numbered x-band fastest).  LAT: e comes from
+// level 1's compact state (L1Src) instead of eo.
+template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT, bool LAT = false>
 __device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict__ en,
                                         T* __restrict__ eprev, int64_t ep, const T* __restrict__ r,
                                         int64_t rp, double* __restrict__ u, int64_t up, int n, int len,
-                                        typename Tr<T>::C w, typename Tr<T>::C hl2, int wv) {
+                                        typename Tr<T>::C w, typename Tr<T>::C hl2, int wv,
+                                        const L1Src<T>& l1 = L1Src<T>{}) {
   using C = typename Tr<T>::C;
   constexpr int VALID = 64 - 2 * IT;
   const int lane = threadIdx.x & 63;
   const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + len - 1) / len;
+  wv = __builtin_amdgcn_readfirstlane(wv);  // one value per wave: rows and bands stay scalar
   if (wv >= gx * gy) return;  // the whole wave
   const int x = 1 + (wv % gx) * VALID - IT + lane;
   const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);
@@ -646,26 +835,31 @@ __device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict_
   for (int t = 0; t < IT; ++t) win[t][0] = win[t][1] = win[t][2] = C(0);
 #pragma unroll
   for (int t = 0; t <= IT; ++t) rw[t] = C(0);
+  L1Col2<T> lc;
   int ys = max(Y0 - IT, 0);
+  if (LAT) {
+    lc.init(l1, x, n);
+    lc.prime(ys, n);
+  }
   const int ye = Y1 + IT;  // one past the last row loaded
   for (; ys + 4 <= ye; ys += 4)
-    tb_steps<T, ZERO, ACCUM, PREV, IT, 4>(eo, en, eprev, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w,
-                                          hl2, win, rw);
+    tb_steps<T, ZERO, ACCUM, PREV, IT, 4, LAT>(eo, en, eprev, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1,
+                                               ys, w, hl2, win, rw, lc);
   for (; ys < ye; ++ys)
-    tb_steps<T, ZERO, ACCUM, PREV, IT, 1>(eo, en, eprev, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1, ys, w,
-                                          hl2, win, rw);
+    tb_steps<T, ZERO, ACCUM, PREV, IT, 1, LAT>(eo, en, eprev, ep, r, rp, u, up, n, x, xc, xin, emit, Y0, Y1,
+                                               ys, w, hl2, win, rw, lc);
 }
 
-template <typename T, bool ZERO, bool ACCUM, int IT>
+template <typename T, bool ZERO, bool ACCUM, int IT, bool LAT>
 __global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r, int64_t rp,
     double* __restrict__ u, int64_t up, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
-    const int* __restrict__ done) {
+    const int* __restrict__ done, L1Src<T> l1) {
   if (*done) return;
   // XCD order: the waves of one XCD are neighbours (their overlapping
   // columns and rows meet in that XCD's L2)
   const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
-  tb_body<T, ZERO, ACCUM, false, IT>(eo, en, nullptr, ep, r, rp, u, up, n, len, w, hl2, wv);
+  tb_body<T, ZERO, ACCUM, false, IT, LAT>(eo, en, nullptr, ep, r, rp, u, up, n, len, w, hl2, wv, l1);
 }
 
 // The same pass over the compact lattice of a coarse level (n = its side),
@@ -849,12 +1043,13 @@ __global__ __launch_bounds__(256) void k_sweep_3d_l0(
 constexpr int TB3_R = 4;                 // rows per lane
 constexpr int TB3_TY = BY3 * TB3_R;      // tile rows (16)
 
-template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT>
+template <typename T, bool ZERO, bool ACCUM, bool PREV, int IT, bool LAT = false>
 __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict__ en,
                                          T* __restrict__ eprev, int64_t ep, int64_t epl,
                                          const T* __restrict__ r, int64_t rp, int64_t rpl,
                                          double* __restrict__ u, int64_t up, int64_t upl, int n,
-                                         int len, typename Tr<T>::C w, typename Tr<T>::C hl2) {
+                                         int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
+                                         const L1Src<T>& l1 = L1Src<T>{}) {
   using C = typename Tr<T>::C;
   constexpr int VX = BX3 - 2 * IT, VY = TB3_TY - 2 * IT;
   __shared__ C P[IT][2][TB3_TY][BX3];
@@ -889,13 +1084,22 @@ __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict
     }
   const int xm_i = max(lx - 1, 0), xp_i = min(lx + 1, BX3 - 1);
   const int ym_row = max(row0 - 1, 0), yp_row = min(row0 + TB3_R, TB3_TY - 1);
+  L1Col3<T, TB3_R> lc;
+  if (LAT) lc.init(l1, x, yb, n);
   int b = 0;
   for (int zl = max(Z0 - IT, 0); zl < Z1 + IT; ++zl, b ^= 1) {
     const int zlc = min(zl, n - 1), zr = min(max(zl - 1, 0), n - 1);
+    C lv[TB3_R], rvs[TB3_R];
 #pragma unroll
     for (int k = 0; k < TB3_R; ++k) {
-      const C v0 = ZERO ? C(0) : ld(eo + int64_t(zlc) * epl + col[k]);
-      const C rv = ld(r + int64_t(zr) * rpl + rcol[k]);
+      rvs[k] = ld(r + int64_t(zr) * rpl + rcol[k]);
+      if (!LAT) lv[k] = ZERO ? C(0) : ld(eo + int64_t(zlc) * epl + col[k]);
+    }
+    if (LAT) lc.at(zlc, lv);
+#pragma unroll
+    for (int k = 0; k < TB3_R; ++k) {
+      const C v0 = lv[k];
+      const C rv = rvs[k];
       win[0][0][k] = win[0][1][k];
       win[0][1][k] = win[0][2][k];
       win[0][2][k] = v0;
@@ -945,13 +1149,14 @@ __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict
   }
 }
 
-template <typename T, bool ZERO, bool ACCUM, int IT>
+template <typename T, bool ZERO, bool ACCUM, int IT, bool LAT>
 __global__ __launch_bounds__(256) void k_sweep_3d_l0_tb(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, int64_t epl, const T* __restrict__ r,
     int64_t rp, int64_t rpl, double* __restrict__ u, int64_t up, int64_t upl, int n, int len,
-    typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done) {
+    typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done, L1Src<T> l1) {
   if (*done) return;
-  tb3_body<T, ZERO, ACCUM, false, IT>(eo, en, nullptr, ep, epl, r, rp, rpl, u, up, upl, n, len, w, hl2);
+  tb3_body<T, ZERO, ACCUM, false, IT, LAT>(eo, en, nullptr, ep, epl, r, rp, rpl, u, up, upl, n, len, w, hl2,
+                                           l1);
 }
 
 template <typename T, bool ZERO, bool PREV, int IT>
@@ -1718,10 +1923,31 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
               rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, m, w, hl2, done);
 }
 
-template <typename T, bool ZERO, bool ACCUM>
+// Device view of a level-1 state (null: the pass reads eo).
+template <typename T>
+static L1Src<T> l1_src(const L1State* l1) {
+  L1Src<T> v{};
+  if (l1) {
+    v.prev = l1->prev ? static_cast<const T*>(l1->prev) + l1->cl.off : nullptr;
+    v.cur = static_cast<const T*>(l1->cur) + l1->cl.off;
+    v.cp = l1->cl.pitch;
+    v.cpl = l1->cl.plane;
+    v.zero_old = l1->zero_old ? 1 : 0;
+  }
+  return v;
+}
+
+// Checks a level-1 state against a level-0 side n.
+static bool l1_ok(const L1State* l1, int d, int n) {
+  if (!l1) return true;
+  return l1->cur && (l1->zero_old || l1->prev) && l1->cl.side == (n - 1) / 2 + 1 && n >= 5 &&
+         l1->cl.pitch >= l1->cl.side && (d == 2 || l1->cl.plane >= l1->cl.pitch * l1->cl.side);
+}
+
+template <typename T, bool ZERO, bool ACCUM, bool LAT>
 static hipError_t tb_t(int n, int it, int len, double omega, const void* eo_, void* en_, const Lay& el,
-                       const void* rm_, const Lay& rl, double* u, const Lay& ul, const int* done,
-                       hipStream_t s) {
+                       const void* rm_, const Lay& rl, double* u, const Lay& ul, const L1Src<T>& l1,
+                       const int* done, hipStream_t s) {
   using C = typename Tr<T>::C;
   const T* eo = eo_ ? static_cast<const T*>(eo_) + el.off : nullptr;
   T* en = en_ ? static_cast<T*>(en_) + el.off : nullptr;
@@ -1730,23 +1956,28 @@ static hipError_t tb_t(int n, int it, int len, double omega, const void* eo_, vo
   const double h = 1.0 / double(n - 1);
   const C w = C(omega / 4.0), hl2 = C(h * h);
   const dim3 g((tb_waves(n, it, len) + 3) / 4);
+#define TB2_ARGS eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done, l1
   switch (it) {
-    case 1: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 1>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
-    case 2: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 2>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
-    case 3: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 3>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
-    default: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 4>), g, dim3(256), s, eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done);
+    case 1: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 1, LAT>), g, dim3(256), s, TB2_ARGS);
+    case 2: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 2, LAT>), g, dim3(256), s, TB2_ARGS);
+    case 3: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 3, LAT>), g, dim3(256), s, TB2_ARGS);
+    default: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 4, LAT>), g, dim3(256), s, TB2_ARGS);
   }
+#undef TB2_ARGS
 }
 
 template <typename T>
 static hipError_t tb_tz(int n, int it, int len, double omega, const void* eo, void* en, const Lay& el,
                         const void* rm, const Lay& rl, double* u, const Lay& ul, bool zero, bool accum,
-                        const int* done, hipStream_t s) {
+                        const L1State* l1, const int* done, hipStream_t s) {
+  const L1Src<T> v = l1_src<T>(l1);
+#define TB2_ARGS n, it, len, omega, eo, en, el, rm, rl, u, ul, v, done, s
+  if (l1)  // the pass takes its e from level 1's compact state
+    return accum ? tb_t<T, false, true, true>(TB2_ARGS) : tb_t<T, false, false, true>(TB2_ARGS);
   if (zero)
-    return accum ? tb_t<T, true, true>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s)
-                 : tb_t<T, true, false>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s);
-  return accum ? tb_t<T, false, true>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s)
-               : tb_t<T, false, false>(n, it, len, omega, eo, en, el, rm, rl, u, ul, done, s);
+    return accum ? tb_t<T, true, true, false>(TB2_ARGS) : tb_t<T, true, false, false>(TB2_ARGS);
+  return accum ? tb_t<T, false, true, false>(TB2_ARGS) : tb_t<T, false, false, false>(TB2_ARGS);
+#undef TB2_ARGS
 }
 
 template <typename T, bool ZERO, bool PREV>
@@ -1794,13 +2025,14 @@ hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const vo
 hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const void* eo, void* en,
                                  const Lay& el, const void* rm, const Lay& rl, double* u,
                                  const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s,
-                                 int len) {
+                                 int len, const L1State* l1) {
   if (len == 0) len = tb_band(n, it);
-  if (n < 3 || it < 1 || it > TB_MAX_IT || len < 1) return hipErrorInvalidValue;
+  if (n < 3 || it < 1 || it > TB_MAX_IT || len < 1 || (l1 && zero) || !l1_ok(l1, 2, n))
+    return hipErrorInvalidValue;
   switch (prec) {
-    case PREC_F64: return tb_tz<double>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
-    case PREC_F32: return tb_tz<float>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
-    default: return tb_tz<bf16>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, done, s);
+    case PREC_F64: return tb_tz<double>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, l1, done, s);
+    case PREC_F32: return tb_tz<float>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, l1, done, s);
+    default: return tb_tz<bf16>(n, it, len, omega, eo, en, el, rm, rl, u, ul, zero, accum, l1, done, s);
   }
 }
 
@@ -1821,10 +2053,10 @@ int tb3_band(int n, int it) {
   return 4;
 }
 
-template <typename T, bool ZERO, bool ACCUM, bool PREV>
+template <typename T, bool ZERO, bool ACCUM, bool PREV, bool LAT>
 static hipError_t tb3_t(int n, int it, int len, double omega, const void* eo_, void* en_, void* ep_,
                         const Lay& el, const void* rm_, const Lay& rl, double* u, const Lay& ul,
-                        bool compact, const int* done, hipStream_t s) {
+                        bool compact, const L1Src<T>& l1, const int* done, hipStream_t s) {
   using C = typename Tr<T>::C;
   const T* eo = eo_ ? static_cast<const T*>(eo_) + el.off : nullptr;
   T* en = en_ ? static_cast<T*>(en_) + el.off : nullptr;
@@ -1834,43 +2066,48 @@ static hipError_t tb3_t(int n, int it, int len, double omega, const void* eo_, v
   const double h = 1.0 / double(n - 1);
   const C w = C(omega / 6.0), hl2 = C(h * h);
   const dim3 g(tb3_blocks(n, it, len)), blk(BX3, BY3);
-  if (compact && !ACCUM) {  // compact lattice of a coarse level
+  if (!LAT && compact && !ACCUM) {  // compact lattice of a coarse level
     if (it == 1)
       HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 1>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
                   rl.pitch, rl.plane, n, len, w, hl2, done);
     HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 2>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
                 rl.pitch, rl.plane, n, len, w, hl2, done);
   }
-  if (it == 1)
-    HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 1>), g, blk, s, eo, en, el.pitch, el.plane, rm, rl.pitch,
-                rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done);
-  HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 2>), g, blk, s, eo, en, el.pitch, el.plane, rm, rl.pitch,
-              rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done);
+#define TB3_ARGS eo, en, el.pitch, el.plane, rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done, l1
+  if (it == 1) HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 1, LAT>), g, blk, s, TB3_ARGS);
+  HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 2, LAT>), g, blk, s, TB3_ARGS);
+#undef TB3_ARGS
 }
 
 template <typename T>
 static hipError_t tb3_tz(int n, int it, int len, double omega, const void* eo, void* en, void* eprev,
                          const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
-                         bool zero, bool accum, bool compact, const int* done, hipStream_t s) {
-#define TB3_ARGS n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, compact, done, s
+                         bool zero, bool accum, bool compact, const L1State* l1, const int* done,
+                         hipStream_t s) {
+  const L1Src<T> v = l1_src<T>(l1);
+#define TB3_ARGS n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, compact, v, done, s
+  if (l1)  // level 0 taking its e from level 1's compact state
+    return accum ? tb3_t<T, false, true, false, true>(TB3_ARGS) : tb3_t<T, false, false, false, true>(TB3_ARGS);
   if (accum)
-    return zero ? tb3_t<T, true, true, false>(TB3_ARGS) : tb3_t<T, false, true, false>(TB3_ARGS);
+    return zero ? tb3_t<T, true, true, false, false>(TB3_ARGS) : tb3_t<T, false, true, false, false>(TB3_ARGS);
   if (eprev)
-    return zero ? tb3_t<T, true, false, true>(TB3_ARGS) : tb3_t<T, false, false, true>(TB3_ARGS);
-  return zero ? tb3_t<T, true, false, false>(TB3_ARGS) : tb3_t<T, false, false, false>(TB3_ARGS);
+    return zero ? tb3_t<T, true, false, true, false>(TB3_ARGS) : tb3_t<T, false, false, true, false>(TB3_ARGS);
+  return zero ? tb3_t<T, true, false, false, false>(TB3_ARGS) : tb3_t<T, false, false, false, false>(TB3_ARGS);
 #undef TB3_ARGS
 }
 
 hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, void* en, void* eprev,
                         const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
-                        bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len) {
+                        bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len,
+                        const L1State* l1) {
   if (len == 0) len = tb3_band(n, it);
-  if (n < 3 || it < 1 || it > TB3_MAX_IT || len < 1 || (accum && (eprev || compact)))
+  if (n < 3 || it < 1 || it > TB3_MAX_IT || len < 1 || (accum && (eprev || compact)) ||
+      (l1 && (zero || compact || eprev)) || !l1_ok(l1, 3, n))
     return hipErrorInvalidValue;
   switch (prec) {
-    case PREC_F64: return tb3_tz<double>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, done, s);
-    case PREC_F32: return tb3_tz<float>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, done, s);
-    default: return tb3_tz<bf16>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, done, s);
+    case PREC_F64: return tb3_tz<double>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, l1, done, s);
+    case PREC_F32: return tb3_tz<float>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, l1, done, s);
+    default: return tb3_tz<bf16>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, l1, done, s);
   }
 }
 
