@@ -85,6 +85,8 @@ def kernel_symbol(d, kind, level, mode):
         return "k_lattice_sweep_%dd<double, %d%s>" % (d, mode & 3, var2)
     if kind == "level_write":
         return "k_level_write_%dd<double, %d>" % (d, mode)
+    if kind == "residual" and mode & 1:  # with the restriction to level 1
+        return "k_residual_restrict_%dd<double>" % d
     if kind == "residual":
         return "k_residual_%dd<double%s>" % (d, var2)
     if kind == "tail":
@@ -100,8 +102,8 @@ def kernel_bytes(d, n, entry):
     N = float(n) ** d
     if kind == "sweep":
         return sweep_bytes(d, n, level, mode) * entry["launches"]
-    if kind == "residual":
-        return (8 + 8 + 8) * N * entry["launches"]  # read u, f; write r (FP64)
+    if kind == "residual":  # read u, f; write r (FP64) and, fused, r restricted to level 1
+        return ((8 + 8 + 8) * N + (8 * N / 2 ** d if mode & 1 else 0)) * entry["launches"]
     if kind == "restrict":
         nf = (n - 1) // (1 << level) + 1
         Nf = float(nf) ** d

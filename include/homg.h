@@ -199,6 +199,7 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   lattice (level 0: of the whole grid), 9 hand-over of a finished coarse
  *   level to the lattice of `level` (chained execution), 10 the leading
  *   coarse levels down to `level` in one workgroup (chained execution).
+ *   mode (kind 1): 1 = the pass also restricts the residual to level 1;
  *   mode (kinds 4, 6, 7, 8): bit 0 = starts from e = 0, bit 1 = adds into u;
  *   bit 2 (kinds 6, 8) = every iteration of the level in one workgroup that
  *   holds the whole lattice; bit 3 (kinds 4, 6) = several iterations in one

@@ -454,6 +454,30 @@ int tail_levels(const homg_ctx* h, int* ms) {
   return cnt;
 }
 
+// Whether a solve's residual also restricts to level 1 in the same pass
+// (2D Laplacian whose schedule visits a coarse level).
+bool residual_restricts(const homg_ctx* h) {
+  return h->d == 2 && !h->has_coef && h->top_level >= 1 && h->n >= 5;
+}
+
+// r_0 = f - A u in the handle's precision with its norm partials (and, see
+// residual_restricts, r_1 = R r_0).
+homg_status enqueue_residual(homg_ctx* h, const double* f, const double* u, int* count,
+                             const int* done, hipStream_t s) {
+  if (residual_restricts(h)) {
+    LAUNCH_K(h, s, K_RESIDUAL, 0, 1,
+             launch_residual_restrict_2d(h->prec, h->n, u, h->dl, f, h->dl, h->r[0], h->rl[0], h->r[1],
+                                         h->rl[1], h->partials, count, done, s));
+    return HOMG_OK;
+  }
+  const Lay none;
+  const double* a0 = h->has_coef ? h->a[0] : nullptr;
+  LAUNCH_K(h, s, K_RESIDUAL, 0, 0,
+           launch_residual(h->prec, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none, h->r[0],
+                           h->rl[0], h->partials, count, done, s));
+  return HOMG_OK;
+}
+
 // Enqueue one MFMG cycle (Sec. 2): restriction pyramid of r_0, the
 // schedule's whole-grid iterations with the last one adding e into acc,
 // then (if f != null) the new residual and its norm as history[cycle].
@@ -461,11 +485,12 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
                           hipStream_t s) {
   int ms = 0;
   const int ntail = tail_levels(h, &ms);
-  for (int m = 0; m < (ntail ? ms : h->top_level); ++m)
+  // in a solve (f given) the residual that precedes every cycle already
+  // restricted r_0 to level 1
+  for (int m = f && residual_restricts(h) ? 1 : 0; m < (ntail ? ms : h->top_level); ++m)
     LAUNCH_K(h, s, K_RESTRICT, m, 0,
              launch_restrict(h->prec, h->d, h->r[m], h->rl[m], h->r[m + 1], h->rl[m + 1], done, s));
   int cur = 0;
-  const Lay none;
   const size_t np = h->sched.size() / 2;
   h->chain_ready = -1;
   h->l1_pending = false;
@@ -496,10 +521,7 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   }
   if (f) {
     int count = 0;
-    const double* a0 = h->has_coef ? h->a[0] : nullptr;
-    LAUNCH_K(h, s, K_RESIDUAL, 0, 0,
-             launch_residual(h->prec, h->d, h->n, acc, h->dl, f, h->dl, a0, a0 ? h->al[0] : none,
-                             h->r[0], h->rl[0], h->partials, &count, done, s));
+    if (homg_status e = enqueue_residual(h, f, acc, &count, done, s)) return e;
     LAUNCH_K(h, s, K_FINALIZE, 0, 1, launch_finalize(h->partials, count, h->st, h->hist, cycle, 1, s));
   }
   return HOMG_OK;
@@ -532,11 +554,7 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
   int count = 0;
   LAUNCH_K(h, s, K_NORM, 0, 0, launch_norm2(h->d, h->n, f, h->dl, h->partials, &count, s));
   LAUNCH_K(h, s, K_FINALIZE, 0, 0, launch_finalize(h->partials, count, h->st, h->hist, 0, 0, s));
-  const double* a0 = h->has_coef ? h->a[0] : nullptr;
-  const Lay none;
-  LAUNCH_K(h, s, K_RESIDUAL, 0, 0,
-           launch_residual(h->prec, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none,
-                           h->r[0], h->rl[0], h->partials, &count, done, s));
+  if (homg_status e = enqueue_residual(h, f, u, &count, done, s)) return e;
   LAUNCH_K(h, s, K_FINALIZE, 0, 1, launch_finalize(h->partials, count, h->st, h->hist, 0, 1, s));
 
   const int limit = stop_on_tol ? h->max_cycles : fixed_cycles;

@@ -53,6 +53,14 @@ hipError_t launch_residual(int prec, int d, int n, const double* u, const Lay& u
                            const double* f, const Lay& fl, const double* a, const Lay& al,
                            void* r0, const Lay& rl, double* partials, int* count,
                            const int* done, hipStream_t s);
+// 2D Laplacian (n >= 5): the residual of launch_residual and, in the same
+// pass, its full-weighting restriction to level 1 (rc, layout cl of side
+// (n-1)/2+1), equal bit for bit to launch_restrict applied to the stored r0.
+// Per-wave sums of r^2 (their number in *count).
+hipError_t launch_residual_restrict_2d(int prec, int n, const double* u, const Lay& ul,
+                                       const double* f, const Lay& fl, void* r0, const Lay& rl,
+                                       void* rc, const Lay& cl, double* partials, int* count,
+                                       const int* done, hipStream_t s);
 // Sums `count` partials in a fixed order.  mode 0: fnorm = sqrt(sum) and
 // resets the state; mode 1: history[cycle] = sqrt(sum)/fnorm and updates done.
 hipError_t launch_finalize(const double* partials, int count, DevState* st, double* history,

@@ -158,10 +158,38 @@ static dim3 grid_of(int d, int n, int len) {
   return dim3((inner + BX3 - 1) / BX3, (inner + BY3 - 1) / BY3, walks);
 }
 
+// The fused 2D residual + restriction (k_residual_restrict_2d): owned
+// columns per wave, waves for a band length, and its band length -- the
+// longest even band of at most 32 rows that still gives 4096 waves (else 2
+// rows), lengthened while that keeps the same number of full rounds of
+// resident waves (MI355X: 256 CUs x 32 waves), so that no short last round
+// of waves runs alone.
+constexpr int RR_W = 62;
+constexpr int RR_SLOTS = 256 * 32;
+static int rr_waves(int n, int len) {
+  return ((n - 2 + RR_W - 1) / RR_W) * ((n - 2 + len - 1) / len);
+}
+static int rr_band(int n) {
+  int len = 2;
+  for (int l : {32, 16, 8, 4})
+    if (rr_waves(n, l) >= 4096) {
+      len = l;
+      break;
+    }
+  const int rounds = rr_waves(n, len) / RR_SLOTS;
+  if (rounds >= 1)
+    while (rr_waves(n, len) > rounds * RR_SLOTS) len += 2;
+  return len;
+}
+
 int partials_bound(int d, int n) {
   if (n < 3) return 1;
   dim3 g = grid_of(d, n, walk_len(d, n));
   int64_t count = int64_t(g.x) * g.y * g.z;
+  if (d == 2) {  // the fused residual + restriction: one partial per wave
+    const int64_t w = rr_waves(n, rr_band(n));
+    if (w > count) count = w;
+  }
   if (d == 3) {  // the 3D residual's grid: 4 rows per lane, walks of 8 planes
     const int64_t inner = n - 2, len3 = inner < 8 ? inner : 8;
     const int64_t c3 = ((inner + BX3 - 1) / BX3) * ((inner + 4 * BY3 - 1) / (4 * BY3)) * ((inner + len3 - 1) / len3);
@@ -190,6 +218,15 @@ Lay padded_layout(int d, int side, int elem_bytes) {
   const int64_t rows = d == 3 ? int64_t(side) * side : side;
   L.alloc = L.off + rows * L.pitch + a;  // tail slack: whole final line
   return L;
+}
+
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (workgroup h
+// runs on XCD h % 8).  xcd_order maps h to a logical index so that each XCD
+// receives one contiguous range of logical workgroups (a bijection on
+// [0, count)).
+__device__ __forceinline__ unsigned xcd_order(unsigned h, unsigned count) {
+  const unsigned q = count / 8, rem = count % 8, x = h % 8;
+  return x * q + min(x, rem) + h / 8;
 }
 
 // ------------------------------------------------------------ norm of f
@@ -353,6 +390,65 @@ __global__ __launch_bounds__(256) void k_residual_3d(
     partials[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
 
+// 2D residual with the restriction to level 1 fused in.  Each wave walks a
+// band of rows over 64 columns and owns the inner 62 (lanes 1..62; lane 63
+// is a halo whose residual only feeds the restriction, lane 0 idles); it
+// also computes the first row of the next band, so that every level-1 node
+// whose fine rows start in the band (x = 2I on an owned even column, y = 2J
+// with 2J - 1 in the band) finds its 3 x 3 fine residuals in the wave: the
+// x neighbours by lane shuffles, the rows in a three-row window.  The fine
+// residual is rounded to T before it is restricted, as the separate
+// restriction would read it back, and the weights and their order are
+// those of tile_restrict_2d.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict_2d(
+    const double* __restrict__ u, int64_t up, const double* __restrict__ f, int64_t fp,
+    T* __restrict__ r, int64_t rp, T* __restrict__ rc, int64_t cp, int n, int len, double inv_h2,
+    double* __restrict__ partials, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  const int wv = __builtin_amdgcn_readfirstlane(int(xcd_order(blockIdx.x, gridDim.x)) * 4 +
+                                                int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int gx = (n - 2 + RR_W - 1) / RR_W;
+  if (wv >= gx * ((n - 2 + len - 1) / len)) return;  // the whole wave
+  const int x = (wv % gx) * RR_W + lane;
+  const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);  // len even: Y0 odd
+  const bool xin = x >= 1 && x <= n - 2;
+  const bool own = xin && lane >= 1 && lane <= RR_W;
+  const bool emit = (x & 1) == 0 && lane >= 2 && lane <= RR_W && x <= n - 3;
+  const int xc = min(x, n - 1);
+  double ym = u[int64_t(Y0 - 1) * up + xc], c = u[int64_t(Y0) * up + xc];
+  C rs2 = C(0), rs1 = C(0);  // row sums of rows y - 2, y - 1
+  double s = 0.0;
+  const int ylast = min(Y1, n - 2);  // the next band's first row, if interior
+  for (int y = Y0; y <= ylast; ++y) {
+    const double* row = u + int64_t(y) * up;
+    const double yp = row[up + xc];
+    // x neighbours from the neighbour lanes (lane 0's own residual is not
+    // used); lane 63's right neighbour lies past the wave
+    const double xm = __shfl_up(c, 1);
+    double xp = __shfl_down(c, 1);
+    if (lane == 63) xp = row[min(xc + 1, n - 1)];
+    const double au = fmac(4.0, c, -((xm + xp) + (ym + yp)));
+    const double rv = fmac(-inv_h2, au, f[int64_t(y) * fp + xc]);
+    const C rt = xin ? rnd<T>(C(rv)) : C(0);
+    if (own && y < Y1) {
+      st(r + int64_t(y) * rp + x, C(rv));
+      s = fmac(rv, rv, s);
+    }
+    const C rs = fmac(C(2), rt, __shfl_up(rt, 1) + __shfl_down(rt, 1));
+    if ((y & 1) && y >= Y0 + 2 && emit)  // y = 2J + 1: level-1 node (x / 2, J) complete
+      st(rc + int64_t(y >> 1) * cp + (x >> 1), fmac(C(2), rs1, rs2 + rs) * C(0.0625));
+    rs2 = rs1;
+    rs1 = rs;
+    ym = c;
+    c = yp;
+  }
+  s = wave_sum(s);
+  if (lane == 0) partials[wv] = s;
+}
+
 // ------------------------------------------------------------ finalize
 
 __global__ __launch_bounds__(256) void k_init_state(DevState* st, double tol, int stop_on_tol) {
@@ -468,15 +564,6 @@ __device__ __forceinline__ void emit_2d(T* en, int64_t eoff, double* u, int64_t 
   } else {
     st(en + eoff, v);
   }
-}
-
-// Workgroups of a launch are dealt to the 8 XCDs round-robin (workgroup h
-// runs on XCD h % 8).  xcd_order maps h to a logical index so that each XCD
-// receives one contiguous range of logical workgroups (a bijection on
-// [0, count)).
-__device__ __forceinline__ unsigned xcd_order(unsigned h, unsigned count) {
-  const unsigned q = count / 8, rem = count % 8, x = h % 8;
-  return x * q + min(x, rem) + h / 8;
 }
 
 // Level 0: every interior node relaxes (plain damped Jacobi).  The walk
@@ -1834,6 +1921,33 @@ hipError_t launch_residual(int prec, int d, int n, const double* u, const Lay& u
     case PREC_F64: return residual_t<double>(d, n, u, ul, f, fl, a, al, r0, rl, partials, count, done, s);
     case PREC_F32: return residual_t<float>(d, n, u, ul, f, fl, a, al, r0, rl, partials, count, done, s);
     default: return residual_t<bf16>(d, n, u, ul, f, fl, a, al, r0, rl, partials, count, done, s);
+  }
+}
+
+template <typename T>
+static hipError_t residual_restrict_t(int n, const double* u, const Lay& ul, const double* f,
+                                      const Lay& fl, void* r0, const Lay& rl, void* rc0,
+                                      const Lay& cl, double* partials, int* count, const int* done,
+                                      hipStream_t s) {
+  const int len = rr_band(n);
+  const int waves = rr_waves(n, len);
+  *count = waves;
+  const double h = 1.0 / double(n - 1);
+  const double inv_h2 = 1.0 / (h * h);
+  HOMG_LAUNCH((k_residual_restrict_2d<T>), dim3((waves + 3) / 4), dim3(256), s, u + ul.off, ul.pitch,
+              f + fl.off, fl.pitch, static_cast<T*>(r0) + rl.off, rl.pitch, static_cast<T*>(rc0) + cl.off,
+              cl.pitch, n, len, inv_h2, partials, done);
+}
+
+hipError_t launch_residual_restrict_2d(int prec, int n, const double* u, const Lay& ul,
+                                       const double* f, const Lay& fl, void* r0, const Lay& rl,
+                                       void* rc, const Lay& cl, double* partials, int* count,
+                                       const int* done, hipStream_t s) {
+  if (n < 5 || (n - 1) % 2 || cl.side != (n - 1) / 2 + 1) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return residual_restrict_t<double>(n, u, ul, f, fl, r0, rl, rc, cl, partials, count, done, s);
+    case PREC_F32: return residual_restrict_t<float>(n, u, ul, f, fl, r0, rl, rc, cl, partials, count, done, s);
+    default: return residual_restrict_t<bf16>(n, u, ul, f, fl, r0, rl, rc, cl, partials, count, done, s);
   }
 }
 

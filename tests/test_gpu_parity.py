@@ -408,6 +408,29 @@ def test_repeat_solves_bitwise_identical(B, torch_cuda):
         assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("n", [5, 9, 65, 129, 1025])
+def test_solve_cycle_equals_residual_then_step_cycle(B, torch_cuda, n, prec):
+    """A solve's residual pass also restricts r_0 to level 1 (2D Laplacian);
+    one solve cycle must equal the residual entry point followed by the step
+    cycle, which restricts with the separate kernel: bit for bit, from a
+    non-zero initial guess, for band and wave counts with ragged ends."""
+    torch = torch_cuda
+    say("fused residual n=%d prec=%s" % (n, prec))
+    rng = np.random.default_rng(500 + n)
+    f = dev(torch, W.uniform(2, n, seed=21))
+    u0 = dev(torch, rand_interior(rng, 2, n))
+    s = B.Solver(2, n, precision=prec)
+    ua = u0.clone()
+    s.solve_cycles(f, ua, 1)
+    r0 = torch.zeros_like(u0)
+    s.residual(f, u0, r0)
+    ub = u0.clone()
+    s.step_cycle(r0, ub)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ua), host(ub))
+
+
 def test_residual_entry_point(B, torch_cuda):
     torch = torch_cuda
     for d, n in ((2, 257), (3, 33)):
