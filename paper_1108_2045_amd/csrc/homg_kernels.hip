@@ -910,7 +910,6 @@ __device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict_
   constexpr int VALID = 64 - 2 * IT;
   const int lane = threadIdx.x & 63;
   const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + len - 1) / len;
-  wv = __builtin_amdgcn_readfirstlane(wv);  // one value per wave: rows and bands stay scalar
   if (wv >= gx * gy) return;  // the whole wave
   const int x = 1 + (wv % gx) * VALID - IT + lane;
   const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);
@@ -1143,7 +1142,8 @@ __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict
   const int gx = (n - 2 + VX - 1) / VX, gy = (n - 2 + VY - 1) / VY;
   const int lg = int(xcd_order(blockIdx.x, gridDim.x));
   const int bx = lg % gx, by = (lg / gx) % gy, bz = lg / (gx * gy);
-  const int lx = threadIdx.x, row0 = threadIdx.y * TB3_R;
+  // threadIdx.y is one value per wave: keep the rows (and their offsets) scalar
+  const int lx = threadIdx.x, row0 = __builtin_amdgcn_readfirstlane(int(threadIdx.y) * TB3_R);
   const int x = 1 + bx * VX - IT + lx;
   const int yb = 1 + by * VY - IT + row0;  // first of the lane's rows
   const int Z0 = 1 + bz * len, Z1 = min(n - 1, Z0 + len);
