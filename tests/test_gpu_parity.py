@@ -409,18 +409,20 @@ def test_repeat_solves_bitwise_identical(B, torch_cuda):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-@pytest.mark.parametrize("n", [5, 9, 65, 129, 1025])
-def test_solve_cycle_equals_residual_then_step_cycle(B, torch_cuda, n, prec):
-    """A solve's residual pass also restricts r_0 to level 1 (2D Laplacian);
-    one solve cycle must equal the residual entry point followed by the step
-    cycle, which restricts with the separate kernel: bit for bit, from a
-    non-zero initial guess, for band and wave counts with ragged ends."""
+@pytest.mark.parametrize("d,n", [(2, 5), (2, 9), (2, 65), (2, 129), (2, 1025),
+                                 (3, 5), (3, 9), (3, 17), (3, 33), (3, 65), (3, 129)])
+def test_solve_cycle_equals_residual_then_step_cycle(B, torch_cuda, d, n, prec):
+    """A solve's residual pass also restricts r_0 to level 1 (2D Laplacian;
+    3D keeps separate residual and restriction launches); one solve cycle
+    must equal the residual entry point followed by the step cycle, which
+    restricts with the separate kernel: bit for bit, from a non-zero initial
+    guess, for tile, band and wave counts with ragged ends."""
     torch = torch_cuda
-    say("fused residual n=%d prec=%s" % (n, prec))
+    say("fused residual d=%d n=%d prec=%s" % (d, n, prec))
     rng = np.random.default_rng(500 + n)
-    f = dev(torch, W.uniform(2, n, seed=21))
-    u0 = dev(torch, rand_interior(rng, 2, n))
-    s = B.Solver(2, n, precision=prec)
+    f = dev(torch, W.uniform(d, n, seed=21))
+    u0 = dev(torch, rand_interior(rng, d, n))
+    s = B.Solver(d, n, precision=prec)
     ua = u0.clone()
     s.solve_cycles(f, ua, 1)
     r0 = torch.zeros_like(u0)
