@@ -77,8 +77,9 @@ def kernel_symbol(d, kind, level, mode):
         base = "k_sweep_%dd_%s" % (d, "l0" if level == 0 else "coarse")
         return "%s<double, %d%s>" % (base, mode, var2)
     if kind == "lattice" and mode & 8:  # several compact-lattice iterations in one pass
-        return "k_lattice_%dd_tb<double, %s, %s, %d>" % (
-            d, "true" if mode & 1 else "false", "true" if mode & 64 else "false", ((mode >> 4) & 3) + 1)
+        return "k_lattice_%dd_tb<double, %s, %s, %d, %s>" % (
+            d, "true" if mode & 1 else "false", "true" if mode & 64 else "false", ((mode >> 4) & 3) + 1,
+            "true" if mode & 128 else "false")
     if kind == "lattice":
         if mode & 4:
             return "k_lattice_small_%dd<double, %s%s>" % (d, "true" if mode & 1 else "false", var2)
@@ -114,7 +115,8 @@ def kernel_bytes(d, n, entry):
     if kind == "gather":
         return 16 * lat * entry["launches"]
     if kind == "lattice" and mode & 8:  # one pass: read x_0, r; write x_it (and x_{it-1})
-        return ((0 if mode & 1 else 8) + 8 + 8 + (8 if mode & 64 else 0)) * lat * entry["launches"]
+        x0 = 16.0 / 2 ** d if mode & 128 else (0 if mode & 1 else 8)  # or the coarser level's two states
+        return (x0 + 8 + 8 + (8 if mode & 64 else 0)) * lat * entry["launches"]
     if kind == "lattice":
         if mode & 4:  # whole lattice in one workgroup: read x_0, r; write two iterates
             return ((0 if mode & 1 else 8) + 8 + 16) * lat * entry["launches"]

@@ -80,9 +80,10 @@ typedef struct homg_options {
     int temporal_block;    /* 2 (default): chained -- the iterations of a coarse level run on its
                               compact lattice, a coarse level followed by another coarse level
                               hands over only that level's lattice values, and the whole grid is
-                              written only before level 0 or the last level (before level 0 of a
-                              Laplacian with damped Jacobi not at all: level 0's first pass
-                              interpolates level 1's lattice values itself);
+                              written only before level 0 or the last level; for a Laplacian
+                              with damped Jacobi, a level followed by the next finer one hands
+                              over nothing: the finer level's first pass interpolates the
+                              coarser level's lattice values itself (level 0 included);
                               1: level-blocked -- as 2, but the whole grid is written after every
                               level;
                               0: one whole-grid launch per iteration.
@@ -204,9 +205,11 @@ homg_status homg_step_cycle(homg_handle h, const double *r0, double *acc, void *
  *   bit 2 (kinds 6, 8) = every iteration of the level in one workgroup that
  *   holds the whole lattice; bit 3 (kinds 4, 6) = several iterations in one
  *   temporally blocked pass, bits 4-5 their number minus one, bit 6 (kind
- *   6) = the pass also stores the iterate before its last, bit 7 (kind 4,
- *   level 0) = the pass takes its first iterate from level 1's compact
- *   lattice state (chained execution: no whole-grid write before level 0).
+ *   6) = the pass also stores the iterate before its last, bit 7 (kinds 4,
+ *   6) = the pass takes its first iterate from the next coarser level's
+ *   compact state (chained execution: no hand-over or whole-grid write in
+ *   between); mode (kind 10): 1 = the tail leaves its finest level's state
+ *   for the next level's first pass instead of handing over.
  * homg_get_profile synchronises outstanding events, then writes up to cap
  * entries and their count in *len.
  */

@@ -89,10 +89,11 @@ struct homg_ctx {
   Profiler prof;
   // learned relaxation (2D): 0 damped Jacobi, 1 the network with weights w
   int chain_ready = -1;        // chained path: level whose x_0 the previous level already wrote
-  // chained path: level 1's compact final state, which the first level-0
-  // pass interpolates itself (no whole-grid write in between)
-  bool l1_pending = false;
-  L1State l1;
+  // chained path: the compact final state of level lat_level + 1, which
+  // the first pass of level lat_level interpolates itself (no hand-over or
+  // whole-grid write in between); -1: none pending
+  int lat_level = -1;
+  L1State lat;
   int smoother = 0;
   int active_smoother = 0;     // smoother of the solve in progress (after any fallback)
   double fallback_ratio = 1.0; // per-cycle contraction at which a solve falls back to Jacobi
@@ -226,6 +227,23 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
 homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, void* xprev,
                          void* xcur, int* cur, double* acc, const int* done, hipStream_t s);
 
+// Whether level mt's iterations (chained execution, Laplacian, damped
+// Jacobi) run as multi-iteration passes whose first pass can take its input
+// iterate from level mt + 1's compact state: level 0, or a compact lattice
+// too large for one workgroup.  In 3D a compact lattice does so only after
+// the coarse tail (whose own one-workgroup hand-over is slow): after a
+// separate level the hand-over kernel plus a plain pass measured as fast or
+// faster (MI355X, 257^3: 31 against 31 us at 129^3, 13 against 16 us at 65^3).
+bool lat_target(const homg_ctx* h, int mt, bool from_tail) {
+  if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || mt < 0) return false;
+  const int nm = (h->n - 1) / (1 << mt) + 1;
+  if (nm < 5 || mt + 1 >= h->levels) return false;
+  if (mt == 0) return true;
+  if (h->d == 3 && !from_tail) return false;
+  return lattice_small_lds(h->prec, h->d, nm, false) > h->lds_limit && mt < int(h->xp3.size()) &&
+         h->xp3[mt];
+}
+
 homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int next_m, int* cur,
                       double* acc, const int* done, hipStream_t s) {
   if (h->active_smoother == 1) return run_level_learned(h, m, it, first, last, next_m, cur, acc, done, s);
@@ -235,9 +253,9 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
   // One launch per iteration: level 0 always (every node is a lattice
   // node), every level when blocking is off, and a coarse last level in
   // reduced precision (its iterate goes into u unrounded).
-  // chained path: the first level-0 pass reads level 1's compact state
-  const L1State* l1 = (m == 0 && h->l1_pending) ? &h->l1 : nullptr;
-  if (m == 0) h->l1_pending = false;
+  // chained path: the first pass reads the next coarser level's compact state
+  const L1State* l1 = h->lat_level == m ? &h->lat : nullptr;
+  h->lat_level = -1;
   if (m == 0 && h->d == 3 && h->temporal) {
     // level 0 in 3D: up to TB3_MAX_IT iterations per pass, same iterates
     for (int t0 = 0; t0 < it; t0 += TB3_MAX_IT) {
@@ -269,7 +287,8 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
     }
     return HOMG_OK;
   }
-  if (l1) return fail(h, HOMG_ERR_UNSUPPORTED, "level 1 left no whole-grid state for level 0");
+  if (l1 && (m == 0 || !h->temporal || (last && h->prec != PREC_F64)))
+    return fail(h, HOMG_ERR_UNSUPPORTED, "the coarser level left no state for this level's iterations");
   if (m == 0 || !h->temporal || (last && h->prec != PREC_F64)) {
     for (int t = 0; t < it; ++t) {
       int mode = 0;
@@ -293,6 +312,8 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
   // chained path: the previous level already left x_0 in X0
   const bool chained_in = !first && h->chain_ready == m;
   h->chain_ready = -1;
+  if (l1 && !lat_target(h, m, true))
+    return fail(h, HOMG_ERR_UNSUPPORTED, "the coarser level left no state for this level's iterations");
   if (lattice_small_lds(h->prec, h->d, nm, am != nullptr) <= h->lds_limit) {
     LAUNCH_K(h, s, K_LATTICE, m, 4 | (first ? 1 : 0),
              launch_lattice_small(h->prec, h->d, nm, chained_in ? 1 : l, it, h->omega, first,
@@ -302,7 +323,7 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
     xcur = X1;
   } else if (!am && m < int(h->xp3.size()) && h->xp3[m]) {
     // Laplacian: several iterations per pass over the lattice
-    if (!first && !chained_in)
+    if (!first && !chained_in && !l1)
       LAUNCH_K(h, s, K_GATHER, m, 0, launch_gather(h->prec, h->d, h->e[*cur], h->el, l, X0, cl, done, s));
     void* X[2] = {X0, X1};
     int src = 0;
@@ -311,13 +332,17 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
     for (int t0 = 0; t0 < it; t0 += gmax) {
       const int g = std::min(gmax, it - t0);
       const bool zero = first && t0 == 0, lastg = t0 + g == it;
-      void* pv = (lastg && g > 1) ? h->xp3[m] : nullptr;
+      // the first pass may take x_0 from the coarser level's state (x_0 is
+      // then never stored: a single-iteration last pass stores it as x_{it-1})
+      const L1State* ls = t0 == 0 ? l1 : nullptr;
+      void* pv = (lastg && (g > 1 || ls)) ? h->xp3[m] : nullptr;
       const Lay none;
-      LAUNCH_K(h, s, K_LATTICE, m, SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | ((g - 1) << 4) | (pv ? 64 : 0),
+      LAUNCH_K(h, s, K_LATTICE, m,
+               SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | ((g - 1) << 4) | (pv ? 64 : 0) | (ls ? 128 : 0),
                h->d == 2 ? launch_lattice_2d_tb(h->prec, nm, g, h->omega, X[src], X[1 - src], pv, cl,
-                                                h->r[m], h->rl[m], zero, done, s)
+                                                h->r[m], h->rl[m], zero, done, s, 0, ls)
                          : launch_tb_3d(h->prec, nm, g, h->omega, X[src], X[1 - src], pv, cl, h->r[m],
-                                        h->rl[m], nullptr, none, zero, false, true, done, s));
+                                        h->rl[m], nullptr, none, zero, false, true, done, s, 0, ls));
       if (lastg) xprev = pv ? pv : X[src];
       src = 1 - src;
     }
@@ -349,15 +374,14 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
 // always whole-grid.
 homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, void* xprev,
                          void* xcur, int* cur, double* acc, const int* done, hipStream_t s) {
-  // chained path into a temporally blocked level 0 (Laplacian, damped
-  // Jacobi): its first pass interpolates level 1's compact state itself
-  if (h->temporal == 2 && !last && m == 1 && next_m == 0 && h->active_smoother == 0 && !h->has_coef &&
-      h->n >= 5) {
-    h->l1.prev = (wmode & SW_ZERO_OLD) ? nullptr : xprev;
-    h->l1.cur = xcur;
-    h->l1.cl = h->rl[1];
-    h->l1.zero_old = (wmode & SW_ZERO_OLD) != 0;
-    h->l1_pending = true;
+  // chained path into the next finer level's multi-iteration passes: its
+  // first pass interpolates this level's compact state itself
+  if (!last && next_m == m - 1 && lat_target(h, next_m, false)) {
+    h->lat.prev = (wmode & SW_ZERO_OLD) ? nullptr : xprev;
+    h->lat.cur = xcur;
+    h->lat.cl = h->rl[m];
+    h->lat.zero_old = (wmode & SW_ZERO_OLD) != 0;
+    h->lat_level = next_m;
     return HOMG_OK;
   }
   if (h->temporal == 2 && !last && next_m >= 1 && next_m != m) {
@@ -493,16 +517,29 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   int cur = 0;
   const size_t np = h->sched.size() / 2;
   h->chain_ready = -1;
-  h->l1_pending = false;
+  h->lat_level = -1;
   size_t p0 = 0;
   if (ntail) {
     int its[BATCH_MAX_LEVELS];
     for (int k = 0; k < ntail; ++k) its[k] = h->sched[2 * (ntail - 1 - k) + 1];
     const int nms = (h->n - 1) / (1 << ms) + 1;
-    LAUNCH_K(h, s, K_TAIL, ms, 0,
-             launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms],
-                                h->xc[2 * (ms - 1)], h->rl[ms - 1], done, s));
-    h->chain_ready = ms - 1;
+    const bool next_last = size_t(ntail) + 1 == np;
+    if (lat_target(h, ms - 1, true) && !(next_last && h->prec != PREC_F64)) {
+      // the tail leaves level ms's state; level ms - 1's first pass interpolates it
+      LAUNCH_K(h, s, K_TAIL, ms, 1,
+               launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms], nullptr,
+                                  Lay(), done, s, h->xc[2 * ms], h->xc[2 * ms + 1], h->rl[ms]));
+      h->lat.prev = h->xc[2 * ms];
+      h->lat.cur = h->xc[2 * ms + 1];
+      h->lat.cl = h->rl[ms];
+      h->lat.zero_old = false;
+      h->lat_level = ms - 1;
+    } else {
+      LAUNCH_K(h, s, K_TAIL, ms, 0,
+               launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms],
+                                  h->xc[2 * (ms - 1)], h->rl[ms - 1], done, s));
+      h->chain_ready = ms - 1;
+    }
     p0 = size_t(ntail);
   }
   for (size_t p = p0; p < np; ++p) {

@@ -94,11 +94,14 @@ __host__ __device__ inline int tb_waves(int n, int it, int len) {
   return ((n - 2 + valid - 1) / valid) * ((n - 2 + len - 1) / len);
 }
 int tb_band(int n, int it);
-// Level 1's final compact state (layout cl, side (n-1)/2+1): x_it in cur and
-// x_{it-1} in prev (unread when zero_old: x_{it-1} = 0).  A level-0 pass
-// given one takes its input e from it -- lattice nodes x_it, every other
-// interior node the multilinear interpolant of x_{it-1}, exactly as the
-// level-1 whole-grid write would have stored them -- instead of reading eo.
+// A coarse level's final compact state (layout cl, side (n-1)/2+1 for a
+// pass over side n): x_it in cur and x_{it-1} in prev (unread when
+// zero_old: x_{it-1} = 0).  A pass given one -- level 0 after level 1, or
+// the compact lattice of level m after level m + 1, which sits in it the
+// same way -- takes its input iterate from it: lattice nodes of the
+// coarser level x_it, every other interior node the multilinear
+// interpolant of x_{it-1}, exactly as the coarser level's whole-grid write
+// (or hand-over) would have stored them, instead of reading eo.
 struct L1State {
   const void* prev = nullptr;
   const void* cur = nullptr;
@@ -110,15 +113,17 @@ hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const vo
                                  const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s,
                                  int len = 0, const L1State* l1 = nullptr);
 // The same on the compact lattice of a coarse level (side nm): x_it into en
-// and, when eprev is not null, x_{it-1} into eprev (layout cl).
+// and, when eprev is not null, x_{it-1} into eprev (layout cl); l1: x_0
+// from the next coarser level's state.
 hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const void* eo, void* en,
                                 void* eprev, const Lay& cl, const void* rm, const Lay& rl, bool zero,
-                                const int* done, hipStream_t s, int len = 0);
+                                const int* done, hipStream_t s, int len = 0, const L1State* l1 = nullptr);
 // 3D (7-point Laplacian) counterpart: `it` (<= TB3_MAX_IT) iterations in one
 // pass over the level-0 grid or (compact) a coarse level's lattice of side
 // n (layout el for eo, en, eprev; r in rl); accum (level 0 only): add x_it
 // into u (dense FP64, ul) instead of storing it; eprev (compact only): also
-// store x_{it-1}.  A block walks
+// store x_{it-1}; l1: the input iterate from the next coarser level's
+// state (not with zero).  A block walks
 // `len` planes (0: tb3_band's choice: the longest of 32, 16, 8 planes that
 // still gives TB3_MIN_BLOCKS blocks, else 4).
 constexpr int TB3_MAX_IT = 2;
@@ -157,11 +162,15 @@ hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double o
 // descends one level at a time, run by one workgroup in LDS: restriction
 // of r_ms (side nms, layout rl) to the coarser levels, its[k] iterations of
 // level ms + k, and the hand-over of level ms's final state to the compact
-// x_0 of level ms - 1 (dst, layout tl).  coarse_tail_lds: its LDS bytes.
+// x_0 of level ms - 1 (dst, layout tl) -- or, given scur, level ms's final
+// x_it and x_{it-1} at every node into scur and sprev (layout sl, side nms)
+// for a next pass that interpolates them itself.  coarse_tail_lds: its LDS
+// bytes.
 size_t coarse_tail_lds(int prec, int d, int nms, int nlev);
 hipError_t launch_coarse_tail(int prec, int d, int nms, int nlev, const int* its, double omega,
                               const void* rms, const Lay& rl, void* dst, const Lay& tl,
-                              const int* done, hipStream_t s);
+                              const int* done, hipStream_t s, void* sprev = nullptr,
+                              void* scur = nullptr, const Lay& sl = Lay());
 // LDS bytes of the whole-grid pass of level m.
 size_t level_write_lds(int prec, int d, int n, int m);
 // Whole-grid pass of level m from compact x_{it-1} (xprev) and x_it (xcur):

@@ -950,15 +950,17 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
 
 // The same pass over the compact lattice of a coarse level (n = its side),
 // optionally also storing the iterate before the last (PREV), which the
-// level's whole-grid pass interpolates.
-template <typename T, bool ZERO, bool PREV, int IT>
+// level's whole-grid pass interpolates.  LAT: x_0 is the next coarser
+// level's final state seen on this lattice (the compact lattice of level m
+// sits in that of level m + 1 as level 0 sits in level 1).
+template <typename T, bool ZERO, bool PREV, int IT, bool LAT>
 __global__ __launch_bounds__(256) void k_lattice_2d_tb(
     const T* __restrict__ eo, T* __restrict__ en, T* __restrict__ eprev, int64_t ep,
     const T* __restrict__ r, int64_t rp, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
-    const int* __restrict__ done) {
+    const int* __restrict__ done, L1Src<T> l1) {
   if (*done) return;
   const int wv = int(xcd_order(blockIdx.x, gridDim.x)) * 4 + int(threadIdx.x >> 6);
-  tb_body<T, ZERO, false, PREV, IT>(eo, en, eprev, ep, r, rp, nullptr, 0, n, len, w, hl2, wv);
+  tb_body<T, ZERO, false, PREV, IT, LAT>(eo, en, eprev, ep, r, rp, nullptr, 0, n, len, w, hl2, wv, l1);
 }
 
 // Levels m >= 1: lattice nodes relax, the rest interpolate.  The lane keeps
@@ -1246,13 +1248,14 @@ __global__ __launch_bounds__(256) void k_sweep_3d_l0_tb(
                                            l1);
 }
 
-template <typename T, bool ZERO, bool PREV, int IT>
+template <typename T, bool ZERO, bool PREV, int IT, bool LAT>
 __global__ __launch_bounds__(256) void k_lattice_3d_tb(
     const T* __restrict__ eo, T* __restrict__ en, T* __restrict__ eprev, int64_t ep, int64_t epl,
     const T* __restrict__ r, int64_t rp, int64_t rpl, int n, int len, typename Tr<T>::C w,
-    typename Tr<T>::C hl2, const int* __restrict__ done) {
+    typename Tr<T>::C hl2, const int* __restrict__ done, L1Src<T> l1) {
   if (*done) return;
-  tb3_body<T, ZERO, false, PREV, IT>(eo, en, eprev, ep, epl, r, rp, rpl, nullptr, 0, 0, n, len, w, hl2);
+  tb3_body<T, ZERO, false, PREV, IT, LAT>(eo, en, eprev, ep, epl, r, rp, rpl, nullptr, 0, 0, n, len, w, hl2,
+                                          l1);
 }
 
 // The same iteration on the compact lattice of a coarse level (the
@@ -1689,7 +1692,8 @@ __device__ __forceinline__ void tail_split(int i, int s, float inv_s, int& I, in
 template <typename T, int D>
 __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     const T* __restrict__ rms, int64_t rp, int64_t rpl, T* __restrict__ dst, int64_t dp, int64_t dpl,
-    int nms, int nlev, TailIts its, typename Tr<T>::C w, const int* __restrict__ done) {
+    int nms, int nlev, TailIts its, typename Tr<T>::C w, const int* __restrict__ done,
+    T* __restrict__ sprev, T* __restrict__ scur, int64_t sp, int64_t spl) {
   using C = typename Tr<T>::C;
   if (*done) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1777,6 +1781,19 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     }
     const C* cur = (it & 1) ? xb : xa;
     const C* prv = (it & 1) ? xa : xb;
+    if (k == 0 && scur) {
+      // level ms's final state (every node) for the next level's first
+      // pass, which interpolates it itself
+      const float sinv = 1.0f / float(nk);
+      for (int j = threadIdx.x; j < tail_count<D>(nk); j += SMALL_NT) {
+        int I, J, K;
+        tail_split<D>(j, nk, sinv, I, J, K);
+        const int64_t o = (D == 3 ? int64_t(K) * spl : 0) + int64_t(J) * sp + I;
+        st(sprev + o, prv[j]);
+        st(scur + o, cur[j]);
+      }
+      break;
+    }
     // hand-over to level ms + k - 1 (side nt = 2 nk - 1): lattice nodes of
     // this level take x_it, the others the interpolant of x_{it-1}
     const int nt = 2 * nk - 1, ptl = nt * nt, nti = nt - 2;
@@ -2094,9 +2111,10 @@ static hipError_t tb_tz(int n, int it, int len, double omega, const void* eo, vo
 #undef TB2_ARGS
 }
 
-template <typename T, bool ZERO, bool PREV>
+template <typename T, bool ZERO, bool PREV, bool LAT>
 static hipError_t ltb_t(int nm, int it, int len, double omega, const void* eo_, void* en_, void* ep_,
-                        const Lay& cl, const void* rm_, const Lay& rl, const int* done, hipStream_t s) {
+                        const Lay& cl, const void* rm_, const Lay& rl, const L1Src<T>& l1, const int* done,
+                        hipStream_t s) {
   using C = typename Tr<T>::C;
   const T* eo = eo_ ? static_cast<const T*>(eo_) + cl.off : nullptr;
   T* en = static_cast<T*>(en_) + cl.off;
@@ -2105,34 +2123,40 @@ static hipError_t ltb_t(int nm, int it, int len, double omega, const void* eo_, 
   const double h = 1.0 / double(nm - 1);
   const C w = C(omega / 4.0), hl2 = C(h * h);
   const dim3 g((tb_waves(nm, it, len) + 3) / 4);
+#define LTB_ARGS eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done, l1
   switch (it) {
-    case 1: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 1>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
-    case 2: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 2>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
-    case 3: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 3>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
-    default: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 4>), g, dim3(256), s, eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done);
+    case 1: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 1, LAT>), g, dim3(256), s, LTB_ARGS);
+    case 2: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 2, LAT>), g, dim3(256), s, LTB_ARGS);
+    case 3: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 3, LAT>), g, dim3(256), s, LTB_ARGS);
+    default: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 4, LAT>), g, dim3(256), s, LTB_ARGS);
   }
+#undef LTB_ARGS
 }
 
 template <typename T>
 static hipError_t ltb_tz(int nm, int it, int len, double omega, const void* eo, void* en, void* eprev,
-                         const Lay& cl, const void* rm, const Lay& rl, bool zero, const int* done,
-                         hipStream_t s) {
+                         const Lay& cl, const void* rm, const Lay& rl, bool zero, const L1State* l1,
+                         const int* done, hipStream_t s) {
+  const L1Src<T> v = l1_src<T>(l1);
+#define LTB_ARGS nm, it, len, omega, eo, en, eprev, cl, rm, rl, v, done, s
+  if (l1)
+    return eprev ? ltb_t<T, false, true, true>(LTB_ARGS) : ltb_t<T, false, false, true>(LTB_ARGS);
   if (zero)
-    return eprev ? ltb_t<T, true, true>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s)
-                 : ltb_t<T, true, false>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s);
-  return eprev ? ltb_t<T, false, true>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s)
-               : ltb_t<T, false, false>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, done, s);
+    return eprev ? ltb_t<T, true, true, false>(LTB_ARGS) : ltb_t<T, true, false, false>(LTB_ARGS);
+  return eprev ? ltb_t<T, false, true, false>(LTB_ARGS) : ltb_t<T, false, false, false>(LTB_ARGS);
+#undef LTB_ARGS
 }
 
 hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const void* eo, void* en,
                                 void* eprev, const Lay& cl, const void* rm, const Lay& rl, bool zero,
-                                const int* done, hipStream_t s, int len) {
+                                const int* done, hipStream_t s, int len, const L1State* l1) {
   if (len == 0) len = tb_band(nm, it);
-  if (nm < 3 || it < 1 || it > TB_MAX_IT || len < 1) return hipErrorInvalidValue;
+  if (nm < 3 || it < 1 || it > TB_MAX_IT || len < 1 || (l1 && zero) || !l1_ok(l1, 2, nm))
+    return hipErrorInvalidValue;
   switch (prec) {
-    case PREC_F64: return ltb_tz<double>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, done, s);
-    case PREC_F32: return ltb_tz<float>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, done, s);
-    default: return ltb_tz<bf16>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, done, s);
+    case PREC_F64: return ltb_tz<double>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, l1, done, s);
+    case PREC_F32: return ltb_tz<float>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, l1, done, s);
+    default: return ltb_tz<bf16>(nm, it, len, omega, eo, en, eprev, cl, rm, rl, zero, l1, done, s);
   }
 }
 
@@ -2180,12 +2204,12 @@ static hipError_t tb3_t(int n, int it, int len, double omega, const void* eo_, v
   const double h = 1.0 / double(n - 1);
   const C w = C(omega / 6.0), hl2 = C(h * h);
   const dim3 g(tb3_blocks(n, it, len)), blk(BX3, BY3);
-  if (!LAT && compact && !ACCUM) {  // compact lattice of a coarse level
+  if (compact && !ACCUM) {  // compact lattice of a coarse level
     if (it == 1)
-      HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 1>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
-                  rl.pitch, rl.plane, n, len, w, hl2, done);
-    HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 2>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
-                rl.pitch, rl.plane, n, len, w, hl2, done);
+      HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 1, LAT>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
+                  rl.pitch, rl.plane, n, len, w, hl2, done, l1);
+    HOMG_LAUNCH((k_lattice_3d_tb<T, ZERO, PREV, 2, LAT>), g, blk, s, eo, en, epv, el.pitch, el.plane, rm,
+                rl.pitch, rl.plane, n, len, w, hl2, done, l1);
   }
 #define TB3_ARGS eo, en, el.pitch, el.plane, rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len, w, hl2, done, l1
   if (it == 1) HOMG_LAUNCH((k_sweep_3d_l0_tb<T, ZERO, ACCUM, 1, LAT>), g, blk, s, TB3_ARGS);
@@ -2200,6 +2224,8 @@ static hipError_t tb3_tz(int n, int it, int len, double omega, const void* eo, v
                          hipStream_t s) {
   const L1Src<T> v = l1_src<T>(l1);
 #define TB3_ARGS n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, compact, v, done, s
+  if (l1 && compact)  // a compact lattice taking x_0 from the next coarser level's state
+    return eprev ? tb3_t<T, false, false, true, true>(TB3_ARGS) : tb3_t<T, false, false, false, true>(TB3_ARGS);
   if (l1)  // level 0 taking its e from level 1's compact state
     return accum ? tb3_t<T, false, true, false, true>(TB3_ARGS) : tb3_t<T, false, false, false, true>(TB3_ARGS);
   if (accum)
@@ -2216,7 +2242,7 @@ hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, v
                         const L1State* l1) {
   if (len == 0) len = tb3_band(n, it);
   if (n < 3 || it < 1 || it > TB3_MAX_IT || len < 1 || (accum && (eprev || compact)) ||
-      (l1 && (zero || compact || eprev)) || !l1_ok(l1, 3, n))
+      (l1 && (zero || (eprev && !compact))) || !l1_ok(l1, 3, n))
     return hipErrorInvalidValue;
   switch (prec) {
     case PREC_F64: return tb3_tz<double>(n, it, len, omega, eo, en, eprev, el, rm, rl, u, ul, zero, accum, compact, l1, done, s);
@@ -2374,34 +2400,38 @@ size_t coarse_tail_lds(int prec, int d, int nms, int nlev) {
 
 template <typename T>
 static hipError_t tail_t(int d, int nms, int nlev, const int* its, double omega, const void* rms,
-                         const Lay& rl, void* dst, const Lay& tl, const int* done, hipStream_t s) {
+                         const Lay& rl, void* dst, const Lay& tl, const int* done, hipStream_t s,
+                         void* sprev, void* scur, const Lay& sl) {
   using C = typename Tr<T>::C;
   TailIts ti{};
   for (int k = 0; k < nlev; ++k) ti.it[k] = its[k];
   const size_t lds = coarse_tail_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, nms, nlev);
   const T* r = static_cast<const T*>(rms) + rl.off;
-  T* o = static_cast<T*>(dst) + tl.off;
+  T* o = dst ? static_cast<T*>(dst) + tl.off : nullptr;
+  T* sp = scur ? static_cast<T*>(sprev) + sl.off : nullptr;
+  T* sc = scur ? static_cast<T*>(scur) + sl.off : nullptr;
   if (d == 2) {
     hipError_t a = allow_lds(k_coarse_tail<T, 2>, lds);
     if (a != hipSuccess) return a;
     HOMG_LAUNCH_SMEM((k_coarse_tail<T, 2>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
-                     tl.pitch, tl.plane, nms, nlev, ti, C(omega / 4.0), done);
+                     tl.pitch, tl.plane, nms, nlev, ti, C(omega / 4.0), done, sp, sc, sl.pitch, sl.plane);
   }
   hipError_t a = allow_lds(k_coarse_tail<T, 3>, lds);
   if (a != hipSuccess) return a;
   HOMG_LAUNCH_SMEM((k_coarse_tail<T, 3>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
-                   tl.pitch, tl.plane, nms, nlev, ti, C(omega / 6.0), done);
+                   tl.pitch, tl.plane, nms, nlev, ti, C(omega / 6.0), done, sp, sc, sl.pitch, sl.plane);
 }
 
 hipError_t launch_coarse_tail(int prec, int d, int nms, int nlev, const int* its, double omega,
                               const void* rms, const Lay& rl, void* dst, const Lay& tl,
-                              const int* done, hipStream_t s) {
-  if (nms < 5 || nlev < 1 || nlev > BATCH_MAX_LEVELS || ((nms - 1) >> (nlev - 1)) + 1 < 3)
+                              const int* done, hipStream_t s, void* sprev, void* scur, const Lay& sl) {
+  if (nms < 5 || nlev < 1 || nlev > BATCH_MAX_LEVELS || ((nms - 1) >> (nlev - 1)) + 1 < 3 ||
+      (!scur && !dst) || (scur && (!sprev || sl.side != nms)))
     return hipErrorInvalidValue;
   switch (prec) {
-    case PREC_F64: return tail_t<double>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s);
-    case PREC_F32: return tail_t<float>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s);
-    default: return tail_t<bf16>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s);
+    case PREC_F64: return tail_t<double>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
+    case PREC_F32: return tail_t<float>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
+    default: return tail_t<bf16>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
   }
 }
 

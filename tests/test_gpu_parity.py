@@ -296,6 +296,8 @@ def test_chained_path_with_revisits_and_coarse_end(B, torch_cuda, prec):
     (1025, None),
     (9, [(1, 1), (0, 3)]),
     (257, [(1, 3), (0, 4), (2, 2), (1, 2), (0, 6)]),
+    (1025, [(2, 1), (1, 3), (0, 2)]),
+    (1025, [(3, 2), (2, 1), (1, 1), (0, 1), (2, 5), (1, 6), (0, 4)]),
 ])
 def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, prec):
     """2D level 0 with several iterations per pass (level-blocked and chained
@@ -303,7 +305,9 @@ def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sche
     the middle (stored) and last (added into u), 1 to 9 iterations, grids
     narrower than one wave and row counts that are not multiples of the
     band; after level 1 (the chained path's first pass interpolates level
-    1's lattice itself), also level 1 from e = 0 with a single iteration."""
+    1's lattice itself), also level 1 from e = 0 with a single iteration,
+    and chains of adjacent compact lattices (each first pass interpolating
+    the coarser lattice, from e = 0, with one and several iterations)."""
     torch = torch_cuda
     say("level-0 pass n=%d sched=%s prec=%s" % (n, sched, prec))
     f = dev(torch, W.uniform(2, n, seed=19))
@@ -326,6 +330,8 @@ def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sche
     (129, None),
     (17, [(1, 1), (0, 1)]),
     (9, [(1, 3), (0, 3), (1, 2), (0, 2)]),
+    (129, [(2, 1), (1, 3), (0, 2)]),
+    (129, [(3, 2), (2, 1), (1, 1), (0, 3), (2, 3), (1, 2), (0, 1)]),
 ])
 def test_3d_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, prec):
     """3D level 0 and the compact lattices with two iterations per pass
@@ -333,7 +339,7 @@ def test_3d_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, p
     level 0 first, in the middle and last, odd and even iteration counts,
     grids smaller than one tile, and level 0 right after level 1 (one and
     two iterations in the pass that interpolates level 1's lattice, level
-    1 from e = 0)."""
+    1 from e = 0), and chains of adjacent compact lattices."""
     torch = torch_cuda
     say("3D pass n=%d sched=%s prec=%s" % (n, sched, prec))
     f = dev(torch, W.uniform(3, n, seed=20))
