@@ -461,13 +461,16 @@ __global__ __launch_bounds__(256) void k_init_state(DevState* st, double tol, in
   }
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int count,
-                                                  DevState* st, double* __restrict__ history,
-                                                  int cycle, int mode) {
+// One workgroup of 1024 lanes (a per-wave partial count of ~8k, as the
+// fused 2D residual gives at 4097^2, is then 8 loads per lane).
+constexpr int FIN_NT = 1024;
+__global__ __launch_bounds__(FIN_NT) void k_finalize(const double* __restrict__ partials, int count,
+                                                     DevState* st, double* __restrict__ history,
+                                                     int cycle, int mode) {
   if (mode == 1 && st->done) return;
   double s = 0.0;
-  for (int i = threadIdx.x; i < count; i += 256) s += partials[i];
-  s = block_sum<256>(s);
+  for (int i = threadIdx.x; i < count; i += FIN_NT) s += partials[i];
+  s = block_sum<FIN_NT>(s);
   if (threadIdx.x == 0) {
     if (mode == 0) {
       const double fn = sqrt(s);
@@ -1970,7 +1973,7 @@ hipError_t launch_residual_restrict_2d(int prec, int n, const double* u, const L
 
 hipError_t launch_finalize(const double* partials, int count, DevState* st, double* history,
                            int cycle, int mode, hipStream_t s) {
-  HOMG_LAUNCH(k_finalize, dim3(1), dim3(256), s, partials, count, st, history, cycle, mode);
+  HOMG_LAUNCH(k_finalize, dim3(1), dim3(FIN_NT), s, partials, count, st, history, cycle, mode);
 }
 
 hipError_t launch_init_state(DevState* st, double tol, int stop_on_tol, hipStream_t s) {

@@ -3,7 +3,8 @@
 Every problem of a batch must end exactly where the one-problem solver
 (one launch per iteration, same precision) ends: the batched kernel runs the
 same tile code with the same tiles, so u agrees bit for bit and the cycle
-counts match.  The FP64 batch is also checked against the CPU oracle.
+counts match (the residual norms to the rounding of their summation order).
+The FP64 batch is also checked against the CPU oracle.
 """
 import sys
 
@@ -54,7 +55,10 @@ def test_batch_matches_single_problem_solves(B, torch_cuda, prec):
         r1 = one.solve(fs[i], u1, tol=1e-10)
         assert r1["cycles"] == res["cycles"][i], (s, r1["cycles"], res["cycles"][i])
         assert torch.equal(u1, us[i]), s
-        assert res["relres"][i] == pytest.approx(r1["final_relres"], rel=0, abs=0)
+        # the single-problem solver sums the residual norm over other
+        # partials (its residual is fused with the first restriction), so
+        # the norms agree to the rounding of the summation order
+        assert res["relres"][i] == pytest.approx(r1["final_relres"], rel=1e-14, abs=0)
     if prec == "fp64":
         for i in (0, 2, 5):
             s = sides[i]
