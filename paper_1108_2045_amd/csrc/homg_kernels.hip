@@ -106,6 +106,30 @@ __device__ __forceinline__ C relax_var(C c, C xm, C xp, C ym, C yp, double ac, d
 template <typename C>
 __device__ __forceinline__ C lerp(C a, C b, C t) { return fmac(t, b - a, a); }
 
+// ------------------------------------------------------------ lane exchange
+// The value of the previous / next lane of the wave (lane i gets lane i - 1
+// / i + 1) by a DPP wave shift (a VALU move; no LDS round trip as with
+// __shfl_up / __shfl_down).  The lane at the wave's end reads 0; every
+// caller discards what those lanes compute.
+__device__ __forceinline__ int dpp_prev(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);  // wave_shr:1
+}
+__device__ __forceinline__ int dpp_next(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);  // wave_shl:1
+}
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_prev(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_next(__float_as_int(v))); }
+__device__ __forceinline__ double lane_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(dpp_prev(int(b))), hi = unsigned(dpp_prev(int(b >> 32)));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(dpp_next(int(b))), hi = unsigned(dpp_next(int(b >> 32)));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // ------------------------------------------------------------ reductions
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -883,7 +907,7 @@ __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict
     for (int t = 1; t <= IT; ++t) {
       const int y = y0 - t;
       const C c = win[t - 1][1];
-      const C xm = __shfl_up(c, 1), xp = __shfl_down(c, 1);
+      const C xm = lane_prev(c), xp = lane_next(c);
       const bool in = xin && y >= 1 && y <= n - 2;
       C v = relax_const<C>(c, (xm + xp) + (win[t - 1][0] + win[t - 1][2]), rw[t], w, hl2, C(4));
       if (t < IT) {
