@@ -1147,10 +1147,11 @@ __global__ __launch_bounds__(256) void k_sweep_3d_l0(
 // a 64 x 16 tile of (x, y) columns (four consecutive rows per lane) and
 // walks z; iteration t is computed t planes behind the plane just loaded.
 // A lane keeps, per iteration level, its four rows of the last three planes
-// (the z neighbours, and the y neighbours of its inner rows); the current
-// centre plane of each level is also put in LDS, where the x neighbours and
-// the y neighbours across lanes are read (double-buffered: one barrier per
-// plane).  The tile's outer IT columns and rows only feed the inner ones,
+// (the z neighbours, and the y neighbours of its inner rows); the x
+// neighbours come from the neighbour lanes (DPP wave shifts: a wave is one
+// 64-column row group), and the lane's first and last rows of each level's
+// centre plane go to LDS, where the waves above and below read them as y
+// neighbours (double-buffered: one barrier per plane).  The tile's outer IT columns and rows only feed the inner ones,
 // so a block emits (64 - 2 IT) x (16 - 2 IT) columns and the band of planes
 // is entered IT planes early and left IT planes late.  Every intermediate
 // iterate is rounded as a store would round it, so the result equals IT
@@ -1198,7 +1199,6 @@ __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict
       win[t][0][k] = win[t][1][k] = win[t][2][k] = C(0);
       rr[t][k] = C(0);
     }
-  const int xm_i = max(lx - 1, 0), xp_i = min(lx + 1, BX3 - 1);
   const int ym_row = max(row0 - 1, 0), yp_row = min(row0 + TB3_R, TB3_TY - 1);
   L1Col3<T, TB3_R> lc;
   if (LAT) lc.init(l1, x, yb, n);
@@ -1222,9 +1222,12 @@ __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict
 #pragma unroll
       for (int t = IT - 1; t > 0; --t) rr[t][k] = rr[t - 1][k];
       rr[0][k] = rv;
-      P[0][b][row0 + k][lx] = win[0][1][k];
+      // only a lane's first and last rows are read by the waves next to it
+      if (k == 0 || k == TB3_R - 1) {
+        P[0][b][row0 + k][lx] = win[0][1][k];
 #pragma unroll
-      for (int t = 1; t < IT; ++t) P[t][b][row0 + k][lx] = win[t][2][k];
+        for (int t = 1; t < IT; ++t) P[t][b][row0 + k][lx] = win[t][2][k];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -1236,7 +1239,9 @@ __device__ __forceinline__ void tb3_body(const T* __restrict__ eo, T* __restrict
 #pragma unroll
       for (int k = 0; k < TB3_R; ++k) {
         const C c = win[t - 1][1][k];
-        const C xm = pl[row0 + k][xm_i], xp = pl[row0 + k][xp_i];
+        // x neighbours by DPP wave shifts (the wave is one row of the
+        // tile); the end lanes' values are never emitted
+        const C xm = lane_prev(c), xp = lane_next(c);
         const C ym = k == 0 ? pl[ym_row][lx] : win[t - 1][1][k - 1];
         const C yp = k == TB3_R - 1 ? pl[yp_row][lx] : win[t - 1][1][k + 1];
         v[k] = relax_const<C>(c, ((xm + xp) + (ym + yp)) + (win[t - 1][0][k] + win[t - 1][2][k]),
