@@ -83,12 +83,15 @@ typedef struct homg_options {
                               written only before level 0 or the last level; for a Laplacian
                               with damped Jacobi, a level followed by the next finer one hands
                               over nothing: the finer level's first pass interpolates the
-                              coarser level's lattice values itself (level 0 included);
+                              coarser level's lattice values itself (always before level 0; in
+                              2D between any two lattices large enough for several workgroups;
+                              in 3D after the one-workgroup coarse tail);
                               1: level-blocked -- as 2, but the whole grid is written after every
                               level;
                               0: one whole-grid launch per iteration.
-                              With 1 or 2, several level-0 iterations (2D Laplacian) run in one
-                              pass.  All three give the same results bit for bit. */
+                              With 1 or 2, several iterations of a Laplacian (2D: four, 3D: two)
+                              run in one pass at level 0 and on large lattices.  All three give
+                              the same results bit for bit. */
     int reserved[7];       /* must be 0 */
 } homg_options;
 

@@ -686,7 +686,10 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
 // interpolant of x_{it-1} over its level-1 cell, boundary nodes 0; the
 // formula, its order of operations and the rounding to T are those of the
 // whole-grid write (k_level_write_2d/3d with m = 1), so both give the same
-// bits.
+// bits.  The compact lattice of level m sits in that of level m + 1 the
+// same way (and the hand-over kernels and the coarse tail evaluate the same
+// formula), so the passes over a compact lattice use it too: "level 1" is
+// then level m + 1 and "level 0" level m.
 template <typename T>
 struct L1Src {
   const T* prev;    // x_{it-1}, unread when zero_old
