@@ -228,18 +228,19 @@ homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, v
                          void* xcur, int* cur, double* acc, const int* done, hipStream_t s);
 
 // Whether level mt's iterations (chained execution, Laplacian, damped
-// Jacobi) run as multi-iteration passes whose first pass can take its input
-// iterate from level mt + 1's compact state: level 0, or a compact lattice
-// too large for one workgroup.  In 3D a compact lattice does so only after
-// the coarse tail (whose own one-workgroup hand-over is slow): after a
-// separate level the hand-over kernel plus a plain pass measured as fast or
-// faster (MI355X, 257^3: 31 against 31 us at 129^3, 13 against 16 us at 65^3).
-bool lat_target(const homg_ctx* h, int mt, bool from_tail) {
+// Jacobi) run as multi-iteration passes whose first pass takes its input
+// iterate from level mt + 1's compact state: level 0, or in 2D a compact
+// lattice too large for one workgroup.  In 3D the hand-over kernel plus a
+// plain pass measured as fast or faster on the compact lattices (MI355X,
+// 257^3: 31 against 31 us at 129^3, 13 against 16 us at 65^3, 12 against
+// 16 us at 33^3: at these sizes the pass is latency-bound and the extra
+// loads sit on its critical path).
+bool lat_target(const homg_ctx* h, int mt) {
   if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || mt < 0) return false;
   const int nm = (h->n - 1) / (1 << mt) + 1;
   if (nm < 5 || mt + 1 >= h->levels) return false;
   if (mt == 0) return true;
-  if (h->d == 3 && !from_tail) return false;
+  if (h->d == 3) return false;
   return lattice_small_lds(h->prec, h->d, nm, false) > h->lds_limit && mt < int(h->xp3.size()) &&
          h->xp3[mt];
 }
@@ -312,7 +313,7 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
   // chained path: the previous level already left x_0 in X0
   const bool chained_in = !first && h->chain_ready == m;
   h->chain_ready = -1;
-  if (l1 && !lat_target(h, m, true))
+  if (l1 && !lat_target(h, m))
     return fail(h, HOMG_ERR_UNSUPPORTED, "the coarser level left no state for this level's iterations");
   if (lattice_small_lds(h->prec, h->d, nm, am != nullptr) <= h->lds_limit) {
     LAUNCH_K(h, s, K_LATTICE, m, 4 | (first ? 1 : 0),
@@ -376,7 +377,7 @@ homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, v
                          void* xcur, int* cur, double* acc, const int* done, hipStream_t s) {
   // chained path into the next finer level's multi-iteration passes: its
   // first pass interpolates this level's compact state itself
-  if (!last && next_m == m - 1 && lat_target(h, next_m, false)) {
+  if (!last && next_m == m - 1 && lat_target(h, next_m)) {
     h->lat.prev = (wmode & SW_ZERO_OLD) ? nullptr : xprev;
     h->lat.cur = xcur;
     h->lat.cl = h->rl[m];
@@ -475,6 +476,10 @@ int tail_levels(const homg_ctx* h, int* ms) {
   *ms = h->sched[2 * (cnt - 1)];
   for (int p = cnt; p < np; ++p)
     if (h->sched[2 * p] > *ms) return 0;  // a fused level is visited again
+  // a last coarse level in reduced precision runs whole-grid iterations
+  // (its iterate goes into u unrounded) and reads the whole grid, which the
+  // tail does not write
+  if (cnt + 1 == np && h->prec != PREC_F64) return 0;
   return cnt;
 }
 
@@ -524,16 +529,26 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
     for (int k = 0; k < ntail; ++k) its[k] = h->sched[2 * (ntail - 1 - k) + 1];
     const int nms = (h->n - 1) / (1 << ms) + 1;
     const bool next_last = size_t(ntail) + 1 == np;
-    if (lat_target(h, ms - 1, true) && !(next_last && h->prec != PREC_F64)) {
-      // the tail leaves level ms's state; level ms - 1's first pass interpolates it
+    const bool lat = lat_target(h, ms - 1) && !(next_last && h->prec != PREC_F64);
+    if (lat || h->d == 3) {
+      // the tail leaves level ms's state; level ms - 1's first pass
+      // interpolates it, or (3D) the multi-workgroup hand-over kernel does:
+      // the tail's own one-workgroup hand-over to 33^3 took 16 of its 37 us
       LAUNCH_K(h, s, K_TAIL, ms, 1,
                launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms], nullptr,
                                   Lay(), done, s, h->xc[2 * ms], h->xc[2 * ms + 1], h->rl[ms]));
-      h->lat.prev = h->xc[2 * ms];
-      h->lat.cur = h->xc[2 * ms + 1];
-      h->lat.cl = h->rl[ms];
-      h->lat.zero_old = false;
-      h->lat_level = ms - 1;
+      if (lat) {
+        h->lat.prev = h->xc[2 * ms];
+        h->lat.cur = h->xc[2 * ms + 1];
+        h->lat.cl = h->rl[ms];
+        h->lat.zero_old = false;
+        h->lat_level = ms - 1;
+      } else {
+        LAUNCH_K(h, s, K_TRANSFER, ms - 1, 0,
+                 launch_level_transfer(h->prec, h->d, ms, h->xc[2 * ms], h->xc[2 * ms + 1], h->rl[ms], ms - 1,
+                                       h->xc[2 * (ms - 1)], h->rl[ms - 1], false, done, s));
+        h->chain_ready = ms - 1;
+      }
     } else {
       LAUNCH_K(h, s, K_TAIL, ms, 0,
                launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms],

@@ -298,6 +298,7 @@ def test_chained_path_with_revisits_and_coarse_end(B, torch_cuda, prec):
     (257, [(1, 3), (0, 4), (2, 2), (1, 2), (0, 6)]),
     (1025, [(2, 1), (1, 3), (0, 2)]),
     (1025, [(3, 2), (2, 1), (1, 1), (0, 1), (2, 5), (1, 6), (0, 4)]),
+    (1025, [(3, 2), (2, 3), (1, 2), (0, 1), (2, 1)]),
 ])
 def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, prec):
     """2D level 0 with several iterations per pass (level-blocked and chained
@@ -332,6 +333,7 @@ def test_level0_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sche
     (9, [(1, 3), (0, 3), (1, 2), (0, 2)]),
     (129, [(2, 1), (1, 3), (0, 2)]),
     (129, [(3, 2), (2, 1), (1, 1), (0, 3), (2, 3), (1, 2), (0, 1)]),
+    (65, [(4, 2), (3, 2), (2, 2), (1, 1)]),
 ])
 def test_3d_multi_iteration_pass_is_bitwise_identical(B, torch_cuda, n, sched, prec):
     """3D level 0 and the compact lattices with two iterations per pass
