@@ -960,6 +960,7 @@ homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* 
   LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
   int cur = 0;
   h->chain_ready = -1;
+  h->lat_level = -1;
   if (homg_status e = run_level(h, level, iters, false, false, -1, &cur, nullptr, h->zero_flag, s)) return e;
   LAUNCH(h, launch_unpack(h->prec, h->d, h->e[cur], h->el, e_new, h->dl, s));
   // the solver relies on zero boundaries in both e buffers
