@@ -1665,8 +1665,10 @@ __global__ __launch_bounds__(256) void k_level_transfer_3d(
     T* __restrict__ dst, int64_t dp, int64_t dpl, int nt, int mt, const int* __restrict__ done) {
   using C = typename Tr<T>::C;
   if (*done) return;
-  const int I = 1 + blockIdx.x * 256 + threadIdx.x, J = 1 + blockIdx.y, K = 1 + blockIdx.z;
-  if (I > nt - 2) return;
+  // blocks of 64 x 4 lanes: a row of a small lattice does not leave most of
+  // a 256-lane block idle
+  const int I = 1 + blockIdx.x * BX3 + threadIdx.x, J = 1 + blockIdx.y * BY3 + threadIdx.y, K = 1 + blockIdx.z;
+  if (I > nt - 2 || J > nt - 2) return;
   const int x = I << mt, y = J << mt, z = K << mt;
   const int l = 1 << m, mask = l - 1;
   const C inv_l = C(1) / C(l);
@@ -2492,15 +2494,16 @@ static hipError_t transfer_t(int d, int m, const void* xprev, const void* xcur, 
   const T* xc = static_cast<const T*>(xcur) + cl.off;
   T* o = static_cast<T*>(dst) + tl.off;
   const int nt = tl.side;
-  const dim3 g((nt - 2 + 255) / 256, nt - 2, d == 3 ? nt - 2 : 1);
   if (d == 2) {
+    const dim3 g((nt - 2 + 255) / 256, nt - 2, 1);
     if (zero) HOMG_LAUNCH((k_level_transfer_2d<T, true>), g, dim3(256), s, xp, xc, cl.pitch, m, o, tl.pitch, nt, mt, done);
     HOMG_LAUNCH((k_level_transfer_2d<T, false>), g, dim3(256), s, xp, xc, cl.pitch, m, o, tl.pitch, nt, mt, done);
   }
+  const dim3 g((nt - 2 + BX3 - 1) / BX3, (nt - 2 + BY3 - 1) / BY3, nt - 2), blk(BX3, BY3);
   if (zero)
-    HOMG_LAUNCH((k_level_transfer_3d<T, true>), g, dim3(256), s, xp, xc, cl.pitch, cl.plane, m, o, tl.pitch,
+    HOMG_LAUNCH((k_level_transfer_3d<T, true>), g, blk, s, xp, xc, cl.pitch, cl.plane, m, o, tl.pitch,
                 tl.plane, nt, mt, done);
-  HOMG_LAUNCH((k_level_transfer_3d<T, false>), g, dim3(256), s, xp, xc, cl.pitch, cl.plane, m, o, tl.pitch,
+  HOMG_LAUNCH((k_level_transfer_3d<T, false>), g, blk, s, xp, xc, cl.pitch, cl.plane, m, o, tl.pitch,
               tl.plane, nt, mt, done);
 }
 
