@@ -1742,21 +1742,30 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     for (int j = 0; j < k; ++j) p += 3 * tail_count<D>(side(j));
     return p + which * tail_count<D>(side(k));
   };
-  for (int k = 0; k < nlev; ++k) {
+  // the coarser levels' arrays start at 0 (x_0 = 0 on the coarsest level,
+  // and every boundary node); on level ms, r is loaded (0 on the boundary)
+  // and the iterates' interiors are written before they are read (the
+  // hand-over from level ms + 1, the first iteration), so only their
+  // boundary nodes are cleared
+  for (int k = 1; k < nlev; ++k) {
     const int cnt = tail_count<D>(side(k));
     C* R = lvl(k, 0);
     C* P = lvl(k, 1);
     C* Q = lvl(k, 2);
     for (int i = threadIdx.x; i < cnt; i += SMALL_NT) R[i] = P[i] = Q[i] = C(0);
   }
-  __syncthreads();
   {
     C* R = lvl(0, 0);
+    C* P = lvl(0, 1);
+    C* Q = lvl(0, 2);
     const int cnt = tail_count<D>(nms);
+    const float inv = 1.0f / float(nms);
     for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
-      const int I = i % nms, J = (i / nms) % nms, K = D == 3 ? i / (nms * nms) : 0;
+      int I, J, K;
+      tail_split<D>(i, nms, inv, I, J, K);
       const bool inner = I > 0 && I < nms - 1 && J > 0 && J < nms - 1 && (D == 2 || (K > 0 && K < nms - 1));
       R[i] = inner ? ld(rms + int64_t(K) * rpl + int64_t(J) * rp + I) : C(0);
+      if (!inner) P[i] = Q[i] = C(0);
     }
   }
   __syncthreads();
