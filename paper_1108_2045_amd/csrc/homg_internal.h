@@ -84,9 +84,10 @@ hipError_t launch_sweep(int prec, int d, int n, int m, double omega, const void*
 // calls; reads e (unless zero) and r once, writes en or adds into u once.
 // A wave walks a band of `len` rows (0: tb_band's choice).  Short bands
 // re-read more halo rows (from L2) but put more waves in flight: tb_band
-// returns the longest band (64, 32 or 16 rows) that still gives
-// TB_MIN_WAVES waves, else 8 (measured on MI355X, FP64: the pass beats the
-// single-iteration kernels from 129^2 up, 1.4-2.8x).
+// returns the longest band (64, 32, 16 or 8 rows) that still gives
+// TB_MIN_WAVES waves, else 4 (measured on MI355X, FP64: the pass beats the
+// single-iteration kernels from 129^2 up, 1.4-2.8x; on the small lattices
+// of a 4097^2 solve, 4-row bands took 10 -> 7.6 us per pass at 257^2).
 constexpr int TB_MAX_IT = 4;
 constexpr int TB_MIN_WAVES = 4096;
 __host__ __device__ inline int tb_waves(int n, int it, int len) {

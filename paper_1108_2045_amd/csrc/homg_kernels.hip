@@ -2221,9 +2221,9 @@ hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const vo
 }
 
 int tb_band(int n, int it) {
-  for (int len : {64, 32, 16})
+  for (int len : {64, 32, 16, 8})
     if (tb_waves(n, it, len) >= TB_MIN_WAVES) return len;
-  return 8;
+  return 4;
 }
 
 int tb3_blocks(int n, int it, int len) {
