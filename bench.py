@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 513^3 precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother training and timing")
+    ap.add_argument("--no-level-blocked", action="store_true",
+                    help="skip the level-blocked comparison solves (profiling runs of the default path)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -462,7 +464,7 @@ def main():
 
     # the same solves on the level-blocked path (bit-identical results; the
     # whole grid is written after every level instead of only before level 0)
-    for p in probs:
+    for p in ([] if args.no_level_blocked else probs):
         sc = P.Solver(p["d"], p["n"], max_i=args.max_i, temporal_block=1)
         times = []
         for _ in range(4):
