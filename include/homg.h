@@ -155,7 +155,8 @@ homg_status homg_solve_cycles(homg_handle h, const double *f, double *u, int cyc
 
 /*
  * Residual r = f - A u in FP64 (Sec. 2, the residual equation).  r may be
- * NULL; otherwise a dense FP64 array that receives r (0 on the boundary).
+ * NULL; otherwise a dense FP64 array whose interior entries receive r (its
+ * boundary entries are not written).
  * *relres_out (host) receives ||r||_2 / ||f||_2 over interior nodes.
  * Synchronises the stream.
  */
@@ -235,8 +236,11 @@ homg_status homg_get_profile(homg_handle h, homg_kernel_time *out, int cap, int 
  * step for all of them (the launches captured once in a HIP graph of 64
  * steps, replayed until every problem has retired); each retires when its
  * relative residual reaches tol.  Precision, omega, MaxI and max_cycles
- * come from opt (schedule and temporal_block are ignored: coarse levels one
- * whole-grid pass per iteration, level 0 in multi-iteration passes).
+ * come from opt (schedule and temporal_block are ignored: the MFMG schedule
+ * runs chained -- each coarse level iterates on its compact lattice and
+ * hands over only the next finer level's lattice values, the whole grid is
+ * written once, before level 0 -- and level 0 runs in multi-iteration
+ * passes).
  *
  * homg_batch_create: count >= 1 problems with sides[i] = 2^k + 1, 3 <= side
  *   <= 32769 and at most 16 levels; allocates one device arena for all of
@@ -250,10 +254,21 @@ homg_status homg_get_profile(homg_handle h, homg_kernel_time *out, int cap, int 
  *   HOMG_ERR_HIP on a runtime failure.  Synchronises the stream.
  * homg_batch_set_tile_rows: rows per tile (the tile shape of the
  *   fine-grid stages) for all problems of side `side`; 0 restores the
- *   default.  homg_batch_tune picks them by timing candidate shapes on the
- *   given inputs (u is overwritten; coordinate descent over the sides,
- *   largest first) and reads/appends the choice in the text file cache_path
- *   (lines "<arch/CUs/precision/MaxI key> <side> <rows>"; NULL: no cache).
+ *   default.
+ * homg_batch_set_pass_iters: iterations per level-0 pass (1..4; 0 restores
+ *   the default 4) for all problems of side `side`.  Every pass depth gives
+ *   the same iterates bit for bit; only the traffic and the number of steps
+ *   change.
+ * homg_batch_tune: picks both by timing candidates on the given inputs:
+ *   coordinate descent over the sides, largest first, tile rows in {4, ...,
+ *   128} and then pass iterations in {1, ..., 4}, each candidate timed as
+ *   the median of three solves.  Every timed solve starts from the caller's
+ *   u (a device copy is saved first and restored before each run and at the
+ *   end, so u is left as given); HOMG_ERR_INVALID_ARG if a run needs no
+ *   cycle at all (every initial guess already meets tol).  The choice is
+ *   read from / appended to the text file cache_path (lines "<arch/CUs/
+ *   precision/MaxI key> <side> <rows> <iterations>"; NULL: no cache); a
+ *   cache that covers every side skips the timing.
  */
 typedef struct homg_batch_ctx *homg_batch;
 
@@ -262,6 +277,7 @@ homg_status homg_batch_create(homg_batch *out, int count, const int64_t *sides,
 homg_status homg_batch_solve(homg_batch b, const double *const *f, double *const *u, double tol,
                              void *stream, double *relres_out, int *cycles_out, int *status_out);
 homg_status homg_batch_set_tile_rows(homg_batch b, int64_t side, int rows);
+homg_status homg_batch_set_pass_iters(homg_batch b, int64_t side, int iters);
 homg_status homg_batch_tune(homg_batch b, const double *const *f, double *const *u, double tol,
                             void *stream, const char *cache_path);
 homg_status homg_batch_destroy(homg_batch b);

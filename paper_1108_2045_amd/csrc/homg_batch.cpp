@@ -32,6 +32,8 @@ struct homg_batch_ctx {
   std::vector<int> sides, levels;
   std::vector<int> sweep_levels;  // concatenated per-problem iteration levels
   std::map<int, int> tile_rows;   // side -> rows per tile (absent: default)
+  std::map<int, int> pass_iters;  // side -> iterations per level-0 pass (absent: TB_MAX_IT)
+  size_t sched_cap = 0;           // capacity of d_sweep_levels (ints)
   BatchProblem* h_probs = nullptr;
   BatchProblem* d_probs = nullptr;
   BatchRun* h_run = nullptr;
@@ -97,8 +99,9 @@ void free_batch(homg_batch_ctx* b) {
 // MaxI) iterations each, chained as in the single-problem solver): each
 // coarse level's iterations on its compact lattice and its hand-over to
 // the next finer level's lattice (to the whole grid before level 0), then
-// level 0 in passes of up to TB_MAX_IT iterations, the last adding into u.
-std::vector<int> stage_codes(int L, int max_i) {
+// level 0 in passes of up to `depth` (<= TB_MAX_IT) iterations, the last
+// adding into u.
+std::vector<int> stage_codes(int L, int max_i, int depth) {
   std::vector<int> codes;
   const int M = L - 1;
   auto iters = [&](int m) { return std::min(1 << std::min(M - m + 1, 30), max_i); };
@@ -109,8 +112,8 @@ std::vector<int> stage_codes(int L, int max_i) {
   }
   const int it0 = iters(0);
   int q = 0;
-  for (int t0 = 0; t0 < it0; t0 += TB_MAX_IT, ++q) {
-    const int g = std::min(TB_MAX_IT, it0 - t0);
+  for (int t0 = 0; t0 < it0; t0 += depth, ++q) {
+    const int g = std::min(depth, it0 - t0);
     codes.push_back(bst_code(BST_L0, 0, g, q, M == 0 && t0 == 0, t0 + g == it0));
   }
   return codes;
@@ -122,8 +125,30 @@ int rows_for(const homg_batch_ctx* b, int side) {
   return default_walk_len(2, side);
 }
 
+int depth_for(const homg_batch_ctx* b, int side) {
+  auto it = b->pass_iters.find(side);
+  return (it != b->pass_iters.end() && it->second > 0) ? std::min(it->second, TB_MAX_IT) : TB_MAX_IT;
+}
+
+// Stage table of every problem for the current pass depths (host copy; the
+// upload happens in run_once), and the step bound that follows from it.
+void build_schedule(homg_batch_ctx* b) {
+  b->sweep_levels.clear();
+  int max_cycle_len = 0;
+  for (int i = 0; i < b->count; ++i) {
+    BatchProblem& q = b->h_probs[i];
+    const std::vector<int> codes = stage_codes(b->levels[i], b->max_i, depth_for(b, b->sides[i]));
+    q.sched_off = int(b->sweep_levels.size());
+    q.sweeps = int(codes.size());
+    b->sweep_levels.insert(b->sweep_levels.end(), codes.begin(), codes.end());
+    max_cycle_len = std::max(max_cycle_len, q.top + q.sweeps + 2);
+  }
+  b->max_steps = 4 + (b->max_cycles + 1) * max_cycle_len;
+}
+
 void apply_tiles(homg_batch_ctx* b) {
   for (int i = 0; i < b->count; ++i) b->h_probs[i].len[0] = rows_for(b, b->sides[i]);
+  build_schedule(b);
 }
 
 homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u, double tol,
@@ -134,6 +159,10 @@ homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u
     b->h_probs[i].u = u[i];
   }
   *b->h_run = BatchRun{tol, b->omega, b->count, b->max_cycles, b->max_steps, 0};
+  if (b->sweep_levels.size() > b->sched_cap)
+    return bfail(b, HOMG_ERR_INVALID_ARG, "stage table exceeds its allocation");
+  BHIP(b, hipMemcpyAsync(b->d_sweep_levels, b->sweep_levels.data(), sizeof(int) * b->sweep_levels.size(),
+                         hipMemcpyHostToDevice, s));
   BHIP(b, hipMemcpyAsync(b->d_probs, b->h_probs, sizeof(BatchProblem) * b->count,
                          hipMemcpyHostToDevice, s));
   BHIP(b, hipMemcpyAsync(b->d_run, b->h_run, sizeof(BatchRun), hipMemcpyHostToDevice, s));
@@ -205,9 +234,11 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     total += (bytes + 255) & ~size_t(255);
     return o2;
   };
-  struct Plan { size_t e[2], r[BATCH_MAX_LEVELS], x[BATCH_MAX_LEVELS][2], part, hist; Lay el, rl[BATCH_MAX_LEVELS]; };
+  struct Plan {
+    size_t e[2], r[BATCH_MAX_LEVELS], x[BATCH_MAX_LEVELS][2], part, hist, r64 = 0, x64[2] = {0, 0};
+    Lay el, rl[BATCH_MAX_LEVELS], l64;
+  };
   std::vector<Plan> plans(count);
-  int max_cycle_len = 0;
   for (int i = 0; i < count; ++i) {
     const int n = int(sides[i]);
     const int L = side_k(n);
@@ -222,12 +253,19 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
       p.r[m] = take(size_t(p.rl[m].alloc) * eb);
       for (int c = 0; c < 2 && m >= 1; ++c) p.x[m][c] = take(size_t(p.rl[m].alloc) * eb);
     }
+    if (b->prec != PREC_F64 && L >= 2) {
+      // the FP64 coarsest level of reduced-precision cycles
+      p.l64 = padded_layout(2, (n - 1) / (1 << (L - 1)) + 1, 8);
+      p.r64 = take(sizeof(double) * size_t(p.l64.alloc));
+      p.x64[0] = take(sizeof(double) * size_t(p.l64.alloc));
+      p.x64[1] = take(sizeof(double) * size_t(p.l64.alloc));
+    }
     p.part = take(sizeof(double) * size_t(batch_tiles(n, 1)));
     p.hist = take(sizeof(double) * size_t(b->max_cycles + 1));
-    const int M = L - 1;
-    max_cycle_len = std::max(max_cycle_len, M + int(stage_codes(L, b->max_i).size()) + 2);
+    // the stage table is sized for one iteration per level-0 pass, the
+    // longest sequence any pass depth gives
+    b->sched_cap += stage_codes(L, b->max_i, 1).size();
   }
-  b->max_steps = 4 + (b->max_cycles + 1) * max_cycle_len;
   homg_status st = HOMG_OK;
   if (hipMalloc(&b->arena, total) != hipSuccess) {
     (void)hipGetLastError();
@@ -265,18 +303,21 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
       q.rp[m] = p.rl[m].pitch;
       q.len[m] = default_walk_len(2, (n - 1) / (1 << m) + 1);
     }
+    if (p.r64 || p.x64[0]) {
+      q.r64 = reinterpret_cast<double*>(base + p.r64) + p.l64.off;
+      q.x64[0] = reinterpret_cast<double*>(base + p.x64[0]) + p.l64.off;
+      q.x64[1] = reinterpret_cast<double*>(base + p.x64[1]) + p.l64.off;
+      q.p64 = p.l64.pitch;
+    }
     q.partials = reinterpret_cast<double*>(base + p.part);
     q.history = reinterpret_cast<double*>(base + p.hist);
     q.n = n;
     q.levels = L;
     q.top = L - 1;
-    q.sched_off = int(b->sweep_levels.size());
-    const std::vector<int> codes = stage_codes(L, b->max_i);
-    b->sweep_levels.insert(b->sweep_levels.end(), codes.begin(), codes.end());
-    q.sweeps = int(codes.size());
     q.id = i;
   }
-  if (hipMalloc(reinterpret_cast<void**>(&b->d_sweep_levels), sizeof(int) * b->sweep_levels.size()) != hipSuccess ||
+  build_schedule(b);
+  if (hipMalloc(reinterpret_cast<void**>(&b->d_sweep_levels), sizeof(int) * b->sched_cap) != hipSuccess ||
       hipMemcpy(b->d_sweep_levels, b->sweep_levels.data(), sizeof(int) * b->sweep_levels.size(),
                 hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
@@ -318,6 +359,14 @@ homg_status homg_batch_set_tile_rows(homg_batch b, int64_t side, int rows) {
   return HOMG_OK;
 }
 
+homg_status homg_batch_set_pass_iters(homg_batch b, int64_t side, int iters) {
+  if (!b) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null batch handle");
+  if (iters < 0 || iters > TB_MAX_IT) return bfail(b, HOMG_ERR_INVALID_ARG, "iters must be in [0, 4]");
+  if (iters == 0) b->pass_iters.erase(int(side));
+  else b->pass_iters[int(side)] = iters;
+  return HOMG_OK;
+}
+
 homg_status homg_batch_solve(homg_batch b, const double* const* f, double* const* u, double tol,
                              void* stream, double* relres_out, int* cycles_out, int* status_out) {
   if (!b) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null batch handle");
@@ -343,6 +392,10 @@ homg_status homg_batch_solve(homg_batch b, const double* const* f, double* const
 homg_status homg_batch_tune(homg_batch b, const double* const* f, double* const* u, double tol,
                             void* stream, const char* cache_path) {
   if (!b) return bfail(nullptr, HOMG_ERR_INVALID_ARG, "null batch handle");
+  if (!f || !u) return bfail(b, HOMG_ERR_INVALID_ARG, "null f or u array");
+  if (!(tol > 0.0)) return bfail(b, HOMG_ERR_INVALID_ARG, "tol must be > 0");
+  for (int i = 0; i < b->count; ++i)
+    if (!f[i] || !u[i]) return bfail(b, HOMG_ERR_INVALID_ARG, "null f or u pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<int> distinct = b->sides;
   std::sort(distinct.begin(), distinct.end());
@@ -351,38 +404,86 @@ homg_status homg_batch_tune(homg_batch b, const double* const* f, double* const*
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
   char key[128];
-  std::snprintf(key, sizeof key, "gfx950/cu%d/%s/maxi%d", cus, pname, b->max_i);
-  // cache: lines of the form   <key> <side> <rows>
+  std::snprintf(key, sizeof key, "gfx950/cu%d/%s/maxi%d/rows+iters", cus, pname, b->max_i);
+  // cache: lines of the form   <key> <side> <rows> <iterations per level-0 pass>
   if (cache_path) {
     if (FILE* fp = std::fopen(cache_path, "r")) {
-      char k2[128];
-      int side = 0, rows = 0, hits = 0;
-      while (std::fscanf(fp, "%127s %d %d", k2, &side, &rows) == 3)
-        if (std::strcmp(k2, key) == 0 && std::find(distinct.begin(), distinct.end(), side) != distinct.end()) {
+      char line[256], k2[128];
+      int side = 0, rows = 0, its = 0, hits = 0;
+      while (std::fgets(line, sizeof line, fp))
+        if (std::sscanf(line, "%127s %d %d %d", k2, &side, &rows, &its) == 4 && std::strcmp(k2, key) == 0 &&
+            std::find(distinct.begin(), distinct.end(), side) != distinct.end() && rows > 0 && its > 0 &&
+            its <= TB_MAX_IT) {
           b->tile_rows[side] = rows;
+          b->pass_iters[side] = its;
           ++hits;
         }
       std::fclose(fp);
-      if (hits == int(distinct.size())) return HOMG_OK;
+      if (hits >= int(distinct.size())) return HOMG_OK;
     }
   }
-  hipEvent_t e0, e1;
-  BHIP(b, hipEventCreate(&e0));
-  BHIP(b, hipEventCreate(&e1));
-  auto timed = [&](float* ms) -> homg_status {
-    apply_tiles(b);
-    BHIP(b, hipEventRecord(e0, s));
-    if (homg_status e = run_once(b, f, u, tol, s)) return e;
-    BHIP(b, hipEventRecord(e1, s));
-    BHIP(b, hipEventSynchronize(e1));
-    BHIP(b, hipEventElapsedTime(ms, e0, e1));
-    return HOMG_OK;
+  // Every candidate starts from the caller's initial guesses: they are saved
+  // here and restored (outside the timed region) before each run, and
+  // restored once more at the end, so u is left as given.
+  std::vector<size_t> uoff(b->count + 1, 0);
+  for (int i = 0; i < b->count; ++i) uoff[i + 1] = uoff[i] + size_t(b->sides[i]) * b->sides[i];
+  double* saved = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&saved), sizeof(double) * uoff[b->count]) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, HOMG_ERR_OOM, "tuner copy of the initial guesses could not be allocated");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  homg_status st = HOMG_OK;
+  auto hip_ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == HOMG_OK) st = bfail(b, HOMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return st == HOMG_OK;
   };
-  float best = 0.f;
-  if (homg_status e = timed(&best)) return e;  // warm-up
-  if (homg_status e = timed(&best)) return e;
-  // coordinate descent over the sides, largest first
-  for (auto it = distinct.rbegin(); it != distinct.rend(); ++it) {
+  auto copy_u = [&](bool save) {
+    for (int i = 0; i < b->count && st == HOMG_OK; ++i) {
+      const size_t bytes = sizeof(double) * (uoff[i + 1] - uoff[i]);
+      hip_ok(save ? hipMemcpyAsync(saved + uoff[i], u[i], bytes, hipMemcpyDeviceToDevice, s)
+                  : hipMemcpyAsync(u[i], saved + uoff[i], bytes, hipMemcpyDeviceToDevice, s),
+             "hipMemcpyAsync");
+    }
+  };
+  // one run of the current tiles: restore u, time the solve, check that it
+  // did work (a run whose problems all meet tol at cycle 0 times nothing)
+  auto once = [&](float* ms) {
+    copy_u(false);
+    apply_tiles(b);
+    if (!hip_ok(hipEventRecord(e0, s), "hipEventRecord")) return false;
+    if (homg_status e = run_once(b, f, u, tol, s)) {
+      st = e;
+      return false;
+    }
+    if (!hip_ok(hipEventRecord(e1, s), "hipEventRecord") || !hip_ok(hipEventSynchronize(e1), "hipEventSynchronize") ||
+        !hip_ok(hipEventElapsedTime(ms, e0, e1), "hipEventElapsedTime"))
+      return false;
+    int most = 0;
+    for (int i = 0; i < b->count; ++i) most = std::max(most, b->h_state[i].cycles);
+    if (most < 1) {
+      st = bfail(b, HOMG_ERR_INVALID_ARG, "the initial guesses already meet tol: no cycle to time");
+      return false;
+    }
+    return true;
+  };
+  // a candidate's time: the median of three runs
+  auto timed = [&](float* ms) {
+    float t[3];
+    for (int r = 0; r < 3; ++r)
+      if (!once(&t[r])) return false;
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return true;
+  };
+  hip_ok(hipEventCreate(&e0), "hipEventCreate");
+  hip_ok(hipEventCreate(&e1), "hipEventCreate");
+  copy_u(true);
+  float best = 0.f, warm = 0.f;
+  bool ok = st == HOMG_OK && once(&warm) && timed(&best);
+  // coordinate descent over the sides, largest first: tile rows, then the
+  // iterations per level-0 pass
+  for (auto it = distinct.rbegin(); ok && it != distinct.rend(); ++it) {
     const int side = *it;
     const int keep = rows_for(b, side);
     int best_rows = keep;
@@ -390,19 +491,36 @@ homg_status homg_batch_tune(homg_batch b, const double* const* f, double* const*
       if (rows == keep || rows > side - 2) continue;
       b->tile_rows[side] = rows;
       float ms = 0.f;
-      if (homg_status e = timed(&ms)) return e;
+      if (!(ok = timed(&ms))) break;
       if (ms < best) {
         best = ms;
         best_rows = rows;
       }
     }
     b->tile_rows[side] = best_rows;
+    const int keep_it = depth_for(b, side);
+    int best_it = keep_it;
+    for (int its = 1; ok && its <= TB_MAX_IT; ++its) {
+      if (its == keep_it) continue;
+      b->pass_iters[side] = its;
+      float ms = 0.f;
+      if (!(ok = timed(&ms))) break;
+      if (ms < best) {
+        best = ms;
+        best_it = its;
+      }
+    }
+    b->pass_iters[side] = best_it;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  copy_u(false);
+  hip_ok(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(saved);
+  if (st != HOMG_OK) return st;
   if (cache_path) {
     if (FILE* fp = std::fopen(cache_path, "a")) {
-      for (int side : distinct) std::fprintf(fp, "%s %d %d\n", key, side, rows_for(b, side));
+      for (int side : distinct) std::fprintf(fp, "%s %d %d %d\n", key, side, rows_for(b, side), depth_for(b, side));
       std::fclose(fp);
     }
   }

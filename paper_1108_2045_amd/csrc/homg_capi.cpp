@@ -99,6 +99,11 @@ struct homg_ctx {
   double fallback_ratio = 1.0; // per-cycle contraction at which a solve falls back to Jacobi
   uint16_t* wbf = nullptr;     // the 576 weights in BF16
   float* w32 = nullptr;        // their FP32 values (what the kernels read)
+  // FP32/BF16 cycles: the coarsest level (top_level) in FP64 -- its
+  // right-hand side and iterate pair, compact, layout l64
+  double* r64 = nullptr;
+  double* x64[2] = {nullptr, nullptr};
+  Lay l64;
 };
 
 namespace {
@@ -204,6 +209,9 @@ void free_ctx(homg_ctx* h) {
   (void)hipFree(h->zero_flag);
   (void)hipFree(h->wbf);
   (void)hipFree(h->w32);
+  (void)hipFree(h->r64);
+  (void)hipFree(h->x64[0]);
+  (void)hipFree(h->x64[1]);
   if (h->h_st) (void)hipHostFree(h->h_st);
   if (h->h_hist) (void)hipHostFree(h->h_hist);
   for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
@@ -227,6 +235,16 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
 homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, void* xprev,
                          void* xcur, int* cur, double* acc, const int* done, hipStream_t s);
 
+// Whether the coarsest level of this cycle runs in FP64: FP32/BF16 storage
+// with damped Jacobi.  Its right-hand side is restricted in FP64 from the
+// stored values of the level below, its iterations run in FP64 on the
+// compact lattice, and only the final pair is rounded to the storage type
+// for the hand-over (the residual, the update of u and the norms are FP64
+// in every mode).
+bool top64(const homg_ctx* h) {
+  return h->prec != PREC_F64 && h->active_smoother == 0 && h->top_level >= 1 && h->r64;
+}
+
 // Whether level mt's iterations (chained execution, Laplacian, damped
 // Jacobi) run as multi-iteration passes whose first pass takes its input
 // iterate from level mt + 1's compact state: level 0, or in 2D a compact
@@ -237,6 +255,7 @@ homg_status finish_level(homg_ctx* h, int m, bool last, int next_m, int wmode, v
 // loads sit on its critical path).
 bool lat_target(const homg_ctx* h, int mt) {
   if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || mt < 0) return false;
+  if (top64(h) && mt == h->top_level) return false;  // starts from an FP64 x_0
   const int nm = (h->n - 1) / (1 << mt) + 1;
   if (nm < 5 || mt + 1 >= h->levels) return false;
   if (mt == 0) return true;
@@ -245,9 +264,59 @@ bool lat_target(const homg_ctx* h, int mt) {
          h->xp3[mt];
 }
 
+// `it` FP64 iterations of the coarsest level m (see top64) on its compact
+// lattice: x_0 is 0, the compact hand-over of the previous level, or the
+// whole grid sampled on the lattice, widened exactly; the final pair is
+// rounded to the storage type (into the level's compact pair) and handed
+// over as any blocked level's (same contract as run_level).
+homg_status run_top64(homg_ctx* h, int m, int it, bool first, bool last, int next_m, int* cur,
+                      double* acc, const int* done, hipStream_t s) {
+  const Lay none;
+  const double* am = h->has_coef ? h->a[m] : nullptr;
+  const Lay& alm = am ? h->al[m] : none;
+  const int l = 1 << m, nm = (h->n - 1) / l + 1;
+  const bool chained_in = !first && h->chain_ready == m;
+  h->chain_ready = -1;
+  h->lat_level = -1;
+  double* X[2] = {h->x64[0], h->x64[1]};
+  if (!first)
+    LAUNCH_K(h, s, K_GATHER, m, 1,
+             launch_widen(h->prec, h->d, chained_in ? h->xc[2 * m] : h->e[*cur], chained_in ? h->rl[m] : h->el,
+                          chained_in ? 1 : l, X[0], h->l64, done, s));
+  double* xprev;
+  double* xcur;
+  if (lattice_small_lds(PREC_F64, h->d, nm, am != nullptr) <= h->lds_limit) {
+    LAUNCH_K(h, s, K_LATTICE, m, 4 | (first ? 1 : 0) | 256,
+             launch_lattice_small(PREC_F64, h->d, nm, 1, it, h->omega, first, X[0], h->l64, h->r64, h->l64, am,
+                                  alm, X[0], X[1], h->l64, done, s));
+    xprev = X[0];
+    xcur = X[1];
+  } else {
+    int src = 0;
+    for (int t = 1; t <= it; ++t) {
+      const int mode = (first && t == 1) ? SW_ZERO_OLD : 0;
+      LAUNCH_K(h, s, K_LATTICE, m, mode | 256,
+               launch_sweep(PREC_F64, h->d, nm, 0, h->omega, X[src], X[1 - src], h->l64, h->r64, h->l64, am,
+                            alm, nullptr, none, mode, done, s, true));
+      src = 1 - src;
+    }
+    xcur = X[src];
+    xprev = X[1 - src];
+  }
+  int wmode = last ? SW_ACCUM : 0;
+  if (first && it == 1) wmode |= SW_ZERO_OLD;  // x_0 = 0
+  void* tp = h->xc[2 * m];
+  void* tc = h->xc[2 * m + 1];
+  if (!(wmode & SW_ZERO_OLD))
+    LAUNCH_K(h, s, K_GATHER, m, 2, launch_narrow(h->prec, h->d, xprev, h->l64, tp, h->rl[m], done, s));
+  LAUNCH_K(h, s, K_GATHER, m, 2, launch_narrow(h->prec, h->d, xcur, h->l64, tc, h->rl[m], done, s));
+  return finish_level(h, m, last, next_m, wmode, tp, tc, cur, acc, done, s);
+}
+
 homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int next_m, int* cur,
                       double* acc, const int* done, hipStream_t s) {
   if (h->active_smoother == 1) return run_level_learned(h, m, it, first, last, next_m, cur, acc, done, s);
+  if (top64(h) && m == h->top_level) return run_top64(h, m, it, first, last, next_m, cur, acc, done, s);
   const Lay none;
   const double* am = h->has_coef ? h->a[m] : nullptr;
   const Lay& alm = am ? h->al[m] : none;
@@ -463,7 +532,7 @@ int tail_levels(const homg_ctx* h, int* ms) {
     const int m = h->sched[2 * p];
     if (m != h->top_level - p || m < 2) break;
     const int nm = (h->n - 1) / (1 << m) + 1;
-    if (coarse_tail_lds(h->prec, h->d, nm, p + 1) > h->lds_limit) break;
+    if (coarse_tail_lds(h->prec, h->d, nm, p + 1, top64(h)) > h->lds_limit) break;
     if (h->sched[2 * (p + 1)] != m - 1) {  // the next entry must receive the hand-over
       cnt = p + 1;
       break;
@@ -486,7 +555,21 @@ int tail_levels(const homg_ctx* h, int* ms) {
 // Whether a solve's residual also restricts to level 1 in the same pass
 // (2D Laplacian whose schedule visits a coarse level).
 bool residual_restricts(const homg_ctx* h) {
-  return h->d == 2 && !h->has_coef && h->top_level >= 1 && h->n >= 5;
+  // (an FP64 coarsest level 1 takes its restriction from the separate kernel)
+  return h->d == 2 && !h->has_coef && h->top_level >= 1 && h->n >= 5 && !(top64(h) && h->top_level == 1);
+}
+
+// One restriction of the cycle's pyramid, m -> m + 1 (in FP64 onto an FP64
+// coarsest level).
+homg_status enqueue_restrict(homg_ctx* h, int m, const int* done, hipStream_t s) {
+  if (top64(h) && m + 1 == h->top_level) {
+    LAUNCH_K(h, s, K_RESTRICT, m, 1,
+             launch_restrict_to_f64(h->prec, h->d, h->r[m], h->rl[m], h->r64, h->l64, done, s));
+  } else {
+    LAUNCH_K(h, s, K_RESTRICT, m, 0,
+             launch_restrict(h->prec, h->d, h->r[m], h->rl[m], h->r[m + 1], h->rl[m + 1], done, s));
+  }
+  return HOMG_OK;
 }
 
 // r_0 = f - A u in the handle's precision with its norm partials (and, see
@@ -517,8 +600,7 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   // in a solve (f given) the residual that precedes every cycle already
   // restricted r_0 to level 1
   for (int m = f && residual_restricts(h) ? 1 : 0; m < (ntail ? ms : h->top_level); ++m)
-    LAUNCH_K(h, s, K_RESTRICT, m, 0,
-             launch_restrict(h->prec, h->d, h->r[m], h->rl[m], h->r[m + 1], h->rl[m + 1], done, s));
+    if (homg_status e = enqueue_restrict(h, m, done, s)) return e;
   int cur = 0;
   const size_t np = h->sched.size() / 2;
   h->chain_ready = -1;
@@ -536,7 +618,7 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
       // the tail's own one-workgroup hand-over to 33^3 took 16 of its 37 us
       LAUNCH_K(h, s, K_TAIL, ms, 1,
                launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms], nullptr,
-                                  Lay(), done, s, h->xc[2 * ms], h->xc[2 * ms + 1], h->rl[ms]));
+                                  Lay(), done, s, h->xc[2 * ms], h->xc[2 * ms + 1], h->rl[ms], top64(h)));
       if (lat) {
         h->lat.prev = h->xc[2 * ms];
         h->lat.cur = h->xc[2 * ms + 1];
@@ -552,7 +634,8 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
     } else {
       LAUNCH_K(h, s, K_TAIL, ms, 0,
                launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms],
-                                  h->xc[2 * (ms - 1)], h->rl[ms - 1], done, s));
+                                  h->xc[2 * (ms - 1)], h->rl[ms - 1], done, s, nullptr, nullptr, Lay(),
+                                  top64(h)));
       h->chain_ready = ms - 1;
     }
     p0 = size_t(ntail);
@@ -817,6 +900,18 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
       }
     }
   }
+  if (h->prec != PREC_F64 && h->top_level >= 1 && !stt) {
+    // FP64 coarsest level of reduced-precision cycles, and the compact pair
+    // its rounded state is handed over from (also without level blocking)
+    const int mt = h->top_level;
+    h->l64 = padded_layout(ndim, (h->n - 1) / (1 << mt) + 1, 8);
+    stt = dev_alloc(h, reinterpret_cast<void**>(&h->r64), sizeof(double) * size_t(h->l64.alloc));
+    for (int b = 0; b < 2 && !stt; ++b)
+      stt = dev_alloc(h, reinterpret_cast<void**>(&h->x64[b]), sizeof(double) * size_t(h->l64.alloc));
+    if (h->xc.empty()) h->xc.assign(2 * levels, nullptr);
+    for (int b = 0; b < 2 && !stt; ++b)
+      if (!h->xc[2 * mt + b]) stt = dev_alloc(h, &h->xc[2 * mt + b], size_t(h->rl[mt].alloc) * eb);
+  }
   h->npart = partials_bound(ndim, h->n);
   if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->partials), sizeof(double) * h->npart);
   if (!stt) stt = dev_alloc(h, reinterpret_cast<void**>(&h->st), sizeof(DevState));
@@ -835,8 +930,14 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
        hipMemset(h->zero_flag, 0, sizeof(int) * 64) == hipSuccess;
   for (int m = 0; m < levels && ok; ++m) ok = hipMemset(h->r[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
   // compact lattices: boundary nodes are read as 0 and never written
-  for (int m = 1; m < levels && ok && h->temporal; ++m)
-    for (int b = 0; b < 2 && ok; ++b) ok = hipMemset(h->xc[2 * m + b], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  for (size_t m = 1; 2 * m + 1 < h->xc.size() && ok; ++m)
+    for (int b = 0; b < 2 && ok; ++b)
+      if (h->xc[2 * m + b]) ok = hipMemset(h->xc[2 * m + b], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  if (h->r64) {
+    const size_t b64 = sizeof(double) * size_t(h->l64.alloc);
+    ok = ok && hipMemset(h->r64, 0, b64) == hipSuccess && hipMemset(h->x64[0], 0, b64) == hipSuccess &&
+         hipMemset(h->x64[1], 0, b64) == hipSuccess;
+  }
   for (size_t m = 0; m < h->xp3.size() && ok; ++m)
     if (h->xp3[m]) ok = hipMemset(h->xp3[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
   if (ok) {
@@ -939,7 +1040,13 @@ homg_status homg_step_restrict(homg_handle h, int level, const double* r_fine, d
   if (level < 0 || level >= h->levels - 1) return fail(h, HOMG_ERR_INVALID_ARG, "level out of range");
   DeviceGuard guard(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  h->active_smoother = h->smoother;
   LAUNCH(h, launch_pack(h->prec, h->d, r_fine, h->cdl[level], h->r[level], h->rl[level], s));
+  if (top64(h) && level + 1 == h->top_level) {
+    LAUNCH(h, launch_restrict_to_f64(h->prec, h->d, h->r[level], h->rl[level], h->r64, h->l64, h->zero_flag, s));
+    LAUNCH(h, launch_unpack(PREC_F64, h->d, h->r64, h->l64, r_coarse, h->cdl[level + 1], s));
+    return HOMG_OK;
+  }
   LAUNCH(h, launch_restrict(h->prec, h->d, h->r[level], h->rl[level], h->r[level + 1], h->rl[level + 1],
                             h->zero_flag, s));
   LAUNCH(h, launch_unpack(h->prec, h->d, h->r[level + 1], h->rl[level + 1], r_coarse, h->cdl[level + 1], s));
@@ -957,7 +1064,10 @@ homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   h->active_smoother = h->smoother;
   LAUNCH(h, launch_pack(h->prec, h->d, e_old, h->dl, h->e[0], h->el, s));
-  LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
+  if (top64(h) && level == h->top_level)
+    LAUNCH(h, launch_pack(PREC_F64, h->d, r_level, h->cdl[level], h->r64, h->l64, s));
+  else
+    LAUNCH(h, launch_pack(h->prec, h->d, r_level, h->cdl[level], h->r[level], h->rl[level], s));
   int cur = 0;
   h->chain_ready = -1;
   h->lat_level = -1;

@@ -168,11 +168,25 @@ hipError_t launch_lattice_small(int prec, int d, int nm, int l, int it, double o
 // x_it and x_{it-1} at every node into scur and sprev (layout sl, side nms)
 // for a next pass that interpolates them itself.  coarse_tail_lds: its LDS
 // bytes.
-size_t coarse_tail_lds(int prec, int d, int nms, int nlev);
+// top64 (FP32/BF16 cycles): the coarsest level of the tail in FP64 (its
+// restriction, iterates and arithmetic), rounded to the storage type only
+// for the hand-over.
+size_t coarse_tail_lds(int prec, int d, int nms, int nlev, bool top64 = false);
 hipError_t launch_coarse_tail(int prec, int d, int nms, int nlev, const int* its, double omega,
                               const void* rms, const Lay& rl, void* dst, const Lay& tl,
                               const int* done, hipStream_t s, void* sprev = nullptr,
-                              void* scur = nullptr, const Lay& sl = Lay());
+                              void* scur = nullptr, const Lay& sl = Lay(), bool top64 = false);
+// FP64 coarsest level of a reduced-precision cycle: the restriction to it
+// (input in the storage type of prec, widened exactly, FP64 sums and
+// output); the exact widening of the level-l lattice of an array in the
+// storage type into an FP64 compact array (every node of dl.side); and the
+// rounding of an FP64 compact array to the storage type (to FP32, then BF16).
+hipError_t launch_restrict_to_f64(int prec, int d, const void* rf, const Lay& fl, double* rc,
+                                  const Lay& cl, const int* done, hipStream_t s);
+hipError_t launch_widen(int prec, int d, const void* src, const Lay& sl, int l, double* dst,
+                        const Lay& dl, const int* done, hipStream_t s);
+hipError_t launch_narrow(int prec, int d, const double* src, const Lay& sl, void* dst, const Lay& dl,
+                         const int* done, hipStream_t s);
 // LDS bytes of the whole-grid pass of level m.
 size_t level_write_lds(int prec, int d, int n, int m);
 // Whole-grid pass of level m from compact x_{it-1} (xprev) and x_it (xcur):
@@ -186,7 +200,7 @@ hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, 
 hipError_t launch_level_transfer(int prec, int d, int m, const void* xprev, const void* xcur,
                                  const Lay& cl, int mt, void* dst, const Lay& tl, bool zero_old,
                                  const int* done, hipStream_t s);
-// ---- batched persistent solver (2D, constant coefficient)
+// ---- batched solver (2D, constant coefficient): graph-replayed step launches
 constexpr int BATCH_MAX_LEVELS = 16;
 // Iteration stages of a batched cycle, one int each in the schedule table:
 // kind (bits 0-3), level (4-8), iterations (9-12), index (13-20), zero
@@ -212,6 +226,12 @@ __host__ __device__ inline bool bst_accum(int c) { return (c >> 22) & 1; }
 struct BatchProblem {         // one problem, read by the step kernels
   const double* f;            // caller arrays, dense side n
   double* u;
+  // FP32/BF16 batches: the coarsest level (level top) in FP64 -- its
+  // right-hand side and iterate pair, compact, pitch p64; the iterations
+  // also store their rounding into x[top] for the hand-over
+  double* r64;
+  double* x64[2];
+  int64_t p64;
   void* e[2];                 // internal e ping-pong, pointer at node (0,0)
   void* r[BATCH_MAX_LEVELS];  // residual pyramid, pointer at node (0,0) of each level
   void* x[BATCH_MAX_LEVELS][2];  // compact iterate pair of each coarse level (layout of r)

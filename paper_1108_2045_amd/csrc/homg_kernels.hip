@@ -513,19 +513,23 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const double* __restrict__ 
 // Full weighting (Sec. 2: linearly weighted averages as nested partial
 // reductions): coarse node = (1/4)[1 2 1] per axis of the fine neighbours.
 
-template <typename T>
-__device__ __forceinline__ void tile_restrict_2d(const T* __restrict__ rf, int64_t fp,
-                                                     T* __restrict__ rc, int64_t cp, int nc,
+// TO: the coarse level's storage type, whose arithmetic the restriction
+// uses; TI (the fine level's) is TO except for the restriction to an FP64
+// coarsest level of a reduced-precision cycle, which widens the stored
+// values exactly and sums in FP64.
+template <typename TI, typename TO = TI>
+__device__ __forceinline__ void tile_restrict_2d(const TI* __restrict__ rf, int64_t fp,
+                                                     TO* __restrict__ rc, int64_t cp, int nc,
                                                      int len, int bx, int by) {
-  using C = typename Tr<T>::C;
+  using C = typename Tr<TO>::C;
   const int I = 1 + bx * BX2 + threadIdx.x;
   if (I > nc - 2) return;
   const int J0 = 1 + by * len;
   const int J1 = min(nc - 1, J0 + len);
   const int xi = 2 * I;
   auto rowsum = [&](int yf) {
-    const T* row = rf + int64_t(yf) * fp + xi;
-    return fmac(C(2), ld(row), ld(row - 1) + ld(row + 1));
+    const TI* row = rf + int64_t(yf) * fp + xi;
+    return fmac(C(2), C(ld(row)), C(ld(row - 1)) + C(ld(row + 1)));
   };
   C top = rowsum(2 * J0 - 1);
   for (int J = J0; J < J1; ++J) {
@@ -536,20 +540,20 @@ __device__ __forceinline__ void tile_restrict_2d(const T* __restrict__ rf, int64
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_2d(const T* __restrict__ rf, int64_t fp,
-                                                     T* __restrict__ rc, int64_t cp, int nc,
+template <typename TI, typename TO = TI>
+__global__ __launch_bounds__(256) void k_restrict_2d(const TI* __restrict__ rf, int64_t fp,
+                                                     TO* __restrict__ rc, int64_t cp, int nc,
                                                      int len, const int* __restrict__ done) {
   if (*done) return;
-  tile_restrict_2d<T>(rf, fp, rc, cp, nc, len, blockIdx.x, blockIdx.y);
+  tile_restrict_2d<TI, TO>(rf, fp, rc, cp, nc, len, blockIdx.x, blockIdx.y);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_3d(const T* __restrict__ rf, int64_t fp,
-                                                     int64_t fpl, T* __restrict__ rc, int64_t cp,
+template <typename TI, typename TO = TI>
+__global__ __launch_bounds__(256) void k_restrict_3d(const TI* __restrict__ rf, int64_t fp,
+                                                     int64_t fpl, TO* __restrict__ rc, int64_t cp,
                                                      int64_t cpl, int nc, int len,
                                                      const int* __restrict__ done) {
-  using C = typename Tr<T>::C;
+  using C = typename Tr<TO>::C;
   if (*done) return;
   const int I = 1 + blockIdx.x * BX3 + threadIdx.x;
   const int J = 1 + blockIdx.y * BY3 + threadIdx.y;
@@ -558,8 +562,8 @@ __global__ __launch_bounds__(256) void k_restrict_3d(const T* __restrict__ rf, i
   const int K1 = min(nc - 1, K0 + len);
   const int64_t col = int64_t(2 * J) * fp + 2 * I;
   auto planesum = [&](int zf) {
-    const T* p = rf + int64_t(zf) * fpl + col;
-    auto rs = [&](const T* q) { return fmac(C(2), ld(q), ld(q - 1) + ld(q + 1)); };
+    const TI* p = rf + int64_t(zf) * fpl + col;
+    auto rs = [&](const TI* q) { return fmac(C(2), C(ld(q)), C(ld(q - 1)) + C(ld(q + 1))); };
     return fmac(C(2), rs(p), rs(p - fp) + rs(p + fp));
   };
   C top = planesum(2 * K0 - 1);
@@ -1726,10 +1730,15 @@ __device__ __forceinline__ void tail_split(int i, int s, float inv_s, int& I, in
   }
 }
 
-template <typename T, int D>
+// TOP64 (reduced-precision cycles): the coarsest level of the tail runs in
+// FP64 -- its right-hand side restricted in FP64 from the stored values of
+// the level below, its iterates FP64 -- and only its final pair is rounded
+// to the storage type before the hand-over, as the separate launches do
+// (FP64 restriction, FP64 small-lattice iterations, rounding, transfer).
+template <typename T, int D, bool TOP64>
 __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     const T* __restrict__ rms, int64_t rp, int64_t rpl, T* __restrict__ dst, int64_t dp, int64_t dpl,
-    int nms, int nlev, TailIts its, typename Tr<T>::C w, const int* __restrict__ done,
+    int nms, int nlev, TailIts its, typename Tr<T>::C w, double w64, const int* __restrict__ done,
     T* __restrict__ sprev, T* __restrict__ scur, int64_t sp, int64_t spl) {
   using C = typename Tr<T>::C;
   if (*done) return;
@@ -1742,6 +1751,14 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     for (int j = 0; j < k; ++j) p += 3 * tail_count<D>(side(j));
     return p + which * tail_count<D>(side(k));
   };
+  // FP64 arrays of the coarsest level (TOP64): R, P, Q after all C arrays
+  const int ktop = nlev - 1, ctop = tail_count<D>(side(ktop));
+  double* top64 = nullptr;
+  if (TOP64) {
+    const size_t used = size_t(lvl(ktop, 3) - base) * sizeof(C);
+    top64 = reinterpret_cast<double*>(smem + ((used + 15) & ~size_t(15)));
+    for (int i = threadIdx.x; i < 3 * ctop; i += SMALL_NT) top64[i] = 0.0;
+  }
   // the coarser levels' arrays start at 0 (x_0 = 0 on the coarsest level,
   // and every boundary node); on level ms, r is loaded (0 on the boundary)
   // and the iterates' interiors are written before they are read (the
@@ -1780,6 +1797,24 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
       int I, J, K;
       tail_split<D>(i, ni, inv, I, J, K);
       ++I, ++J, K += D == 3;
+      const int o = (D == 3 ? K * nc * nc : 0) + J * nc + I;
+      if (TOP64 && k == ktop) {
+        // as k_restrict_*<T, double>: the stored values widened, FP64 sums
+        auto rs = [&](int q) { return fmac(2.0, double(F[q]), double(F[q - 1]) + double(F[q + 1])); };
+        double v;
+        if (D == 2) {
+          const int q = 2 * J * fp + 2 * I;
+          const double top = rs(q - fp), mid = rs(q), bot = rs(q + fp);
+          v = fmac(2.0, mid, top + bot) * 0.0625;
+        } else {
+          auto ps = [&](int q) { return fmac(2.0, rs(q), rs(q - fp) + rs(q + fp)); };
+          const int q = 2 * K * fpl + 2 * J * fp + 2 * I;
+          const double top = ps(q - fpl), mid = ps(q), bot = ps(q + fpl);
+          v = fmac(2.0, mid, top + bot) * 0.015625;
+        }
+        top64[o] = v;
+        continue;
+      }
       auto rs = [&](int q) { return fmac(C(2), F[q], F[q - 1] + F[q + 1]); };
       C v;
       if (D == 2) {
@@ -1792,7 +1827,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
         const C top = ps(q - fpl), mid = ps(q), bot = ps(q + fpl);
         v = fmac(C(2), mid, top + bot) * C(0.015625);
       }
-      R[(D == 3 ? K * nc * nc : 0) + J * nc + I] = rnd<T>(v);
+      R[o] = rnd<T>(v);
     }
     __syncthreads();
   }
@@ -1807,7 +1842,42 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     const int it = its.it[k];
     const int ni = nk - 2, icnt = tail_count<D>(ni);
     const float inv = 1.0f / float(ni);
-    for (int t = 1; t <= it; ++t) {
+    if (TOP64 && k == ktop) {
+      // FP64 iterations (as the FP64 small-lattice kernel), then the final
+      // pair rounded to the storage type into xa (x_{it-1}) and xb (x_it)
+      const double* R64 = top64;
+      double* ya = top64 + ctop;
+      double* yb = top64 + 2 * ctop;
+      const double hl2d = h * h;
+      for (int t = 1; t <= it; ++t) {
+        const double* src = (t & 1) ? ya : yb;
+        double* dstl = (t & 1) ? yb : ya;
+        for (int j = threadIdx.x; j < icnt; j += SMALL_NT) {
+          int I, J, K;
+          tail_split<D>(j, ni, inv, I, J, K);
+          const int i = (D == 3 ? (K + 1) * pl : 0) + (J + 1) * nk + (I + 1);
+          const double c = src[i];
+          double v;
+          if (D == 2)
+            v = relax_const<double>(c, (src[i - 1] + src[i + 1]) + (src[i - nk] + src[i + nk]), R64[i], w64,
+                                    hl2d, 4.0);
+          else
+            v = relax_const<double>(
+                c, ((src[i - 1] + src[i + 1]) + (src[i - nk] + src[i + nk])) + (src[i - pl] + src[i + pl]),
+                R64[i], w64, hl2d, 6.0);
+          dstl[i] = v;
+        }
+        __syncthreads();
+      }
+      const double* cur64 = (it & 1) ? yb : ya;
+      const double* prv64 = (it & 1) ? ya : yb;
+      for (int j = threadIdx.x; j < tail_count<D>(nk); j += SMALL_NT) {
+        xa[j] = rnd<T>(C(prv64[j]));
+        xb[j] = rnd<T>(C(cur64[j]));
+      }
+      __syncthreads();
+    }
+    for (int t = 1; t <= it && !(TOP64 && k == ktop); ++t) {
       const C* src = (t & 1) ? xa : xb;
       C* dstl = (t & 1) ? xb : xa;
       for (int j = threadIdx.x; j < icnt; j += SMALL_NT) {
@@ -1825,8 +1895,8 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
       }
       __syncthreads();
     }
-    const C* cur = (it & 1) ? xb : xa;
-    const C* prv = (it & 1) ? xa : xb;
+    const C* cur = (TOP64 && k == ktop) ? xb : ((it & 1) ? xb : xa);
+    const C* prv = (TOP64 && k == ktop) ? xa : ((it & 1) ? xa : xb);
     if (k == 0 && scur) {
       // level ms's final state (every node) for the next level's first
       // pass, which interpolates it itself
@@ -2034,6 +2104,29 @@ static hipError_t restrict_t(int d, const void* rf, const Lay& fl, void* rc, con
   if (d == 2) HOMG_LAUNCH((k_restrict_2d<T>), g, dim3(BX2), s, f, fl.pitch, c, cl.pitch, nc, len, done);
   HOMG_LAUNCH((k_restrict_3d<T>), g, dim3(BX3, BY3), s, f, fl.pitch, fl.plane, c, cl.pitch,
               cl.plane, nc, len, done);
+}
+
+template <typename TI>
+static hipError_t restrict_to_f64_t(int d, const void* rf, const Lay& fl, double* rc, const Lay& cl,
+                                    const int* done, hipStream_t s) {
+  const int nc = cl.side;
+  const int len = walk_len(d, nc);
+  const dim3 g = grid_of(d, nc, len);
+  const TI* f = static_cast<const TI*>(rf) + fl.off;
+  double* c = rc + cl.off;
+  if (d == 2) HOMG_LAUNCH((k_restrict_2d<TI, double>), g, dim3(BX2), s, f, fl.pitch, c, cl.pitch, nc, len, done);
+  HOMG_LAUNCH((k_restrict_3d<TI, double>), g, dim3(BX3, BY3), s, f, fl.pitch, fl.plane, c, cl.pitch,
+              cl.plane, nc, len, done);
+}
+
+hipError_t launch_restrict_to_f64(int prec, int d, const void* rf, const Lay& fl, double* rc,
+                                  const Lay& cl, const int* done, hipStream_t s) {
+  if (cl.side < 3) return hipSuccess;
+  switch (prec) {
+    case PREC_F64: return restrict_to_f64_t<double>(d, rf, fl, rc, cl, done, s);
+    case PREC_F32: return restrict_to_f64_t<float>(d, rf, fl, rc, cl, done, s);
+    default: return restrict_to_f64_t<bf16>(d, rf, fl, rc, cl, done, s);
+  }
 }
 
 hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void* rc,
@@ -2368,6 +2461,69 @@ hipError_t launch_sample(int d, const double* src, const Lay& sl, int stride, do
 
 // ------------------------------------------------------------ level-blocked launchers
 
+// FP64 compact copy (exact widening) of the level-l lattice of an array
+// stored in T; every node of the compact side, boundary included.
+template <typename T>
+__global__ __launch_bounds__(256) void k_widen(const T* __restrict__ src, int64_t sp, int64_t spl, int l,
+                                               double* __restrict__ dst, int64_t dp, int64_t dpl, int side,
+                                               int nz, const int* __restrict__ done) {
+  if (*done) return;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= side || z >= nz) return;
+  dst[int64_t(z) * dpl + int64_t(y) * dp + x] =
+      double(ld(src + int64_t(z) * l * spl + int64_t(y) * l * sp + int64_t(x) * l));
+}
+
+hipError_t launch_widen(int prec, int d, const void* src, const Lay& sl, int l, double* dst,
+                        const Lay& dl, const int* done, hipStream_t s) {
+  const int side = dl.side, nz = d == 3 ? side : 1;
+  const dim3 g = copy_grid(d, side);
+  switch (prec) {
+    case PREC_F64:
+      HOMG_LAUNCH((k_widen<double>), g, dim3(256), s, static_cast<const double*>(src) + sl.off, sl.pitch,
+                  sl.plane, l, dst + dl.off, dl.pitch, dl.plane, side, nz, done);
+    case PREC_F32:
+      HOMG_LAUNCH((k_widen<float>), g, dim3(256), s, static_cast<const float*>(src) + sl.off, sl.pitch,
+                  sl.plane, l, dst + dl.off, dl.pitch, dl.plane, side, nz, done);
+    default:
+      HOMG_LAUNCH((k_widen<bf16>), g, dim3(256), s, static_cast<const bf16*>(src) + sl.off, sl.pitch,
+                  sl.plane, l, dst + dl.off, dl.pitch, dl.plane, side, nz, done);
+  }
+}
+
+// FP64 compact array -> storage type T (rounded as k_pack rounds: to FP32,
+// then, for BF16, to BF16), every node of the compact side.
+template <typename T>
+__global__ __launch_bounds__(256) void k_narrow(const double* __restrict__ src, int64_t sp, int64_t spl,
+                                                T* __restrict__ dst, int64_t dp, int64_t dpl, int side, int nz,
+                                                const int* __restrict__ done) {
+  if (*done) return;
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= side || z >= nz) return;
+  st(dst + int64_t(z) * dpl + int64_t(y) * dp + x, typename Tr<T>::C(src[int64_t(z) * spl + int64_t(y) * sp + x]));
+}
+
+hipError_t launch_narrow(int prec, int d, const double* src, const Lay& sl, void* dst, const Lay& dl,
+                         const int* done, hipStream_t s) {
+  const int side = sl.side, nz = d == 3 ? side : 1;
+  const dim3 g = copy_grid(d, side);
+  switch (prec) {
+    case PREC_F64:
+      HOMG_LAUNCH((k_narrow<double>), g, dim3(256), s, src + sl.off, sl.pitch, sl.plane,
+                  static_cast<double*>(dst) + dl.off, dl.pitch, dl.plane, side, nz, done);
+    case PREC_F32:
+      HOMG_LAUNCH((k_narrow<float>), g, dim3(256), s, src + sl.off, sl.pitch, sl.plane,
+                  static_cast<float*>(dst) + dl.off, dl.pitch, dl.plane, side, nz, done);
+    default:
+      HOMG_LAUNCH((k_narrow<bf16>), g, dim3(256), s, src + sl.off, sl.pitch, sl.plane,
+                  static_cast<bf16*>(dst) + dl.off, dl.pitch, dl.plane, side, nz, done);
+  }
+}
+
 hipError_t launch_gather(int prec, int d, const void* src, const Lay& sl, int l, void* dst,
                          const Lay& dl, const int* done, hipStream_t s) {
   (void)done;
@@ -2434,50 +2590,60 @@ static hipError_t small_tz(int d, int nm, int l, int it, double omega, const voi
                    C(omega / 6.0), hl2, done);
 }
 
-size_t coarse_tail_lds(int prec, int d, int nms, int nlev) {
+size_t coarse_tail_lds(int prec, int d, int nms, int nlev, bool top64) {
   const size_t cs = prec == PREC_F64 ? 8 : 4;
-  size_t cnt = 0;
+  size_t cnt = 0, ctop = 0;
   for (int k = 0; k < nlev; ++k) {
     const size_t nk = size_t((nms - 1) >> k) + 1;
-    cnt += 3 * (d == 2 ? nk * nk : nk * nk * nk);
+    ctop = d == 2 ? nk * nk : nk * nk * nk;
+    cnt += 3 * ctop;
   }
-  return cnt * cs;
+  size_t b = cnt * cs;
+  if (top64 && prec != PREC_F64) b = ((b + 15) & ~size_t(15)) + 3 * ctop * 8;
+  return b;
 }
 
-template <typename T>
+template <typename T, bool TOP64>
 static hipError_t tail_t(int d, int nms, int nlev, const int* its, double omega, const void* rms,
                          const Lay& rl, void* dst, const Lay& tl, const int* done, hipStream_t s,
                          void* sprev, void* scur, const Lay& sl) {
   using C = typename Tr<T>::C;
   TailIts ti{};
   for (int k = 0; k < nlev; ++k) ti.it[k] = its[k];
-  const size_t lds = coarse_tail_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, nms, nlev);
+  const size_t lds = coarse_tail_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, nms, nlev, TOP64);
   const T* r = static_cast<const T*>(rms) + rl.off;
   T* o = dst ? static_cast<T*>(dst) + tl.off : nullptr;
   T* sp = scur ? static_cast<T*>(sprev) + sl.off : nullptr;
   T* sc = scur ? static_cast<T*>(scur) + sl.off : nullptr;
   if (d == 2) {
-    hipError_t a = allow_lds(k_coarse_tail<T, 2>, lds);
+    hipError_t a = allow_lds(k_coarse_tail<T, 2, TOP64>, lds);
     if (a != hipSuccess) return a;
-    HOMG_LAUNCH_SMEM((k_coarse_tail<T, 2>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
-                     tl.pitch, tl.plane, nms, nlev, ti, C(omega / 4.0), done, sp, sc, sl.pitch, sl.plane);
+    HOMG_LAUNCH_SMEM((k_coarse_tail<T, 2, TOP64>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
+                     tl.pitch, tl.plane, nms, nlev, ti, C(omega / 4.0), omega / 4.0, done, sp, sc, sl.pitch,
+                     sl.plane);
   }
-  hipError_t a = allow_lds(k_coarse_tail<T, 3>, lds);
+  hipError_t a = allow_lds(k_coarse_tail<T, 3, TOP64>, lds);
   if (a != hipSuccess) return a;
-  HOMG_LAUNCH_SMEM((k_coarse_tail<T, 3>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
-                   tl.pitch, tl.plane, nms, nlev, ti, C(omega / 6.0), done, sp, sc, sl.pitch, sl.plane);
+  HOMG_LAUNCH_SMEM((k_coarse_tail<T, 3, TOP64>), dim3(1), dim3(SMALL_NT), lds, s, r, rl.pitch, rl.plane, o,
+                   tl.pitch, tl.plane, nms, nlev, ti, C(omega / 6.0), omega / 6.0, done, sp, sc, sl.pitch,
+                   sl.plane);
 }
 
 hipError_t launch_coarse_tail(int prec, int d, int nms, int nlev, const int* its, double omega,
                               const void* rms, const Lay& rl, void* dst, const Lay& tl,
-                              const int* done, hipStream_t s, void* sprev, void* scur, const Lay& sl) {
-  if (nms < 5 || nlev < 1 || nlev > BATCH_MAX_LEVELS || ((nms - 1) >> (nlev - 1)) + 1 < 3 ||
+                              const int* done, hipStream_t s, void* sprev, void* scur, const Lay& sl,
+                              bool top64) {
+  if (nms < 5 || nlev < 2 || nlev > BATCH_MAX_LEVELS || ((nms - 1) >> (nlev - 1)) + 1 < 3 ||
       (!scur && !dst) || (scur && (!sprev || sl.side != nms)))
     return hipErrorInvalidValue;
   switch (prec) {
-    case PREC_F64: return tail_t<double>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
-    case PREC_F32: return tail_t<float>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
-    default: return tail_t<bf16>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
+    case PREC_F64: return tail_t<double, false>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
+    case PREC_F32:
+      return top64 ? tail_t<float, true>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl)
+                   : tail_t<float, false>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
+    default:
+      return top64 ? tail_t<bf16, true>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl)
+                   : tail_t<bf16, false>(d, nms, nlev, its, omega, rms, rl, dst, tl, done, s, sprev, scur, sl);
   }
 }
 
@@ -2581,17 +2747,21 @@ hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, 
 }
 
 // ------------------------------------------------------------ batched solver
-// Many independent 2D problems of uneven size in ONE persistent launch.  All
-// problems advance in lockstep global steps; at step k every unfinished
+// Many independent 2D problems of uneven size advanced together.  All
+// problems move in lockstep global steps; at step k every unfinished
 // problem runs the next stage of its own sequence
 //     norm(f), ||f||, residual, norm      (cycle 0)
-//     restriction 0..M-1, the schedule's iterations, residual, norm   (cycles 1, 2, ...)
-// The step's tiles (the same tiles, and the same tile code, as the
-// one-problem kernels) are spread over the co-resident workgroups, and a
-// grid barrier separates steps.  The norm stage of a cycle retires its
-// problem once the relative residual reaches the tolerance.  A barrier
-// that waits longer than its time limit raises an abort flag that every
-// workgroup checks, so the launch always terminates.
+//     restriction 0..M-1, per coarse level its iterations on the compact
+//     lattice and the hand-over to the next finer level (to the whole grid
+//     before level 0), level 0 in multi-iteration passes, residual, norm
+//                                                     (cycles 1, 2, ...)
+// One launch of k_batched_step runs one step for all problems: the step's
+// tiles (the same tiles, and the same tile code, as the one-problem
+// kernels) are spread round-robin over the launch's workgroups, and the
+// launch boundary separates steps.  The launches are recorded once in a
+// HIP graph (build_batch_graph) that the host replays.  The norm stage of
+// a cycle retires its problem once the relative residual reaches the
+// tolerance.
 
 __device__ __forceinline__ int tiles_of(int side, int len) {
   const int inner = side - 2;
@@ -2633,6 +2803,13 @@ __host__ __device__ __forceinline__ int batch_tb_len(const BatchProblem& p) { re
 constexpr int BATCH_XF_ROWS = 8;  // rows of a hand-over tile
 
 __device__ __forceinline__ int level_side(const BatchProblem& p, int m) { return (p.n - 1) / (1 << m) + 1; }
+
+// Level m of a batched problem is its FP64 coarsest level: reduced-precision
+// storage and m the top (>= 1) level.
+template <typename T>
+__device__ __forceinline__ bool batch_top64(const BatchProblem& p, int m) {
+  return sizeof(T) != 8 && p.top >= 1 && m == p.top;
+}
 
 __device__ __forceinline__ int stage_tiles(const BatchProblem& p, const StageInfo& si) {
   switch (si.kind) {
@@ -2708,15 +2885,43 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
     case BK_RESTRICT: {
       const int nc = (n - 1) / (2 << si.level) + 1;
       const int gxc = (nc - 2 + BX2 - 1) / BX2;
-      tile_restrict_2d<T>(static_cast<const T*>(p.r[si.level]), p.rp[si.level],
-                          static_cast<T*>(p.r[si.level + 1]), p.rp[si.level + 1], nc,
-                          p.len[si.level + 1], t % gxc, t / gxc);
+      if (batch_top64<T>(p, si.level + 1))
+        tile_restrict_2d<T, double>(static_cast<const T*>(p.r[si.level]), p.rp[si.level], p.r64, p.p64, nc,
+                                    p.len[si.level + 1], t % gxc, t / gxc);
+      else
+        tile_restrict_2d<T>(static_cast<const T*>(p.r[si.level]), p.rp[si.level],
+                            static_cast<T*>(p.r[si.level + 1]), p.rp[si.level + 1], nc,
+                            p.len[si.level + 1], t % gxc, t / gxc);
       break;
     }
     case BK_STAGE: {
       const int c = si.code, m = si.level, kind = bst_kind(c);
       const bool zero = bst_zero(c);
-      if (kind == BST_SWEEP) {  // iteration bst_index of level m >= 1 on its compact lattice
+      if (kind == BST_SWEEP && batch_top64<T>(p, m)) {
+        // the coarsest level in FP64 (the formula of the small-lattice
+        // kernel), each iterate also stored rounded for the hand-over
+        const int nm = level_side(p, m), it = bst_index(c);
+        const double* xo = p.x64[(it - 1) & 1];
+        double* xn = p.x64[it & 1];
+        T* xr = static_cast<T*>(p.x[m][it & 1]);
+        const double hl = 1.0 / double(nm - 1), hl2 = hl * hl, w = run.omega / 4.0;
+        const int gxm = (nm - 2 + BX2 - 1) / BX2;
+        const int I = 1 + (t % gxm) * BX2 + threadIdx.x;
+        const int J0 = 1 + (t / gxm) * p.len[m], J1 = min(nm - 1, J0 + p.len[m]);
+        if (I <= nm - 2)
+          for (int J = J0; J < J1; ++J) {
+            const int64_t o = int64_t(J) * p.p64 + I;
+            double v;
+            if (zero) {
+              v = relax_const<double>(0.0, (0.0 + 0.0) + (0.0 + 0.0), p.r64[o], w, hl2, 4.0);
+            } else {
+              v = relax_const<double>(xo[o], (xo[o - 1] + xo[o + 1]) + (xo[o - p.p64] + xo[o + p.p64]), p.r64[o],
+                                      w, hl2, 4.0);
+            }
+            xn[o] = v;
+            st(xr + int64_t(J) * p.rp[m] + I, typename Tr<T>::C(v));
+          }
+      } else if (kind == BST_SWEEP) {  // iteration bst_index of level m >= 1 on its compact lattice
         const int nm = level_side(p, m), it = bst_index(c);
         const T* xo = static_cast<const T*>(p.x[m][(it - 1) & 1]);
         T* xn = static_cast<T*>(p.x[m][it & 1]);
@@ -2881,15 +3086,16 @@ hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds) {
   }
 }
 
-// The batched solve as a HIP graph of two kernel nodes (state reset, then the
-// persistent kernel).  The persistent node carries the cooperative launch
-// attribute: the runtime then places all `grid` workgroups at once (or
-// refuses the launch), which the grid barrier between steps relies on.
+// Reset of a batched solve's per-problem state and step counter (an
+// ordinary launch on the caller's stream before the first replay).
 hipError_t launch_batch_init(int P, BatchState* bs, int* done, BatchSync* sync, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_init, dim3((P + 255) / 256), dim3(256), 0, s, bs, done, P, sync);
   return hipGetLastError();
 }
 
+// The graph one replay runs: BATCH_STEPS_PER_REPLAY step launches in a
+// chain (each `grid` workgroups of 256 lanes; step j of the replay runs
+// global step base + j), then the one-lane node that advances base.
 hipError_t build_batch_graph(int prec, int P, int grid, const BatchProblem* probs, BatchState* bs,
                              int* done, const int* levels_of_sweep, const BatchRun* run,
                              BatchSync* sync, hipGraph_t* out) {

@@ -89,6 +89,7 @@ def load_library(path=LIB_PATH):
     L.homg_batch_solve.argtypes = [H, PP, PP, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double),
                                    ip, ip]
     L.homg_batch_set_tile_rows.argtypes = [H, ctypes.c_int64, ctypes.c_int]
+    L.homg_batch_set_pass_iters.argtypes = [H, ctypes.c_int64, ctypes.c_int]
     L.homg_batch_tune.argtypes = [H, PP, PP, ctypes.c_double, vp, ctypes.c_char_p]
     L.homg_batch_destroy.argtypes = [H]
     L.homg_set_smoother.argtypes = [H, ctypes.c_int, vp, ctypes.c_double, vp]
@@ -116,7 +117,8 @@ def load_library(path=LIB_PATH):
     for name in ("homg_create", "homg_destroy", "homg_set_coefficient", "homg_solve",
                  "homg_solve_cycles", "homg_residual", "homg_get_schedule", "homg_step_restrict",
                  "homg_step_sweeps", "homg_step_cycle", "homg_set_profiling", "homg_get_profile",
-                 "homg_batch_create", "homg_batch_solve", "homg_batch_set_tile_rows", "homg_batch_tune",
+                 "homg_batch_create", "homg_batch_solve", "homg_batch_set_tile_rows", "homg_batch_set_pass_iters",
+                 "homg_batch_tune",
                  "homg_batch_destroy", "homg_set_smoother", "homg_get_smoother_weights",
                  "homg_smoother_gate", "homg_trainer_create", "homg_trainer_add_problem",
                  "homg_trainer_count", "homg_trainer_train", "homg_trainer_loss", "homg_trainer_destroy",
@@ -147,6 +149,16 @@ def _ptr(t, dtype=None):
     if t.dtype != want:
         raise ValueError("arrays must be %s" % str(want).replace("torch.", ""))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _shape(t, shape, what):
+    """Raise ValueError unless tensor t (if given) has exactly `shape`.  The C
+    ABI takes raw pointers and cannot see sizes: an undersized array would
+    be read or written past its end by the kernels."""
+    if t is None:
+        return
+    if tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError("%s must have shape %s, got %s" % (what, tuple(shape), tuple(t.shape)))
 
 
 def _stream(stream):
@@ -200,7 +212,16 @@ class Solver:
         except Exception:
             pass
 
+    def _grid(self, level=0):
+        return ((self.n - 1) // (1 << level) + 1,) * self.ndim
+
+    def _level(self, level):
+        side = (self.n - 1) // (1 << level) + 1 if level >= 0 else 0
+        if level < 0 or side < 3 or (side - 1) << level != self.n - 1:
+            raise ValueError("level %d out of range for side %d" % (level, self.n))
+
     def set_coefficient(self, a, stream=None):
+        _shape(a, self._grid(), "a")
         self._check(lib().homg_set_coefficient(self._h, _ptr(a), _stream(stream)))
 
     def _info(self):
@@ -218,6 +239,8 @@ class Solver:
                 "smoother_fell_back": bool(info.smoother_fell_back)}
 
     def solve(self, f, u, tol=1e-10, stream=None, raise_on_status=True):
+        _shape(f, self._grid(), "f")
+        _shape(u, self._grid(), "u")
         info, hist = self._info()
         st = lib().homg_solve(self._h, _ptr(f), _ptr(u), tol, _stream(stream), ctypes.byref(info))
         out = self._result(info, hist)
@@ -227,12 +250,16 @@ class Solver:
         return out
 
     def solve_cycles(self, f, u, cycles, stream=None):
+        _shape(f, self._grid(), "f")
+        _shape(u, self._grid(), "u")
         info, hist = self._info()
         st = lib().homg_solve_cycles(self._h, _ptr(f), _ptr(u), cycles, _stream(stream), ctypes.byref(info))
         self._check(st)
         return self._result(info, hist)
 
     def residual(self, f, u, r=None, stream=None):
+        for t, what in ((f, "f"), (u, "u"), (r, "r")):
+            _shape(t, self._grid(), what)
         rel = ctypes.c_double()
         self._check(lib().homg_residual(self._h, _ptr(f), _ptr(u), _ptr(r), ctypes.byref(rel), _stream(stream)))
         return rel.value
@@ -257,13 +284,23 @@ class Solver:
                  "launches": b.launches, "ms": b.ms} for b in buf[:n.value]]
 
     def step_restrict(self, level, r_fine, r_coarse, stream=None):
+        self._level(level)
+        self._level(level + 1)
+        _shape(r_fine, self._grid(level), "r_fine")
+        _shape(r_coarse, self._grid(level + 1), "r_coarse")
         self._check(lib().homg_step_restrict(self._h, level, _ptr(r_fine), _ptr(r_coarse), _stream(stream)))
 
     def step_sweeps(self, level, iters, e_old, r_level, e_new, stream=None):
+        self._level(level)
+        _shape(e_old, self._grid(), "e_old")
+        _shape(r_level, self._grid(level), "r_level")
+        _shape(e_new, self._grid(), "e_new")
         self._check(lib().homg_step_sweeps(self._h, level, iters, _ptr(e_old), _ptr(r_level),
                                            _ptr(e_new), _stream(stream)))
 
     def step_cycle(self, r0, acc, stream=None):
+        _shape(r0, self._grid(), "r0")
+        _shape(acc, self._grid(), "acc")
         self._check(lib().homg_step_cycle(self._h, _ptr(r0), _ptr(acc), _stream(stream)))
 
     def set_smoother(self, smoother, w=None, fallback_ratio=0.0, stream=None):
@@ -280,6 +317,8 @@ class Solver:
         return out
 
     def smoother_gate(self, fs, cycles, stream=None):
+        for f in fs:
+            _shape(f, self._grid(), "f")
         n = len(fs)
         arr = (ctypes.c_void_p * n)(*[_ptr(f).value for f in fs])
         rl = (ctypes.c_double * n)()
@@ -368,12 +407,22 @@ def _check_global(st):
         raise HomgError(st, lib().homg_last_error(None).decode())
 
 
+def _lattice(x, *others):
+    """Side nm of the square compact lattice x; every other array (None
+    allowed) must have x's shape."""
+    if x.dim() != 2 or x.shape[0] != x.shape[1] or x.shape[0] < 3:
+        raise ValueError("x must be a square lattice of side >= 3, got %s" % (tuple(x.shape),))
+    for t, what in others:
+        _shape(t, x.shape, what)
+    return int(x.shape[0])
+
+
 def learn_forward(x, r, a, w, hl, y, stream=None):
     """Network output of the learned relaxation on one compact lattice
     (dense float32 GPU arrays of side nm; a may be None)."""
     import torch
     f32 = torch.float32
-    nm = x.shape[0]
+    nm = _lattice(x, (r, "r"), (a, "a"), (y, "y"))
     _check_global(lib().homg_learn_forward(nm, hl, _ptr(x, f32), _ptr(r, f32),
                                            _ptr(a, f32) if a is not None else None,
                                            _ptr(_weights(w), f32), _ptr(y, f32), _stream(stream)))
@@ -383,7 +432,7 @@ def learn_grad(x, r, a, delta, w, hl, stream=None):
     """(dL/dw as a float64 GPU tensor of 576, E(delta - y), L) for one sample."""
     import torch
     f32 = torch.float32
-    nm = x.shape[0]
+    nm = _lattice(x, (r, "r"), (a, "a"), (delta, "delta"))
     g = torch.empty(SMOOTHER_WEIGHTS + 1, dtype=torch.float64, device="cuda")
     loss = ctypes.c_double()
     _check_global(lib().homg_learn_grad(nm, hl, _ptr(x, f32), _ptr(r, f32),
@@ -395,6 +444,8 @@ def learn_grad(x, r, a, delta, w, hl, stream=None):
 def learn_adam(theta, m1, m2, grad, t, lr, w_out, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     import torch
     f32 = torch.float32
+    for v, what in ((theta, "theta"), (m1, "m1"), (m2, "m2"), (grad, "grad"), (w_out, "w_out")):
+        _shape(v, (SMOOTHER_WEIGHTS,), what)
     _check_global(lib().homg_learn_adam(_ptr(theta, f32), _ptr(m1, f32), _ptr(m2, f32), _ptr(grad), t, lr,
                                         beta1, beta2, eps, _ptr(w_out, f32), _stream(stream)))
 
@@ -422,17 +473,21 @@ class BatchSolver:
         if st != HOMG_OK:
             raise HomgError(st, lib().homg_last_error(None).decode())
 
+    def _check_arrays(self, fs, us):
+        n = len(self.sides)
+        if len(fs) != n or len(us) != n:
+            raise ValueError("need one f and one u per problem")
+        for i, side in enumerate(self.sides):
+            _shape(fs[i], (side, side), "f[%d]" % i)
+            _shape(us[i], (side, side), "u[%d]" % i)
+
     @staticmethod
     def _ptrs(ts):
         return (ctypes.c_void_p * len(ts))(*[_ptr(t).value for t in ts])
 
     def solve(self, fs, us, tol=1e-10, stream=None, raise_on_status=True):
+        self._check_arrays(fs, us)
         n = len(self.sides)
-        if len(fs) != n or len(us) != n:
-            raise ValueError("need one f and one u per problem")
-        for t, s in zip(fs, self.sides):
-            if tuple(t.shape) != (s, s):
-                raise ValueError("array shape does not match its side")
         rel = (ctypes.c_double * n)()
         cyc = (ctypes.c_int * n)()
         sts = (ctypes.c_int * n)()
@@ -445,7 +500,11 @@ class BatchSolver:
     def set_tile_rows(self, side, rows):
         self._check(lib().homg_batch_set_tile_rows(self._h, side, rows))
 
+    def set_pass_iters(self, side, iters):
+        self._check(lib().homg_batch_set_pass_iters(self._h, side, iters))
+
     def tune(self, fs, us, tol=1e-10, cache_path=None, stream=None):
+        self._check_arrays(fs, us)
         self._check(lib().homg_batch_tune(self._h, self._ptrs(fs), self._ptrs(us), tol, _stream(stream),
                                           cache_path.encode() if cache_path else None))
 

@@ -84,3 +84,85 @@ def test_calls_reject_null_handle():
     info = B.Info()
     assert L.homg_solve(None, None, None, 1e-10, None, ctypes.byref(info)) == 1
     assert L.homg_residual(None, None, None, None, None, None) == 1
+
+
+# ------------------------------------------------- argument shapes (binding)
+#
+# The C ABI takes raw device pointers and cannot see array sizes, so the
+# binding checks every array's shape against the handle before any call.
+# These objects are built without a device: the checks must fire first.
+
+def _solver(ndim, n):
+    from paper_1108_2045_amd import homg as B
+    s = B.Solver.__new__(B.Solver)
+    s._h, s.ndim, s.n, s.max_cycles, s.precision = None, ndim, n, 10, "fp64"
+    return s
+
+
+def _t(*shape, dtype=None):
+    import torch
+    return torch.zeros(shape, dtype=dtype or torch.float64)
+
+
+@pytest.mark.parametrize("ndim,n", [(2, 33), (3, 17)])
+def test_solver_rejects_wrong_shapes(ndim, n):
+    s = _solver(ndim, n)
+    good, small = _t(*([n] * ndim)), _t(*([n - 1] * ndim))
+    flat = _t(n ** ndim)
+    with pytest.raises(ValueError, match="shape"):
+        s.solve(small, good)
+    with pytest.raises(ValueError, match="shape"):
+        s.solve(good, small)
+    with pytest.raises(ValueError, match="shape"):
+        s.solve_cycles(good, flat, 1)
+    with pytest.raises(ValueError, match="shape"):
+        s.residual(good, good, small)
+    with pytest.raises(ValueError, match="shape"):
+        s.set_coefficient(small)
+    with pytest.raises(ValueError, match="shape"):
+        s.step_cycle(good, small)
+    nc = (n - 1) // 2 + 1
+    with pytest.raises(ValueError, match="shape"):
+        s.step_restrict(0, good, good)          # coarse array of the fine side
+    with pytest.raises(ValueError, match="shape"):
+        s.step_restrict(1, good, _t(*([(nc - 1) // 2 + 1] * ndim)))
+    with pytest.raises(ValueError, match="shape"):
+        s.step_sweeps(1, 1, good, good, good)   # level-1 residual of the fine side
+    with pytest.raises(ValueError, match="level"):
+        s.step_sweeps(9, 1, good, good, good)
+    with pytest.raises(ValueError, match="shape"):
+        s.smoother_gate([good, small], 2)
+    # right shapes pass the shape check and stop at the device check
+    with pytest.raises(ValueError, match="GPU"):
+        s.solve(good, good)
+    with pytest.raises(ValueError, match="GPU"):
+        s.step_sweeps(1, 1, good, _t(*([nc] * ndim)), good)
+
+
+def test_batch_and_learned_calls_reject_wrong_shapes():
+    import torch
+    from paper_1108_2045_amd import homg as B
+    b = B.BatchSolver.__new__(B.BatchSolver)
+    b._h, b.sides = None, [9, 17]
+    fs = [_t(9, 9), _t(17, 17)]
+    with pytest.raises(ValueError, match="shape"):
+        b.solve(fs, [_t(9, 9), _t(9, 9)])
+    with pytest.raises(ValueError, match="shape"):
+        b.tune([_t(9, 9), _t(16, 16)], fs)
+    with pytest.raises(ValueError, match="one f and one u"):
+        b.solve(fs, fs[:1])
+    f32 = torch.float32
+    x = _t(17, 17, dtype=f32)
+    w = _t(B.SMOOTHER_WEIGHTS, dtype=f32)
+    with pytest.raises(ValueError, match="shape"):
+        B.learn_forward(x, _t(9, 9, dtype=f32), None, w, 0.1, x)
+    with pytest.raises(ValueError, match="shape"):
+        B.learn_forward(x, x, None, w, 0.1, _t(17, 16, dtype=f32))
+    with pytest.raises(ValueError, match="square"):
+        B.learn_grad(_t(17, 9, dtype=f32), x, None, x, w, 0.1)
+    with pytest.raises(ValueError, match="shape"):
+        B.learn_grad(x, x, _t(16, 16, dtype=f32), x, w, 0.1)
+    with pytest.raises(ValueError, match="shape"):
+        B.learn_adam(w, w, _t(10, dtype=f32), _t(B.SMOOTHER_WEIGHTS), 1, 1e-3, w)
+    with pytest.raises(ValueError):
+        B.learn_forward(x, x, None, _t(575, dtype=f32), 0.1, x)

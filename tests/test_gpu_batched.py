@@ -129,3 +129,55 @@ def test_batch_reports_unconverged_problems(B, torch_cuda):
     bs = B.BatchSolver(sides, precision="fp64", max_cycles=2)
     res = bs.solve(fs, us, tol=1e-12, raise_on_status=False)
     assert res["status"] == 7 and res["statuses"] == [7, 7] and res["cycles"] == [2, 2]
+
+
+def test_batch_pass_iterations_are_bitwise_identical(B, torch_cuda):
+    """Level-0 passes of 1, 2, 3 or 4 iterations give the same iterates bit
+    for bit (only the number of steps changes)."""
+    torch = torch_cuda
+    sides = [129, 65, 257, 17]
+    fs = [dev(torch, W.uniform(2, s, seed=400 + i)) for i, s in enumerate(sides)]
+    outs = []
+    for its in (4, 1, 2, 3):
+        say("batch pass iterations %d" % its)
+        bs = B.BatchSolver(sides, precision="fp32")
+        for s in set(sides):
+            bs.set_pass_iters(s, its)
+        us = [torch.zeros((s, s), dtype=torch.float64, device="cuda") for s in sides]
+        res = bs.solve(fs, us, tol=1e-10)
+        outs.append((res["cycles"], [u.clone() for u in us]))
+    for cyc, us in outs[1:]:
+        assert cyc == outs[0][0]
+        assert all(torch.equal(a, b) for a, b in zip(us, outs[0][1]))
+
+
+def test_batch_tuner_times_real_solves_and_restores_u(B, torch_cuda, tmp_path):
+    """Every timed candidate starts from the caller's initial guess (a
+    non-zero one here), which the tuner leaves in place; a tuning run whose
+    guesses already meet tol is refused, since it would time no cycle."""
+    torch = torch_cuda
+    sides = [65, 129, 33]
+    rng = np.random.default_rng(5)
+    fs = [dev(torch, W.uniform(2, s, seed=500 + i)) for i, s in enumerate(sides)]
+    u0 = []
+    for s in sides:
+        g = np.zeros((s, s))
+        g[1:-1, 1:-1] = rng.standard_normal((s - 2, s - 2))
+        u0.append(dev(torch, g))
+    us = [u.clone() for u in u0]
+    bs = B.BatchSolver(sides, precision="fp32")
+    say("tuner from a non-zero guess")
+    bs.tune(fs, us, tol=1e-10, cache_path=str(tmp_path / "t.txt"))
+    assert all(torch.equal(a, b) for a, b in zip(us, u0))
+    lines = open(tmp_path / "t.txt").read().split("\n")
+    assert sum(1 for ln in lines if ln.strip()) == len(set(sides))
+    for ln in lines:
+        if ln.strip():
+            key, side, rows, its = ln.split()
+            assert int(side) in sides and int(rows) >= 1 and 1 <= int(its) <= 4
+    res = bs.solve(fs, us, tol=1e-10)
+    assert res["status"] == 0 and min(res["cycles"]) >= 1
+    say("tuner on converged guesses")
+    with pytest.raises(B.HomgError) as ei:
+        B.BatchSolver(sides, precision="fp32").tune(fs, us, tol=1e-3)
+    assert ei.value.status == 1
