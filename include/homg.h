@@ -394,6 +394,27 @@ homg_status homg_learn_grad(int nm, double hl, const float *x, const float *r, c
 homg_status homg_learn_adam(float *theta, float *m1, float *m2, const double *grad, int t, double lr,
                             double beta1, double beta2, double eps, float *w_out, void *stream);
 
+/*
+ * homg_residual without a handle and without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Laplacian of the handle-free
+ * grid (5-point for ndim 2, 7-point for ndim 3), side n = 2^k + 1 (2D k <=
+ * 15, 3D k <= 10).  f, u, r: dense FP64 device arrays of n^ndim nodes; the
+ * interior entries of r (required) receive f - A u, its boundary entries are
+ * not written; *relres_out (host, may
+ * be NULL) receives ||r||_2 / ||f||_2 over interior nodes (the stream is
+ * then synchronised).  Results equal homg_residual's bit for bit.
+ * The partial sums live in a static device workspace of
+ * HOMG_NOALLOC_MAX_PARTIALS doubles plus 64 bytes (about 1 MiB), which
+ * every GPU that runs this call holds until the process ends; a grid that
+ * needs more partial sums gets HOMG_ERR_WORKSPACE.  All calls on one GPU
+ * share that workspace: calls that overlap on one GPU (different streams or
+ * host threads) race; a call clears what it needs before use.
+ */
+#define HOMG_NOALLOC_MAX_PARTIALS 131072
+homg_status homg_residual_noalloc(int ndim, int64_t n, const double *f, const double *u, double *r,
+                                  double *relres_out, void *stream);
+
 /* Text of the last error on h (or of the calling thread if h is NULL). */
 const char *homg_last_error(homg_handle h);
 

@@ -6,4 +6,4 @@ does not touch the GPU; creating a Solver does.
 """
 from .homg import (DIFFUSION_5PT_2D, JACOBI, LAPLACE_5PT_2D, LAPLACE_7PT_3D, LEARNED,  # noqa: F401
                    SMOOTHER_WEIGHTS, BatchSolver, HomgError, Solver, Trainer, learn_adam, learn_forward,
-                   jacobi_weights, learn_grad, lib, version)
+                   jacobi_weights, learn_grad, lib, residual_noalloc, version)

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhomg.so")
-SOURCES = ["homg_kernels.hip", "homg_learned.hip", "homg_capi.cpp", "homg_batch.cpp", "homg_train.cpp"]
+SOURCES = ["homg_kernels.hip", "homg_learned.hip", "homg_capi.cpp", "homg_batch.cpp", "homg_train.cpp",
+           "homg_noalloc.hip"]
 ARCH = "gfx950"
 
 

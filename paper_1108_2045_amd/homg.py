@@ -110,6 +110,8 @@ def load_library(path=LIB_PATH):
                                   ctypes.POINTER(ctypes.c_double), vp]
     L.homg_learn_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, vp, vp]
+    L.homg_residual_noalloc.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp,
+                                        ctypes.POINTER(ctypes.c_double), vp]
     L.homg_last_error.argtypes = [H]
     L.homg_last_error.restype = ctypes.c_char_p
     L.homg_version.argtypes = []
@@ -122,7 +124,7 @@ def load_library(path=LIB_PATH):
                  "homg_batch_destroy", "homg_set_smoother", "homg_get_smoother_weights",
                  "homg_smoother_gate", "homg_trainer_create", "homg_trainer_add_problem",
                  "homg_trainer_count", "homg_trainer_train", "homg_trainer_loss", "homg_trainer_destroy",
-                 "homg_learn_forward", "homg_learn_grad", "homg_learn_adam"):
+                 "homg_learn_forward", "homg_learn_grad", "homg_learn_adam", "homg_residual_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -448,6 +450,21 @@ def learn_adam(theta, m1, m2, grad, t, lr, w_out, beta1=0.9, beta2=0.999, eps=1e
         _shape(v, (SMOOTHER_WEIGHTS,), what)
     _check_global(lib().homg_learn_adam(_ptr(theta, f32), _ptr(m1, f32), _ptr(m2, f32), _ptr(grad), t, lr,
                                         beta1, beta2, eps, _ptr(w_out, f32), _stream(stream)))
+
+
+def residual_noalloc(f, u, r, stream=None):
+    """r = f - A u (Laplacian) and ||r|| / ||f|| with no handle and no device
+    allocation (the library's static workspace); f, u, r dense float64 GPU
+    arrays of the same cubic/square shape."""
+    ndim = f.dim()
+    n = int(f.shape[0])
+    _shape(f, (n,) * ndim, "f")
+    _shape(u, (n,) * ndim, "u")
+    _shape(r, (n,) * ndim, "r")
+    rel = ctypes.c_double()
+    _check_global(lib().homg_residual_noalloc(ndim, n, _ptr(f), _ptr(u), _ptr(r), ctypes.byref(rel),
+                                              _stream(stream)))
+    return rel.value
 
 
 class BatchSolver:
