@@ -168,6 +168,29 @@ homg_status homg_residual(homg_handle h, const double *f, const double *u, doubl
 homg_status homg_get_schedule(homg_handle h, int *pairs, int cap, int *len);
 
 /*
+ * Paper-reproduction support (Sec. 4).
+ *
+ * homg_l1_error: the normalised L1 error of Sec. 4 in discrete form,
+ *   *err_out (host) = sum |u_ref - v| / sum |u_ref| over all n^d nodes of the
+ *   dense FP64 device arrays u_ref (e.g. the analytic solution sampled at the
+ *   nodes) and v (the approximation); sum |u_ref - v| itself if u_ref = 0.
+ *   Fixed summation order; synchronises.
+ * homg_trace_cycle: one MFMG cycle (the handle's schedule) on A e = f - A u
+ *   from e = 0, run one whole-grid iteration at a time, recording after
+ *   iteration k (k = 1 .. sweeps of the cycle) the normalised L1 error of
+ *   u + e_k against u_ref in err_out[k-1] (host, cap entries); the last
+ *   iteration adds e into u, as a solve's cycle does.  *count receives the
+ *   number of iterations.  Each iteration is one work unit (WU) of Sec. 4
+ *   (an operation over the entire grid).  FP64 handles with damped Jacobi
+ *   only (HOMG_ERR_UNSUPPORTED otherwise); HOMG_ERR_WORKSPACE if cap is
+ *   smaller than the cycle's iterations.  Synchronises.
+ */
+homg_status homg_l1_error(homg_handle h, const double *u_ref, const double *v, double *err_out,
+                          void *stream);
+homg_status homg_trace_cycle(homg_handle h, const double *f, double *u, const double *u_ref,
+                             double *err_out, int cap, int *count, void *stream);
+
+/*
  * Kernel-level entry points (the steps of one cycle, for testing and
  * measurement).  Dense FP64 device arrays in and out; inside, the data are
  * converted to the handle's precision and layout, the same kernels as in

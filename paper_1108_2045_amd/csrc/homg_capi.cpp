@@ -104,6 +104,10 @@ struct homg_ctx {
   double* r64 = nullptr;
   double* x64[2] = {nullptr, nullptr};
   Lay l64;
+  // L1 error (Sec. 4): partial sums and per-iteration results (allocated on first use)
+  double* l1part = nullptr;
+  double* l1out = nullptr;
+  int l1cap = 0;
 };
 
 namespace {
@@ -209,6 +213,8 @@ void free_ctx(homg_ctx* h) {
   (void)hipFree(h->zero_flag);
   (void)hipFree(h->wbf);
   (void)hipFree(h->w32);
+  (void)hipFree(h->l1part);
+  (void)hipFree(h->l1out);
   (void)hipFree(h->r64);
   (void)hipFree(h->x64[0]);
   (void)hipFree(h->x64[1]);
@@ -1210,6 +1216,91 @@ homg_status homg_smoother_gate(homg_handle h, int count, const double* const* f,
   (void)hipFree(u);
   if (st != HOMG_OK) return st;
   *accepted = ok;
+  return HOMG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of the L1 error for up to `slots` results.
+homg_status l1_ready(homg_ctx* h, int slots) {
+  if (!h->l1part)
+    if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->l1part), sizeof(double) * l1_partials())) return e;
+  if (h->l1cap < slots) {
+    (void)hipFree(h->l1out);
+    h->l1out = nullptr;
+    h->l1cap = 0;
+    if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->l1out), sizeof(double) * slots)) return e;
+    h->l1cap = slots;
+  }
+  return HOMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+homg_status homg_l1_error(homg_handle h, const double* u_ref, const double* v, double* err_out, void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!u_ref || !v || !err_out) return fail(h, HOMG_ERR_INVALID_ARG, "null argument");
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (homg_status e = l1_ready(h, 1)) return e;
+  LAUNCH(h, launch_l1(PREC_F64, h->d, h->n, u_ref, v, nullptr, h->el, h->l1part, h->l1out, s));
+  HIPCHK(h, hipMemcpyAsync(err_out, h->l1out, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return HOMG_OK;
+}
+
+homg_status homg_trace_cycle(homg_handle h, const double* f, double* u, const double* u_ref, double* err_out,
+                             int cap, int* count, void* stream) {
+  if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
+  if (!f || !u || !u_ref || !err_out || !count) return fail(h, HOMG_ERR_INVALID_ARG, "null argument");
+  if (h->prec != PREC_F64 || h->smoother != HOMG_SMOOTHER_JACOBI)
+    return fail(h, HOMG_ERR_UNSUPPORTED, "the cycle trace runs FP64 damped-Jacobi handles");
+  if (cap < h->total_sweeps) return fail(h, HOMG_ERR_WORKSPACE, "err_out holds fewer entries than the cycle's iterations");
+  if (homg_status c = check_ready(h)) return c;
+  DeviceGuard guard(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (homg_status e = l1_ready(h, h->total_sweeps)) return e;
+  h->active_smoother = 0;
+  const int* done = h->zero_flag;
+  // r_0 = f - A u and its pyramid, as at the start of a solve's cycle
+  int pcount = 0;
+  const Lay none;
+  const double* a0 = h->has_coef ? h->a[0] : nullptr;
+  LAUNCH(h, launch_residual(h->prec, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none, h->r[0], h->rl[0],
+                            h->partials, &pcount, done, s));
+  for (int m = 0; m < h->top_level; ++m)
+    if (homg_status e = enqueue_restrict(h, m, done, s)) return e;
+  // the schedule one whole-grid iteration at a time (the form in which
+  // every iterate exists on the whole grid), the L1 error of u + e after
+  // each; the last iteration adds e into u
+  const int keep = h->temporal;
+  h->temporal = 0;
+  h->chain_ready = -1;
+  h->lat_level = -1;
+  int cur = 0, k = 0;
+  homg_status st = HOMG_OK;
+  const size_t np = h->sched.size() / 2;
+  for (size_t p = 0; p < np && st == HOMG_OK; ++p) {
+    const int m = h->sched[2 * p], it = h->sched[2 * p + 1];
+    for (int t = 0; t < it && st == HOMG_OK; ++t, ++k) {
+      const bool first = p == 0 && t == 0, last = p + 1 == np && t + 1 == it;
+      st = run_level(h, m, 1, first, last, -1, &cur, u, done, s);
+      if (st != HOMG_OK) break;
+      hipError_t le = launch_l1(h->prec, h->d, h->n, u_ref, u, last ? nullptr : h->e[cur], h->el, h->l1part,
+                                h->l1out + k, s);
+      ++h->launches;
+      if (le != hipSuccess) st = fail(h, HOMG_ERR_HIP, std::string("launch_l1: ") + hipGetErrorString(le));
+    }
+  }
+  h->temporal = keep;
+  if (st != HOMG_OK) return st;
+  HIPCHK(h, hipMemcpyAsync(err_out, h->l1out, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  *count = k;
   return HOMG_OK;
 }
 

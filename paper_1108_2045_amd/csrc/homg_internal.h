@@ -66,6 +66,13 @@ hipError_t launch_residual_restrict_2d(int prec, int n, const double* u, const L
 hipError_t launch_finalize(const double* partials, int count, DevState* st, double* history,
                            int cycle, int mode, hipStream_t s);
 hipError_t launch_init_state(DevState* st, double tol, int stop_on_tol, hipStream_t s);
+// Normalised L1 error (Sec. 4, discrete): *out (device) = sum |uref - v| /
+// sum |uref| over all n^d nodes, v = u + e (e: internal iterate of type
+// prec, layout el) or v = u when e is null; uref and u dense FP64.  part:
+// l1_partials() doubles of workspace.
+int l1_partials();
+hipError_t launch_l1(int prec, int d, int n, const double* uref, const double* u, const void* e,
+                     const Lay& el, double* part, double* out, hipStream_t s);
 // One full-weighting restriction: fine level (side nf) -> coarse (side (nf-1)/2+1).
 hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void* rc,
                            const Lay& cl, const int* done, hipStream_t s);

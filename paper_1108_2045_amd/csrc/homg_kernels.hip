@@ -509,6 +509,53 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const double* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------ L1 error
+// The normalised L1 error of Sec. 4 in its discrete form, sum |u_ref - v| /
+// sum |u_ref| over all nodes, with v = u (+ e, an internal iterate in its
+// storage type and padded layout, when given).  A fixed grid of L1_BLOCKS
+// workgroups walks the rows; each writes its two partial sums, and one
+// workgroup adds them in a fixed order -- the result does not depend on
+// timing.
+constexpr int L1_BLOCKS = 1024;
+
+template <typename T, bool HAS_E>
+__global__ __launch_bounds__(256) void k_l1_partial(const double* __restrict__ uref, const double* __restrict__ u,
+                                                    const T* __restrict__ e, int64_t ep, int64_t epl, int n,
+                                                    int d, double* __restrict__ part) {
+  const int64_t rows = d == 3 ? int64_t(n) * n : int64_t(n);
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int64_t j = d == 3 ? row % n : row, k = d == 3 ? row / n : 0;
+    const int64_t o = row * n;
+    for (int i = threadIdx.x; i < n; i += 256) {
+      double v = u[o + i];
+      if (HAS_E) v += double(ld(e + k * epl + j * ep + i));
+      const double a = uref[o + i];
+      s1 += fabs(a - v);
+      s2 += fabs(a);
+    }
+  }
+  s1 = block_sum<256>(s1);
+  __syncthreads();
+  s2 = block_sum<256>(s2);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_l1_finish(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    s1 += part[2 * b];
+    s2 += part[2 * b + 1];
+  }
+  s1 = block_sum<256>(s1);
+  __syncthreads();
+  s2 = block_sum<256>(s2);
+  if (threadIdx.x == 0) *out = s2 > 0.0 ? s1 / s2 : s1;
+}
+
 // ------------------------------------------------------------ restriction
 // Full weighting (Sec. 2: linearly weighted averages as nested partial
 // reductions): coarse node = (1/4)[1 2 1] per axis of the fine neighbours.
@@ -2081,6 +2128,33 @@ hipError_t launch_residual_restrict_2d(int prec, int n, const double* u, const L
     case PREC_F64: return residual_restrict_t<double>(n, u, ul, f, fl, r0, rl, rc, cl, partials, count, done, s);
     case PREC_F32: return residual_restrict_t<float>(n, u, ul, f, fl, r0, rl, rc, cl, partials, count, done, s);
     default: return residual_restrict_t<bf16>(n, u, ul, f, fl, r0, rl, rc, cl, partials, count, done, s);
+  }
+}
+
+template <typename T>
+static hipError_t l1_t(int d, int n, const double* uref, const double* u, const void* e, const Lay& el,
+                       double* part, double* out, hipStream_t s) {
+  const int64_t rows = d == 3 ? int64_t(n) * n : int64_t(n);
+  const int nb = int(rows < L1_BLOCKS ? rows : L1_BLOCKS);
+  if (e)
+    hipExtLaunchKernelGGL((k_l1_partial<T, true>), dim3(nb), dim3(256), 0, s, g_ev_start, g_ev_stop, 0, uref, u,
+                          static_cast<const T*>(e) + el.off, el.pitch, el.plane, n, d, part);
+  else
+    hipExtLaunchKernelGGL((k_l1_partial<T, false>), dim3(nb), dim3(256), 0, s, g_ev_start, g_ev_stop, 0, uref,
+                          u, static_cast<const T*>(nullptr), int64_t(0), int64_t(0), n, d, part);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  HOMG_LAUNCH(k_l1_finish, dim3(1), dim3(256), s, part, nb, out);
+}
+
+int l1_partials() { return 2 * L1_BLOCKS; }
+
+hipError_t launch_l1(int prec, int d, int n, const double* uref, const double* u, const void* e,
+                     const Lay& el, double* part, double* out, hipStream_t s) {
+  switch (prec) {
+    case PREC_F64: return l1_t<double>(d, n, uref, u, e, el, part, out, s);
+    case PREC_F32: return l1_t<float>(d, n, uref, u, e, el, part, out, s);
+    default: return l1_t<bf16>(d, n, uref, u, e, el, part, out, s);
   }
 }
 

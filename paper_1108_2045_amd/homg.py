@@ -110,6 +110,8 @@ def load_library(path=LIB_PATH):
                                   ctypes.POINTER(ctypes.c_double), vp]
     L.homg_learn_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, vp, vp]
+    L.homg_l1_error.argtypes = [H, dp, dp, ctypes.POINTER(ctypes.c_double), vp]
+    L.homg_trace_cycle.argtypes = [H, dp, dp, dp, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ip, vp]
     L.homg_residual_noalloc.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp,
                                         ctypes.POINTER(ctypes.c_double), vp]
     L.homg_last_error.argtypes = [H]
@@ -124,7 +126,8 @@ def load_library(path=LIB_PATH):
                  "homg_batch_destroy", "homg_set_smoother", "homg_get_smoother_weights",
                  "homg_smoother_gate", "homg_trainer_create", "homg_trainer_add_problem",
                  "homg_trainer_count", "homg_trainer_train", "homg_trainer_loss", "homg_trainer_destroy",
-                 "homg_learn_forward", "homg_learn_grad", "homg_learn_adam", "homg_residual_noalloc"):
+                 "homg_learn_forward", "homg_learn_grad", "homg_learn_adam", "homg_residual_noalloc",
+                 "homg_l1_error", "homg_trace_cycle"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -265,6 +268,27 @@ class Solver:
         rel = ctypes.c_double()
         self._check(lib().homg_residual(self._h, _ptr(f), _ptr(u), _ptr(r), ctypes.byref(rel), _stream(stream)))
         return rel.value
+
+    def l1_error(self, u_ref, v, stream=None):
+        """Normalised L1 error sum|u_ref - v| / sum|u_ref| (Sec. 4), computed on the GPU."""
+        _shape(u_ref, self._grid(), "u_ref")
+        _shape(v, self._grid(), "v")
+        err = ctypes.c_double()
+        self._check(lib().homg_l1_error(self._h, _ptr(u_ref), _ptr(v), ctypes.byref(err), _stream(stream)))
+        return err.value
+
+    def trace_cycle(self, f, u, u_ref, stream=None):
+        """One MFMG cycle from e = 0, one whole-grid iteration at a time: the
+        normalised L1 error of u + e after every iteration (one WU each); u
+        receives u + e at the end."""
+        for t, what in ((f, "f"), (u, "u"), (u_ref, "u_ref")):
+            _shape(t, self._grid(), what)
+        cap = sum(it for _, it in self.schedule())
+        buf = (ctypes.c_double * max(cap, 1))()
+        cnt = ctypes.c_int()
+        self._check(lib().homg_trace_cycle(self._h, _ptr(f), _ptr(u), _ptr(u_ref), buf, cap, ctypes.byref(cnt),
+                                           _stream(stream)))
+        return list(buf[:cnt.value])
 
     def schedule(self):
         n = ctypes.c_int()
