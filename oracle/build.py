@@ -10,6 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "homg_oracle.c")
+SRC_POW2 = os.path.join(HERE, "pow2_oracle.c")  # the power-of-two layout of Sec. 3
 LIB = os.path.join(HERE, "liboracle.so")
 
 
@@ -17,7 +18,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           SRC, "-o", tmp, "-lm"]
+           SRC, SRC_POW2, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
