@@ -367,14 +367,43 @@ def paper_section(P, W, torch, dev, sizes=(65, 129, 257, 513, 1025)):
     fig4 = R.fig4(probs)
     f129, u129 = next((f, u) for n, f, u in probs if n == 129)
     search = R.search(f129, u129)
+    # the paper's 128^2 grid in the power-of-two layout of Sec. 3
+    f128, u128 = (torch.from_numpy(a).to(dev) for a in W.poly2d(128))
+    fig4_pow2 = R.fig4([(128, f128, u128)], max_is=(2, 4, 32), grid_layout="pow2")
+    search_pow2 = R.search(f128, u128, grid_layout="pow2")
     out = {"problem": "2D Poisson, polynomial source of Sec. 4 (negated for -Laplace), zero Dirichlet, "
                       "one MFMG cycle from u = 0, FP64, omega 4/5",
-           "fig4": fig4, "search_129": search,
+           "fig4": fig4, "search_129": search, "fig4_pow2_128": fig4_pow2, "search_pow2_128": search_pow2,
            "paper_values": {"iterations_128sq_maxi2": 31, "l1_maxi4": 0.05, "l1_maxi32": 0.016,
                             "status": "parity unpinned (Fig. 1 schedule missing)"},
            "seconds": time.perf_counter() - t0}
     log("paper runs: %s" % json.dumps({"fig4": [(r["n"], r["max_i"], r["wu"], round(r["l1"], 4)) for r in fig4]}))
     return out
+
+
+def pow2_section(P, W, torch, dev, reps=3):
+    """The power-of-two grid strategy of Sec. 3 on the bench workload's 2D
+    size: 4096^2 (power of two) against 4097^2 (nested), FP64, f ~ U[-1,1]
+    seed 0, time to 1e-10 (median of `reps` after one warm-up)."""
+    out = {}
+    for name, n, layout in (("pow2_4096", 4096, "pow2"), ("nested_4097", 4097, "nested")):
+        f = torch.from_numpy(W.uniform(2, n, seed=0)).to(dev)
+        s = P.Solver(2, n, grid_layout=layout)
+        u = torch.zeros_like(f)
+        times, res = [], None
+        for _ in range(reps + 1):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = s.solve(f, u, tol=1e-10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[name] = {"time_to_1e-10_s": sorted(times[1:])[len(times[1:]) // 2], "cycles": res["cycles"],
+                     "final_relres": res["final_relres"], "sweeps_per_cycle": sum(it for _, it in s.schedule())}
+        s.close()
+    log("pow2: %s" % out)
+    return {"workload": "2D Poisson FP64, f ~ U[-1,1] seed 0, MaxI 4: power-of-two layout (Sec. 3) "
+                        "against the nested grid of the same size", "results": out}
 
 
 def main():
@@ -389,6 +418,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-problem batched solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother training and timing")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 4 reproduction runs")
+    ap.add_argument("--no-pow2", action="store_true", help="skip the power-of-two layout timing")
     ap.add_argument("--no-level-blocked", action="store_true",
                     help="skip the level-blocked comparison solves (profiling runs of the default path)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -520,6 +550,9 @@ def main():
     paper = None
     if not args.no_paper:
         paper = paper_section(P, W, torch, dev)
+    pow2 = None
+    if not args.no_pow2:
+        pow2 = pow2_section(P, W, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -535,7 +568,7 @@ def main():
                       "problems": per, "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:10],
            "mixed_precision": mixed, "batched": batched, "learned_smoother": learned,
-           "paper_reproduction": paper}
+           "paper_reproduction": paper, "pow2_grid": pow2}
     print(json.dumps(out), flush=True)
 
 

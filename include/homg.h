@@ -92,8 +92,22 @@ typedef struct homg_options {
                               With 1 or 2, several iterations of a Laplacian (2D: four, 3D: two)
                               run in one pass at level 0 and on large lattices.  All three give
                               the same results bit for bit. */
-    int reserved[7];       /* must be 0 */
+    int grid_layout;       /* HOMG_GRID_NESTED (0): n = 2^k + 1 nodes per side, nested level
+                              lattices (Sec. 2).  HOMG_GRID_POW2 (1): the power-of-two strategy of
+                              Sec. 3 -- 2D Laplacian, FP64, n = 2^k (k >= 2) nodes per side, node
+                              (j,i) at (i h, j h) with h = 1/(n-1); four quadrants whose level-m
+                              marks are measured from each quadrant's external corner up to the
+                              points just outside it (index n/2 or n/2 - 1), every mark relaxing
+                              with its quadrant's own restricted residual (one nested restriction
+                              sequence per quadrant, anchored at its corner), every other node
+                              interpolating bilinearly from its own quadrant's marks only.  Every
+                              level-m >= 1 iteration is one whole-grid launch; level 0 runs as on
+                              nested grids.  The batched, learned, step-restrict/step-sweeps and
+                              variable-coefficient paths are nested-only (HOMG_ERR_UNSUPPORTED). */
+    int reserved[6];       /* must be 0 */
 } homg_options;
+
+enum { HOMG_GRID_NESTED = 0, HOMG_GRID_POW2 = 1 };
 
 typedef struct homg_info {
     int cycles;            /* MFMG cycles executed */
@@ -114,8 +128,9 @@ void homg_options_init(homg_options *opt);
 
 /*
  * Create a solver for one grid.  ndim in {2,3}; dims[0..ndim-1] all equal to
- * n = 2^k + 1 with k >= 1; levels in [1, k] (0 selects k, so the coarsest
- * lattice is 3^d with one interior unknown); stencil must match ndim.  opt
+ * n = 2^k + 1 with k >= 1 (power-of-two layout: n = 2^k, k >= 2); levels in
+ * [1, k] (0 selects k, so the coarsest lattice is 3^d with one interior
+ * unknown -- one per quadrant in the power-of-two layout); stencil must match ndim.  opt
  * may be NULL (defaults).  Allocates all device workspace on the current
  * device (padded internal copies of e and the residual pyramid); *out is set
  * only on success.

@@ -104,6 +104,11 @@ struct homg_ctx {
   double* r64 = nullptr;
   double* x64[2] = {nullptr, nullptr};
   Lay l64;
+  // power-of-two layout (Sec. 3): the quadrants' restriction families,
+  // level m >= 1 of quadrant q at fam[4 m + q], layout faml[m]
+  bool pow2 = false;
+  std::vector<double*> fam;
+  std::vector<Lay> faml;
   // L1 error (Sec. 4): partial sums and per-iteration results (allocated on first use)
   double* l1part = nullptr;
   double* l1out = nullptr;
@@ -207,6 +212,7 @@ void free_ctx(homg_ctx* h) {
   for (double* p : h->a) (void)hipFree(p);
   for (void* p : h->xc) (void)hipFree(p);
   for (void* p : h->xp3) (void)hipFree(p);
+  for (double* p : h->fam) (void)hipFree(p);
   (void)hipFree(h->partials);
   (void)hipFree(h->st);
   (void)hipFree(h->hist);
@@ -260,7 +266,7 @@ bool top64(const homg_ctx* h) {
 // 16 us at 33^3: at these sizes the pass is latency-bound and the extra
 // loads sit on its critical path).
 bool lat_target(const homg_ctx* h, int mt) {
-  if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || mt < 0) return false;
+  if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || mt < 0 || h->pow2) return false;
   if (top64(h) && mt == h->top_level) return false;  // starts from an FP64 x_0
   const int nm = (h->n - 1) / (1 << mt) + 1;
   if (nm < 5 || mt + 1 >= h->levels) return false;
@@ -323,6 +329,21 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
                       double* acc, const int* done, hipStream_t s) {
   if (h->active_smoother == 1) return run_level_learned(h, m, it, first, last, next_m, cur, acc, done, s);
   if (top64(h) && m == h->top_level) return run_top64(h, m, it, first, last, next_m, cur, acc, done, s);
+  if (h->pow2 && m >= 1) {
+    // power-of-two layout: one whole-grid launch per iteration
+    const double* fm[4] = {h->fam[4 * m], h->fam[4 * m + 1], h->fam[4 * m + 2], h->fam[4 * m + 3]};
+    for (int t = 0; t < it; ++t) {
+      int mode = 0;
+      if (first && t == 0) mode |= SW_ZERO_OLD;
+      if (last && t == it - 1) mode |= SW_ACCUM;
+      LAUNCH_K(h, s, K_SWEEP, m, mode | 256,
+               launch_p2_sweep(h->n, m, h->omega, static_cast<const double*>(h->e[*cur]),
+                               static_cast<double*>(h->e[1 - *cur]), h->el, fm, h->faml[m], acc, h->dl, mode,
+                               done, s));
+      *cur = 1 - *cur;
+    }
+    return HOMG_OK;
+  }
   const Lay none;
   const double* am = h->has_coef ? h->a[m] : nullptr;
   const Lay& alm = am ? h->al[m] : none;
@@ -531,7 +552,7 @@ homg_status run_level_learned(homg_ctx* h, int m, int it, bool first, bool last,
 // damped Jacobi).
 int tail_levels(const homg_ctx* h, int* ms) {
   const int np = int(h->sched.size() / 2);
-  if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || np < 3) return 0;
+  if (h->temporal != 2 || h->active_smoother != 0 || h->has_coef || np < 3 || h->pow2) return 0;
   if (h->sched[0] != h->top_level) return 0;
   int cnt = 0;
   for (int p = 0; p + 1 < np; ++p) {
@@ -562,12 +583,21 @@ int tail_levels(const homg_ctx* h, int* ms) {
 // (2D Laplacian whose schedule visits a coarse level).
 bool residual_restricts(const homg_ctx* h) {
   // (an FP64 coarsest level 1 takes its restriction from the separate kernel)
-  return h->d == 2 && !h->has_coef && h->top_level >= 1 && h->n >= 5 && !(top64(h) && h->top_level == 1);
+  return h->d == 2 && !h->has_coef && h->top_level >= 1 && h->n >= 5 && !(top64(h) && h->top_level == 1) &&
+         !h->pow2;
 }
 
 // One restriction of the cycle's pyramid, m -> m + 1 (in FP64 onto an FP64
 // coarsest level).
 homg_status enqueue_restrict(homg_ctx* h, int m, const int* done, hipStream_t s) {
+  if (h->pow2) {  // one restriction per quadrant family
+    for (int q = 0; q < 4; ++q)
+      LAUNCH_K(h, s, K_RESTRICT, m, 2,
+               launch_p2_restrict(m == 0 ? static_cast<const double*>(h->r[0]) : h->fam[4 * m + q],
+                                  m == 0 ? h->rl[0] : h->faml[m], m == 0, h->n, q & 1, q >> 1,
+                                  h->fam[4 * (m + 1) + q], h->faml[m + 1], done, s));
+    return HOMG_OK;
+  }
   if (top64(h) && m + 1 == h->top_level) {
     LAUNCH_K(h, s, K_RESTRICT, m, 1,
              launch_restrict_to_f64(h->prec, h->d, h->r[m], h->rl[m], h->r64, h->l64, done, s));
@@ -769,6 +799,7 @@ void ctx_view(const homg_ctx* h, CtxView* v) {
   v->prec = h->prec;
   v->has_coef = h->has_coef ? 1 : 0;
   v->smoother = h->smoother;
+  v->pow2 = h->pow2 ? 1 : 0;
   v->fallback_ratio = h->fallback_ratio;
   v->sched = h->sched;
 }
@@ -801,7 +832,21 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   if (!dims) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null dims");
   for (int i = 1; i < ndim; ++i)
     if (dims[i] != dims[0]) return fail(nullptr, HOMG_ERR_UNSUPPORTED, "all sides must be equal");
-  const int k = side_exponent(dims[0]);
+  const bool pow2 = opt && opt->struct_size == sizeof(homg_options) && opt->grid_layout == HOMG_GRID_POW2;
+  if (opt && opt->struct_size == sizeof(homg_options) && opt->grid_layout != HOMG_GRID_NESTED && !pow2)
+    return fail(nullptr, HOMG_ERR_INVALID_ARG, "unknown grid_layout");
+  int k = side_exponent(dims[0]);
+  if (pow2) {
+    k = -1;
+    if (dims[0] >= 4 && (dims[0] & (dims[0] - 1)) == 0)
+      for (k = 0; (int64_t(1) << k) < dims[0]; ++k) {
+      }
+    if (k < 2) return fail(nullptr, HOMG_ERR_INVALID_ARG, "power-of-two layout: side must be 2^k with k >= 2");
+    if (ndim != 2 || stencil != HOMG_LAPLACE_5PT_2D)
+      return fail(nullptr, HOMG_ERR_UNSUPPORTED, "power-of-two layout: 2D Laplacian only");
+    if (opt->precision != HOMG_FP64)
+      return fail(nullptr, HOMG_ERR_UNSUPPORTED, "power-of-two layout: FP64 only");
+  }
   if (k < 1) return fail(nullptr, HOMG_ERR_INVALID_ARG, "side must be 2^k + 1 with k >= 1");
   if ((ndim == 2 && k > 15) || (ndim == 3 && k > 10))
     return fail(nullptr, HOMG_ERR_UNSUPPORTED, "grid too large");
@@ -821,7 +866,7 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
     if (opt->struct_size != sizeof(homg_options))
       return fail(nullptr, HOMG_ERR_INVALID_ARG, "homg_options.struct_size mismatch");
     o = *opt;
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
       if (o.reserved[i] != 0) return fail(nullptr, HOMG_ERR_INVALID_ARG, "reserved options must be 0");
   }
   double omega = o.omega > 0 ? o.omega : (ndim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
@@ -868,6 +913,7 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   h->max_i = max_i;
   h->max_cycles = max_cycles;
   h->temporal = o.temporal_block;
+  h->pow2 = pow2;
   h->sched = sched;
   h->top_level = 0;
   h->total_sweeps = 0;
@@ -883,7 +929,7 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   h->dl = dense_layout(ndim, h->n);
   h->el = padded_layout(ndim, h->n, eb);
   for (int m = 0; m < levels; ++m) {
-    const int side = (h->n - 1) / (1 << m) + 1;
+    const int side = pow2 ? (m == 0 ? h->n : h->n >> m) : (h->n - 1) / (1 << m) + 1;
     h->rl.push_back(padded_layout(ndim, side, eb));
     h->al.push_back(padded_layout(ndim, side, 8));
     h->cdl.push_back(dense_layout(ndim, side));
@@ -891,8 +937,16 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   homg_status stt = HOMG_OK;
   for (int b = 0; b < 2 && !stt; ++b) stt = dev_alloc(h, &h->e[b], size_t(h->el.alloc) * eb);
   h->r.assign(levels, nullptr);
-  for (int m = 0; m < levels && !stt; ++m) stt = dev_alloc(h, &h->r[m], size_t(h->rl[m].alloc) * eb);
-  if (h->temporal) {
+  for (int m = 0; m < (pow2 ? 1 : levels) && !stt; ++m) stt = dev_alloc(h, &h->r[m], size_t(h->rl[m].alloc) * eb);
+  if (pow2) {
+    // four restriction families, levels 1 .. levels-1 (side n >> m)
+    h->fam.assign(4 * levels, nullptr);
+    h->faml = h->rl;
+    for (int m = 1; m < levels && !stt; ++m)
+      for (int q = 0; q < 4 && !stt; ++q)
+        stt = dev_alloc(h, reinterpret_cast<void**>(&h->fam[4 * m + q]), sizeof(double) * size_t(h->faml[m].alloc));
+  }
+  if (h->temporal && !pow2) {
     h->xc.assign(2 * levels, nullptr);
     for (int m = 1; m < levels && !stt; ++m)
       for (int b = 0; b < 2 && !stt; ++b)
@@ -934,7 +988,11 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   ok = ok && hipMemset(h->e[0], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
        hipMemset(h->e[1], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
        hipMemset(h->zero_flag, 0, sizeof(int) * 64) == hipSuccess;
-  for (int m = 0; m < levels && ok; ++m) ok = hipMemset(h->r[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  for (int m = 0; m < levels && ok; ++m)
+    if (h->r[m]) ok = hipMemset(h->r[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  for (int m = 1; m < int(h->fam.size()) / 4 && ok; ++m)
+    for (int q = 0; q < 4 && ok; ++q)
+      ok = hipMemset(h->fam[4 * m + q], 0, sizeof(double) * size_t(h->faml[m].alloc)) == hipSuccess;
   // compact lattices: boundary nodes are read as 0 and never written
   for (size_t m = 1; 2 * m + 1 < h->xc.size() && ok; ++m)
     for (int b = 0; b < 2 && ok; ++b)
@@ -1044,6 +1102,7 @@ homg_status homg_step_restrict(homg_handle h, int level, const double* r_fine, d
   if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
   if (!r_fine || !r_coarse) return fail(h, HOMG_ERR_INVALID_ARG, "null array");
   if (level < 0 || level >= h->levels - 1) return fail(h, HOMG_ERR_INVALID_ARG, "level out of range");
+  if (h->pow2) return fail(h, HOMG_ERR_UNSUPPORTED, "step_restrict: nested grids only");
   DeviceGuard guard(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   h->active_smoother = h->smoother;
@@ -1065,6 +1124,7 @@ homg_status homg_step_sweeps(homg_handle h, int level, int iters, const double* 
   if (!e_old || !r_level || !e_new) return fail(h, HOMG_ERR_INVALID_ARG, "null array");
   if (level < 0 || level >= h->levels) return fail(h, HOMG_ERR_INVALID_ARG, "level out of range");
   if (iters < 1) return fail(h, HOMG_ERR_INVALID_ARG, "iters must be >= 1");
+  if (h->pow2) return fail(h, HOMG_ERR_UNSUPPORTED, "step_sweeps: nested grids only");
   if (homg_status c = check_ready(h)) return c;
   DeviceGuard guard(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1132,8 +1192,8 @@ homg_status homg_set_smoother(homg_handle h, int smoother, const float* w, doubl
   if (!h) return fail(nullptr, HOMG_ERR_INVALID_ARG, "null handle");
   if (smoother != HOMG_SMOOTHER_JACOBI && smoother != HOMG_SMOOTHER_LEARNED)
     return fail(h, HOMG_ERR_INVALID_ARG, "unknown smoother");
-  if (smoother == HOMG_SMOOTHER_LEARNED && h->d != 2)
-    return fail(h, HOMG_ERR_UNSUPPORTED, "the learned smoother is 2D only");
+  if (smoother == HOMG_SMOOTHER_LEARNED && (h->d != 2 || h->pow2))
+    return fail(h, HOMG_ERR_UNSUPPORTED, "the learned smoother is 2D only, on nested grids");
   if (smoother == HOMG_SMOOTHER_LEARNED && !w && !h->w32)
     return fail(h, HOMG_ERR_INVALID_ARG, "the learned smoother needs weights");
   DeviceGuard guard(h->device);

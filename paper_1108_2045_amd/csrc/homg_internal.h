@@ -207,6 +207,19 @@ hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, 
 hipError_t launch_level_transfer(int prec, int d, int m, const void* xprev, const void* xcur,
                                  const Lay& cl, int mt, void* dst, const Lay& tl, bool zero_old,
                                  const int* done, hipStream_t s);
+// ---- power-of-two grids (Sec. 3; 2D Laplacian, FP64), N = 2^k nodes per side
+// Family restriction of quadrant (sx, sy): level 1 from the whole-grid r_0
+// (from_r0; F in layout fl of side N, read from that quadrant's corner) or
+// level j from level j - 1 (compact, side 2 * cl.side).
+hipError_t launch_p2_restrict(const double* F, const Lay& fl, bool from_r0, int N, int sx, int sy, double* C,
+                              const Lay& cl, const int* done, hipStream_t s);
+// One whole-grid iteration at level m >= 1; fam[q] (q = 2 sy + sx) is the
+// level-m family array of quadrant q (layout fl, side N >> m); mode: SW_ZERO_OLD
+// / SW_ACCUM (add into u, layout ul, instead of storing en).
+hipError_t launch_p2_sweep(int N, int m, double omega, const double* eo, double* en, const Lay& el,
+                           const double* const* fam, const Lay& fl, double* u, const Lay& ul, int mode,
+                           const int* done, hipStream_t s);
+
 // ---- batched solver (2D, constant coefficient): graph-replayed step launches
 constexpr int BATCH_MAX_LEVELS = 16;
 // Iteration stages of a batched cycle, one int each in the schedule table:
@@ -332,7 +345,7 @@ hipError_t launch_add_dense(double* v, const double* e, int64_t count, hipStream
 
 // What the trainer needs to know about a solver handle.
 struct CtxView {
-  int d = 0, n = 0, levels = 0, stencil = 0, prec = 0, has_coef = 0, smoother = 0;
+  int d = 0, n = 0, levels = 0, stencil = 0, prec = 0, has_coef = 0, smoother = 0, pow2 = 0;
   double fallback_ratio = 1.0;
   std::vector<int> sched;  // (level, iterations) pairs
 };

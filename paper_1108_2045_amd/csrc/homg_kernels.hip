@@ -517,6 +517,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const double* __restrict__ 
 // workgroup adds them in a fixed order -- the result does not depend on
 // timing.
 constexpr int L1_BLOCKS = 1024;
+constexpr int P2_ROWS = 8;  // rows walked per block by the power-of-two sweep
 
 template <typename T, bool HAS_E>
 __global__ __launch_bounds__(256) void k_l1_partial(const double* __restrict__ uref, const double* __restrict__ u,
@@ -2818,6 +2819,138 @@ hipError_t launch_level_write(int prec, int d, int n, int m, const void* xprev, 
     case PREC_F32: return level_write_t<float>(d, n, m, xprev, xcur, cl, en, el, u, ul, mode, done, s);
     default: return level_write_t<bf16>(d, n, m, xprev, xcur, cl, en, el, u, ul, mode, done, s);
   }
+}
+
+// ------------------------------------------------------------ power-of-two grids
+// Sec. 3: a 2D grid of N = 2^k nodes per side in four quadrants.  Level-m
+// marks of quadrant (sx, sy) are the nodes whose coordinates, measured from
+// the quadrant's external corner (index 0 on side 0, N-1 on side 1), are
+// multiples of l = 2^m no larger than N/2 -- the last one just outside the
+// quadrant.  Every interior mark relaxes (5-point stencil at distance l on
+// the whole grid, a neighbour outside the grid reads 0) with its quadrant's
+// restricted residual; every other interior node interpolates bilinearly
+// from the marks of the quadrant that owns it (no cross-quadrant reads).
+// The marks of side 0 are even and those of side 1 odd on every axis, so
+// each node has at most one owner lattice.  Each quadrant's residuals form
+// a nested sequence anchored at its corner ("family"): level j is the full
+// weighting of level j-1 on compact arrays of side N >> j whose index 0 (the
+// domain boundary) stays 0.
+
+// Mark side (0 or 1) of coordinate x at stride l = 2^m, or -1.
+__device__ __forceinline__ int p2_side(int x, int N, int m) {
+  const int mask = (1 << m) - 1, half = N >> 1;
+  if ((x & mask) == 0 && x <= half) return 0;
+  const int a = N - 1 - x;
+  if ((a & mask) == 0 && a <= half) return 1;
+  return -1;
+}
+
+// One iteration at level m >= 1 over the whole grid.  fam[q] points at node
+// (0, 0) of family q's level-m array (pitch fp).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_p2_sweep(const double* __restrict__ eo, double* __restrict__ en,
+                                                  int64_t ep, const double* __restrict__ f0,
+                                                  const double* __restrict__ f1, const double* __restrict__ f2,
+                                                  const double* __restrict__ f3, int64_t fp, int N, int m,
+                                                  double w, double hl2, double* __restrict__ u, int64_t up,
+                                                  const int* __restrict__ done) {
+  if (*done) return;
+  const int x = 1 + blockIdx.x * 256 + threadIdx.x;
+  if (x > N - 2) return;
+  const int l = 1 << m, half = N >> 1;
+  const int sx = p2_side(x, N, m);
+  const int tx = x >= half ? 1 : 0;
+  const int ax = tx ? N - 1 - x : x, cx = (ax >> m) << m;
+  const int gx0 = tx ? N - 1 - cx : cx, gx1 = tx ? N - 1 - (cx + l) : cx + l;
+  const double fx = double(ax - cx) / double(l);
+  const int y0 = 1 + blockIdx.y * P2_ROWS, y1 = min(N - 1, y0 + P2_ROWS);
+  for (int y = y0; y < y1; ++y) {
+    const int sy = p2_side(y, N, m);
+    double v;
+    if (sx >= 0 && sy >= 0) {
+      const double* fam = sy ? (sx ? f3 : f2) : (sx ? f1 : f0);
+      const int a = sx ? N - 1 - x : x, b = sy ? N - 1 - y : y;
+      const double rv = fam[int64_t(b >> m) * fp + (a >> m)];
+      double c = 0.0, q = 0.0;
+      if (!(MODE & SW_ZERO_OLD)) {
+        const double* row = eo + int64_t(y) * ep;
+        c = row[x];
+        const double xm = x - l >= 0 ? row[x - l] : 0.0;
+        const double xp = x + l <= N - 1 ? row[x + l] : 0.0;
+        const double ym = y - l >= 0 ? eo[int64_t(y - l) * ep + x] : 0.0;
+        const double yp = y + l <= N - 1 ? eo[int64_t(y + l) * ep + x] : 0.0;
+        q = (xm + xp) + (ym + yp);
+      }
+      v = relax_const<double>(c, q, rv, w, hl2, 4.0);
+    } else if (MODE & SW_ZERO_OLD) {
+      v = 0.0;
+    } else {
+      const int ty = y >= half ? 1 : 0;
+      const int ay = ty ? N - 1 - y : y, cy = (ay >> m) << m;
+      const int gy0 = ty ? N - 1 - cy : cy, gy1 = ty ? N - 1 - (cy + l) : cy + l;
+      const double fy = double(ay - cy) / double(l);
+      const double* r0 = eo + int64_t(gy0) * ep;
+      const double* r1 = eo + int64_t(gy1) * ep;
+      v = lerp(lerp(r0[gx0], r0[gx1], fx), lerp(r1[gx0], r1[gx1], fx), fy);
+    }
+    if (MODE & SW_ACCUM)
+      add_to(u + int64_t(y) * up + x, v);
+    else
+      st_w(en + int64_t(y) * ep + x, v);
+  }
+}
+
+// Family level j from level j-1 (compact, pitch fp), or -- from_r0 -- level 1
+// from the whole-grid r_0 (pitch fp) seen from the corner (sx, sy).
+__global__ __launch_bounds__(256) void k_p2_restrict(const double* __restrict__ F, int64_t fp,
+                                                     double* __restrict__ Cc, int64_t cp, int nc, int N,
+                                                     int sx, int sy, int from_r0, const int* __restrict__ done) {
+  if (*done) return;
+  const int A = blockIdx.x * 256 + threadIdx.x, B = blockIdx.y;
+  if (A >= nc) return;
+  if (A == 0 || B == 0) {
+    Cc[int64_t(B) * cp + A] = 0.0;
+    return;
+  }
+  auto at = [&](int b, int a) {
+    if (from_r0) {
+      const int gx = sx ? N - 1 - a : a, gy = sy ? N - 1 - b : b;
+      return F[int64_t(gy) * fp + gx];
+    }
+    return F[int64_t(b) * fp + a];
+  };
+  auto rs = [&](int b) { return fmac(2.0, at(b, 2 * A), at(b, 2 * A - 1) + at(b, 2 * A + 1)); };
+  const double top = rs(2 * B - 1), mid = rs(2 * B), bot = rs(2 * B + 1);
+  Cc[int64_t(B) * cp + A] = fmac(2.0, mid, top + bot) * 0.0625;
+}
+
+hipError_t launch_p2_restrict(const double* F, const Lay& fl, bool from_r0, int N, int sx, int sy, double* C,
+                              const Lay& cl, const int* done, hipStream_t s) {
+  const int nc = cl.side;
+  HOMG_LAUNCH(k_p2_restrict, dim3((nc + 255) / 256, nc), dim3(256), s, F + fl.off, fl.pitch, C + cl.off,
+              cl.pitch, nc, N, sx, sy, from_r0 ? 1 : 0, done);
+}
+
+hipError_t launch_p2_sweep(int N, int m, double omega, const double* eo, double* en, const Lay& el,
+                           const double* const* fam, const Lay& fl, double* u, const Lay& ul, int mode,
+                           const int* done, hipStream_t s) {
+  if (m < 1 || N < 4 || (N & (N - 1)) || fl.side != (N >> m)) return hipErrorInvalidValue;
+  const double hl = double(1 << m) / double(N - 1);
+  const dim3 g((N - 2 + 255) / 256, (N - 2 + P2_ROWS - 1) / P2_ROWS);
+  const double* e = eo + el.off;
+  double* o = en + el.off;
+  double* uu = u ? u + ul.off : nullptr;
+  const double *f0 = fam[0] + fl.off, *f1 = fam[1] + fl.off, *f2 = fam[2] + fl.off, *f3 = fam[3] + fl.off;
+#define P2_CASE(MODE)                                                                                       \
+  HOMG_LAUNCH((k_p2_sweep<MODE>), g, dim3(256), s, e, o, el.pitch, f0, f1, f2, f3, fl.pitch, N, m, omega / 4.0, \
+              hl * hl, uu, ul.pitch, done)
+  switch (mode & (SW_ZERO_OLD | SW_ACCUM)) {
+    case 0: P2_CASE(0);
+    case SW_ZERO_OLD: P2_CASE(SW_ZERO_OLD);
+    case SW_ACCUM: P2_CASE(SW_ACCUM);
+    default: P2_CASE(SW_ZERO_OLD | SW_ACCUM);
+  }
+#undef P2_CASE
 }
 
 // ------------------------------------------------------------ batched solver

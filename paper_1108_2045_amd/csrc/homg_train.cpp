@@ -137,7 +137,7 @@ homg_status homg_trainer_add_problem(homg_trainer t, homg_handle h, const double
   if (cycles < 1 || cycles > 64) return tfail(t, HOMG_ERR_INVALID_ARG, "cycles must be in [1, 64]");
   CtxView v;
   ctx_view(h, &v);
-  if (v.d != 2) return tfail(t, HOMG_ERR_UNSUPPORTED, "training needs a 2D handle");
+  if (v.d != 2 || v.pow2) return tfail(t, HOMG_ERR_UNSUPPORTED, "training needs a 2D handle on a nested grid");
   const bool var = v.stencil == HOMG_DIFFUSION_5PT_2D;
   if (var && !v.has_coef) return tfail(t, HOMG_ERR_INVALID_ARG, "set the coefficient first");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -18,6 +18,7 @@ STATUS_NAMES = {
 }
 LAPLACE_5PT_2D, LAPLACE_7PT_3D, DIFFUSION_5PT_2D = 0, 1, 2
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+GRID_LAYOUTS = {"nested": 0, "pow2": 1}
 
 
 class HomgError(RuntimeError):
@@ -31,7 +32,7 @@ class Options(ctypes.Structure):
                 ("max_i", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("schedule", ctypes.POINTER(ctypes.c_int)), ("schedule_len", ctypes.c_int),
                 ("precision", ctypes.c_int), ("temporal_block", ctypes.c_int),
-                ("reserved", ctypes.c_int * 7)]
+                ("grid_layout", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
 
 
 class Info(ctypes.Structure):
@@ -176,7 +177,7 @@ class Solver:
     """One HOMG solver for a d-dimensional grid of side n = 2^k + 1."""
 
     def __init__(self, ndim, n, levels=0, stencil=None, omega=0.0, max_i=4, max_cycles=200,
-                 schedule=None, precision="fp64", temporal_block=2):
+                 schedule=None, precision="fp64", temporal_block=2, grid_layout="nested"):
         L = lib()
         if stencil is None:
             stencil = LAPLACE_5PT_2D if ndim == 2 else LAPLACE_7PT_3D
@@ -187,6 +188,7 @@ class Solver:
         opt.max_cycles = max_cycles
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         opt.temporal_block = temporal_block
+        opt.grid_layout = GRID_LAYOUTS[grid_layout] if isinstance(grid_layout, str) else int(grid_layout)
         self._sched_buf = None
         if schedule is not None:
             flat = [int(v) for pair in schedule for v in pair]
@@ -201,6 +203,7 @@ class Solver:
         self._h = h
         self.ndim, self.n, self.max_cycles = ndim, n, max_cycles
         self.precision = precision
+        self.pow2 = opt.grid_layout == GRID_LAYOUTS["pow2"]
 
     def _check(self, st):
         if st != HOMG_OK:
@@ -221,6 +224,8 @@ class Solver:
         return ((self.n - 1) // (1 << level) + 1,) * self.ndim
 
     def _level(self, level):
+        if getattr(self, "pow2", False):
+            return  # the library refuses the nested-only step entry points
         side = (self.n - 1) // (1 << level) + 1 if level >= 0 else 0
         if level < 0 or side < 3 or (side - 1) << level != self.n - 1:
             raise ValueError("level %d out of range for side %d" % (level, self.n))
@@ -312,14 +317,16 @@ class Solver:
     def step_restrict(self, level, r_fine, r_coarse, stream=None):
         self._level(level)
         self._level(level + 1)
-        _shape(r_fine, self._grid(level), "r_fine")
-        _shape(r_coarse, self._grid(level + 1), "r_coarse")
+        if not getattr(self, "pow2", False):
+            _shape(r_fine, self._grid(level), "r_fine")
+            _shape(r_coarse, self._grid(level + 1), "r_coarse")
         self._check(lib().homg_step_restrict(self._h, level, _ptr(r_fine), _ptr(r_coarse), _stream(stream)))
 
     def step_sweeps(self, level, iters, e_old, r_level, e_new, stream=None):
         self._level(level)
         _shape(e_old, self._grid(), "e_old")
-        _shape(r_level, self._grid(level), "r_level")
+        if not getattr(self, "pow2", False):
+            _shape(r_level, self._grid(level), "r_level")
         _shape(e_new, self._grid(), "e_new")
         self._check(lib().homg_step_sweeps(self._h, level, iters, _ptr(e_old), _ptr(r_level),
                                            _ptr(e_new), _stream(stream)))

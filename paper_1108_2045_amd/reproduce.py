@@ -67,11 +67,11 @@ def candidate_schedules(M, max_i):
     return out
 
 
-def one_cycle_l1(f, u_ref, schedule=None, max_i=4, levels=0):
+def one_cycle_l1(f, u_ref, schedule=None, max_i=4, levels=0, grid_layout="nested"):
     """Normalised L1 error after one MFMG cycle from u = 0 (FP64)."""
     import torch
     n, d = int(f.shape[0]), f.dim()
-    s = _h.Solver(d, n, levels=levels, max_i=max_i, schedule=schedule)
+    s = _h.Solver(d, n, levels=levels, max_i=max_i, schedule=schedule, grid_layout=grid_layout)
     u = torch.zeros_like(f)
     s.solve_cycles(f, u, 1)
     err = s.l1_error(u_ref, u)
@@ -80,12 +80,12 @@ def one_cycle_l1(f, u_ref, schedule=None, max_i=4, levels=0):
     return err, iters
 
 
-def trace(f, u_ref, max_i=4, schedule=None):
+def trace(f, u_ref, max_i=4, schedule=None, grid_layout="nested"):
     """L1 error after every iteration (WU) of one MFMG cycle from u = 0,
     with the level of each iteration."""
     import torch
     n, d = int(f.shape[0]), f.dim()
-    s = _h.Solver(d, n, max_i=max_i, schedule=schedule, temporal_block=0)
+    s = _h.Solver(d, n, max_i=max_i, schedule=schedule, temporal_block=0, grid_layout=grid_layout)
     u = torch.zeros_like(f)
     errs = s.trace_cycle(f, u, u_ref)
     levels = [m for m, it in s.schedule() for _ in range(it)]
@@ -93,31 +93,31 @@ def trace(f, u_ref, max_i=4, schedule=None):
     return errs, levels
 
 
-def fig4(problems, max_is=(4, 32)):
+def fig4(problems, max_is=(4, 32), grid_layout="nested"):
     """Fig. 4 runs: for each (n, f, u_ref) and MaxI, the one-cycle L1 error
     and the curve sampled at the end of every level visit as (WU, L1)."""
     runs = []
     for n, f, u_ref in problems:
         for max_i in max_is:
-            errs, levels = trace(f, u_ref, max_i=max_i)
+            errs, levels = trace(f, u_ref, max_i=max_i, grid_layout=grid_layout)
             pts = [(k + 1, errs[k]) for k in range(len(errs))
                    if k + 1 == len(errs) or levels[k + 1] != levels[k]]
-            runs.append({"n": n, "max_i": max_i, "wu": len(errs), "l1": errs[-1],
+            runs.append({"n": n, "layout": grid_layout, "max_i": max_i, "wu": len(errs), "l1": errs[-1],
                          "curve": [[w, round(e, 6)] for w, e in pts]})
     return runs
 
 
-def search(f, u_ref, max_is=(2, 4, 32), keep=4):
+def search(f, u_ref, max_is=(2, 4, 32), keep=4, grid_layout="nested"):
     """One-cycle L1 error and iteration count of every candidate level
     pattern, per MaxI; returns the MFMG entry, the best patterns by L1 and by
     L1 x WU, and the patterns with the paper's 31 iterations (MaxI 2)."""
     n = int(f.shape[0])
-    M = n.bit_length() - 2  # n = 2^k + 1, M = k - 1
+    M = n.bit_length() - 2  # n = 2^k + 1 (nested) or 2^k (power of two): M = k - 1
     res = {}
     for max_i in max_is:
         rows = []
         for name, sched in candidate_schedules(M, max_i):
-            err, iters = one_cycle_l1(f, u_ref, schedule=sched, max_i=max_i)
+            err, iters = one_cycle_l1(f, u_ref, schedule=sched, max_i=max_i, grid_layout=grid_layout)
             rows.append({"pattern": name, "wu": iters, "l1": err})
         rows.sort(key=lambda r: r["l1"])
         mfmg = next(r for r in rows if r["pattern"] == "c2-double-back0-x1")

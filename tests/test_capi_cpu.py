@@ -166,3 +166,25 @@ def test_batch_and_learned_calls_reject_wrong_shapes():
         B.learn_adam(w, w, _t(10, dtype=f32), _t(B.SMOOTHER_WEIGHTS), 1, 1e-3, w)
     with pytest.raises(ValueError):
         B.learn_forward(x, x, None, _t(575, dtype=f32), 0.1, x)
+
+
+@pytest.mark.parametrize("ndim,n,prec,stencil,status", [
+    (2, 129, 0, 0, 1),    # not a power of two
+    (2, 2, 0, 0, 1),      # too small
+    (3, 64, 0, 1, 2),     # 3D
+    (2, 64, 1, 0, 2),     # FP32
+    (2, 64, 0, 2, 2),     # diffusion stencil
+])
+def test_pow2_layout_rejects_unsupported(ndim, n, prec, stencil, status):
+    from paper_1108_2045_amd import homg as B
+    L = B.load_library()
+    opt = B.Options()
+    L.homg_options_init(ctypes.byref(opt))
+    opt.grid_layout = 1
+    opt.precision = prec
+    dims = (ctypes.c_int64 * 3)(n, n, n)
+    h = ctypes.c_void_p()
+    assert L.homg_create(ctypes.byref(h), ndim, dims, 0, stencil, ctypes.byref(opt)) == status
+    assert not h.value
+    opt.grid_layout = 7
+    assert L.homg_create(ctypes.byref(h), 2, dims, 0, 0, ctypes.byref(opt)) == 1
