@@ -406,6 +406,32 @@ def pow2_section(P, W, torch, dev, reps=3):
                         "against the nested grid of the same size", "results": out}
 
 
+def in_cycle_section(P, W, torch, dev, reps=3):
+    """Sec. 2's memory-saving restriction (inside the cycle, one extra
+    array) against the pyramid: device workspace and time to 1e-10 on the
+    3D 257^3 FP64 bench problem and the 3D 513^3 FP32 problem."""
+    out = {}
+    for name, n, prec, gen in (("3d_257_fp64", 257, "fp64", W.uniform), ("3d_513_fp32", 513, "fp32", W.normal)):
+        f = torch.from_numpy(gen(3, n, seed=0)).to(dev)
+        for mode in ("pyramid", "in_cycle"):
+            s = P.Solver(3, n, precision=prec, restriction=mode)
+            u = torch.zeros_like(f)
+            times, res = [], None
+            for _ in range(reps + 1):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = s.solve(f, u, tol=1e-10)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            out["%s_%s" % (name, mode)] = {"workspace_bytes": s.workspace_bytes(), "cycles": res["cycles"],
+                                           "time_to_1e-10_s": sorted(times[1:])[len(times[1:]) // 2]}
+            s.close()
+        del f
+    log("in-cycle restriction: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,6 +445,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother training and timing")
     ap.add_argument("--no-paper", action="store_true", help="skip the Sec. 4 reproduction runs")
     ap.add_argument("--no-pow2", action="store_true", help="skip the power-of-two layout timing")
+    ap.add_argument("--no-in-cycle", action="store_true", help="skip the in-cycle restriction comparison")
     ap.add_argument("--no-level-blocked", action="store_true",
                     help="skip the level-blocked comparison solves (profiling runs of the default path)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -553,6 +580,9 @@ def main():
     pow2 = None
     if not args.no_pow2:
         pow2 = pow2_section(P, W, torch, dev)
+    in_cycle = None
+    if not args.no_in_cycle:
+        in_cycle = in_cycle_section(P, W, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -568,7 +598,7 @@ def main():
                       "problems": per, "parallelism": "single GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:10],
            "mixed_precision": mixed, "batched": batched, "learned_smoother": learned,
-           "paper_reproduction": paper, "pow2_grid": pow2}
+           "paper_reproduction": paper, "pow2_grid": pow2, "restriction_in_cycle": in_cycle}
     print(json.dumps(out), flush=True)
 
 

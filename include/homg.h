@@ -104,10 +104,19 @@ typedef struct homg_options {
                               level-m >= 1 iteration is one whole-grid launch; level 0 runs as on
                               nested grids.  The batched, learned, step-restrict/step-sweeps and
                               variable-coefficient paths are nested-only (HOMG_ERR_UNSUPPORTED). */
-    int reserved[6];       /* must be 0 */
+    int restriction;       /* HOMG_RESTRICT_PYRAMID (0): every cycle first restricts r_0 to all its
+                              levels, one compact array per level (Sec. 2, restrictions as a
+                              pre-processing step in independent arrays).
+                              HOMG_RESTRICT_IN_CYCLE (1): Sec. 2's memory-saving form -- the
+                              restrictions run inside the cycle, before each coarse level, into one
+                              extra array (two halves, sized for levels 1 and 2, holding the last
+                              two levels of the chain; a level below them restarts the chain from
+                              r_0).  Same results bit for bit; nested grids only. */
+    int reserved[5];       /* must be 0 */
 } homg_options;
 
 enum { HOMG_GRID_NESTED = 0, HOMG_GRID_POW2 = 1 };
+enum { HOMG_RESTRICT_PYRAMID = 0, HOMG_RESTRICT_IN_CYCLE = 1 };
 
 typedef struct homg_info {
     int cycles;            /* MFMG cycles executed */
@@ -177,6 +186,10 @@ homg_status homg_solve_cycles(homg_handle h, const double *f, double *u, int cyc
  */
 homg_status homg_residual(homg_handle h, const double *f, const double *u, double *r,
                           double *relres_out, void *stream);
+
+/* Device memory the handle holds (its workspace; the caller's arrays not
+ * included), in bytes, to *bytes (host). */
+homg_status homg_workspace_bytes(homg_handle h, size_t *bytes);
 
 /* The schedule in use: writes up to cap (level, iterations) pairs into
  * pairs (host) and returns their count in *len. */

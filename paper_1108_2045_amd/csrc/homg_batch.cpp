@@ -205,8 +205,9 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     if (opt->struct_size != sizeof(homg_options))
       return bfail(nullptr, HOMG_ERR_INVALID_ARG, "homg_options.struct_size mismatch");
     o = *opt;
-    if (o.grid_layout != HOMG_GRID_NESTED)
-      return bfail(nullptr, HOMG_ERR_UNSUPPORTED, "the batched solver runs nested grids only");
+    if (o.grid_layout != HOMG_GRID_NESTED || o.restriction != HOMG_RESTRICT_PYRAMID)
+      return bfail(nullptr, HOMG_ERR_UNSUPPORTED,
+                   "the batched solver runs nested grids with the restriction pyramid only");
   }
   for (int i = 0; i < count; ++i) {
     const int k = side_k(sides[i]);

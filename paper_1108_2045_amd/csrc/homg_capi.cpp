@@ -104,6 +104,16 @@ struct homg_ctx {
   double* r64 = nullptr;
   double* x64[2] = {nullptr, nullptr};
   Lay l64;
+  // in-cycle restriction (Sec. 2): one extra array, two halves rbuf[0]
+  // (odd levels) and rbuf[1] (even levels), instead of the pyramid; r[m]
+  // (m >= 1) aliases them.  rhs_ready: the highest level of the current
+  // chain (its level and the one below are valid); rhs_top64: the FP64
+  // coarsest right-hand side of this cycle is computed.
+  size_t ws_bytes = 0;          // device bytes allocated by the handle
+  bool incycle = false;
+  void* rbuf[2] = {nullptr, nullptr};
+  int rhs_ready = 0;
+  bool rhs_top64 = false;
   // power-of-two layout (Sec. 3): the quadrants' restriction families,
   // level m >= 1 of quadrant q at fam[4 m + q], layout faml[m]
   bool pow2 = false;
@@ -208,7 +218,13 @@ void free_ctx(homg_ctx* h) {
   if (!h) return;
   (void)hipFree(h->e[0]);
   (void)hipFree(h->e[1]);
-  for (void* p : h->r) (void)hipFree(p);
+  if (h->incycle) {
+    if (!h->r.empty()) (void)hipFree(h->r[0]);
+    (void)hipFree(h->rbuf[0]);
+    (void)hipFree(h->rbuf[1]);
+  } else {
+    for (void* p : h->r) (void)hipFree(p);
+  }
   for (double* p : h->a) (void)hipFree(p);
   for (void* p : h->xc) (void)hipFree(p);
   for (void* p : h->xp3) (void)hipFree(p);
@@ -236,6 +252,7 @@ homg_status dev_alloc(homg_ctx* h, void** p, size_t bytes) {
     (void)hipGetLastError();
     return fail(h, HOMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
+  h->ws_bytes += bytes;
   return HOMG_OK;
 }
 
@@ -608,10 +625,36 @@ homg_status enqueue_restrict(homg_ctx* h, int m, const int* done, hipStream_t s)
   return HOMG_OK;
 }
 
+// In-cycle restriction (Sec. 2, restrictions done inside the cycle with one
+// extra array): before level m runs, make r_m valid -- continue the chain of
+// nested restrictions from the last level computed, or restart it from r_0
+// when the level lies below the two the array still holds.  The same
+// restriction kernels run on the same values, so the result equals the
+// pyramid's bit for bit.  No-op for the pyramid.
+homg_status prepare_rhs(homg_ctx* h, int m, const int* done, hipStream_t s) {
+  if (!h->incycle || m <= 0) return HOMG_OK;
+  const bool t64 = top64(h) && m == h->top_level;
+  if (t64 && h->rhs_top64) return HOMG_OK;
+  const int target = t64 ? m - 1 : m;
+  if (target >= 1 && !(target <= h->rhs_ready && target >= h->rhs_ready - 1)) {
+    const int from = target > h->rhs_ready ? h->rhs_ready : 0;
+    for (int j = from; j < target; ++j)
+      if (homg_status e = enqueue_restrict(h, j, done, s)) return e;
+    h->rhs_ready = target;
+  }
+  if (t64) {
+    if (homg_status e = enqueue_restrict(h, m - 1, done, s)) return e;
+    h->rhs_top64 = true;
+  }
+  return HOMG_OK;
+}
+
 // r_0 = f - A u in the handle's precision with its norm partials (and, see
 // residual_restricts, r_1 = R r_0).
 homg_status enqueue_residual(homg_ctx* h, const double* f, const double* u, int* count,
                              const int* done, hipStream_t s) {
+  h->rhs_ready = residual_restricts(h) ? 1 : 0;
+  h->rhs_top64 = false;
   if (residual_restricts(h)) {
     LAUNCH_K(h, s, K_RESIDUAL, 0, 1,
              launch_residual_restrict_2d(h->prec, h->n, u, h->dl, f, h->dl, h->r[0], h->rl[0], h->r[1],
@@ -635,8 +678,14 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
   const int ntail = tail_levels(h, &ms);
   // in a solve (f given) the residual that precedes every cycle already
   // restricted r_0 to level 1
-  for (int m = f && residual_restricts(h) ? 1 : 0; m < (ntail ? ms : h->top_level); ++m)
+  for (int m = f && residual_restricts(h) ? 1 : 0; !h->incycle && m < (ntail ? ms : h->top_level); ++m)
     if (homg_status e = enqueue_restrict(h, m, done, s)) return e;
+  if (!f) {  // a step cycle: r_0 was just given, nothing restricted yet
+    h->rhs_ready = 0;
+    h->rhs_top64 = false;
+  }
+  if (ntail)
+    if (homg_status e = prepare_rhs(h, ms, done, s)) return e;
   int cur = 0;
   const size_t np = h->sched.size() / 2;
   h->chain_ready = -1;
@@ -688,6 +737,7 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
       else if (h->active_smoother == 1 || !(next_last && h->prec != PREC_F64))
         next_m = mn;
     }
+    if (homg_status e = prepare_rhs(h, m, done, s)) return e;
     if (homg_status e = run_level(h, m, it, p == 0, p + 1 == np, next_m, &cur, acc, done, s)) return e;
   }
   if (f) {
@@ -866,7 +916,7 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
     if (opt->struct_size != sizeof(homg_options))
       return fail(nullptr, HOMG_ERR_INVALID_ARG, "homg_options.struct_size mismatch");
     o = *opt;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
       if (o.reserved[i] != 0) return fail(nullptr, HOMG_ERR_INVALID_ARG, "reserved options must be 0");
   }
   double omega = o.omega > 0 ? o.omega : (ndim == 2 ? 4.0 / 5.0 : 6.0 / 7.0);
@@ -878,6 +928,10 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
     return fail(nullptr, HOMG_ERR_INVALID_ARG, "unknown precision");
   if (o.temporal_block < 0 || o.temporal_block > 2)
     return fail(nullptr, HOMG_ERR_INVALID_ARG, "temporal_block must be 0, 1 or 2");
+  if (o.restriction != HOMG_RESTRICT_PYRAMID && o.restriction != HOMG_RESTRICT_IN_CYCLE)
+    return fail(nullptr, HOMG_ERR_INVALID_ARG, "unknown restriction mode");
+  if (o.restriction == HOMG_RESTRICT_IN_CYCLE && pow2)
+    return fail(nullptr, HOMG_ERR_UNSUPPORTED, "in-cycle restriction: nested grids only");
 
   std::vector<int> sched;
   if (o.schedule) {
@@ -914,6 +968,7 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   h->max_cycles = max_cycles;
   h->temporal = o.temporal_block;
   h->pow2 = pow2;
+  h->incycle = o.restriction == HOMG_RESTRICT_IN_CYCLE;
   h->sched = sched;
   h->top_level = 0;
   h->total_sweeps = 0;
@@ -937,7 +992,15 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   homg_status stt = HOMG_OK;
   for (int b = 0; b < 2 && !stt; ++b) stt = dev_alloc(h, &h->e[b], size_t(h->el.alloc) * eb);
   h->r.assign(levels, nullptr);
-  for (int m = 0; m < (pow2 ? 1 : levels) && !stt; ++m) stt = dev_alloc(h, &h->r[m], size_t(h->rl[m].alloc) * eb);
+  const int rown = (pow2 || h->incycle) ? 1 : levels;  // arrays the pyramid owns
+  for (int m = 0; m < rown && !stt; ++m) stt = dev_alloc(h, &h->r[m], size_t(h->rl[m].alloc) * eb);
+  if (h->incycle) {
+    // the one extra array: odd levels in the first half (level 1's size),
+    // even levels in the second (level 2's size)
+    for (int b = 0; b < 2 && b + 1 < levels && !stt; ++b)
+      stt = dev_alloc(h, &h->rbuf[b], size_t(h->rl[b + 1].alloc) * eb);
+    for (int m = 1; m < levels && !stt; ++m) h->r[m] = h->rbuf[(m - 1) & 1];
+  }
   if (pow2) {
     // four restriction families, levels 1 .. levels-1 (side n >> m)
     h->fam.assign(4 * levels, nullptr);
@@ -988,8 +1051,10 @@ homg_status homg_create(homg_handle* out, int ndim, const int64_t* dims, int lev
   ok = ok && hipMemset(h->e[0], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
        hipMemset(h->e[1], 0, size_t(h->el.alloc) * eb) == hipSuccess &&
        hipMemset(h->zero_flag, 0, sizeof(int) * 64) == hipSuccess;
-  for (int m = 0; m < levels && ok; ++m)
+  for (int m = 0; m < rown && ok; ++m)
     if (h->r[m]) ok = hipMemset(h->r[m], 0, size_t(h->rl[m].alloc) * eb) == hipSuccess;
+  for (int b = 0; b < 2 && ok; ++b)
+    if (h->rbuf[b]) ok = hipMemset(h->rbuf[b], 0, size_t(h->rl[b + 1].alloc) * eb) == hipSuccess;
   for (int m = 1; m < int(h->fam.size()) / 4 && ok; ++m)
     for (int q = 0; q < 4 && ok; ++q)
       ok = hipMemset(h->fam[4 * m + q], 0, sizeof(double) * size_t(h->faml[m].alloc)) == hipSuccess;
@@ -1083,6 +1148,12 @@ homg_status homg_residual(homg_handle h, const double* f, const double* u, doubl
   HIPCHK(h, hipMemcpyAsync(h->h_hist, h->hist, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (relres_out) *relres_out = h->h_hist[0];
+  return HOMG_OK;
+}
+
+homg_status homg_workspace_bytes(homg_handle h, size_t* bytes) {
+  if (!h || !bytes) return fail(h, HOMG_ERR_INVALID_ARG, "null argument");
+  *bytes = h->ws_bytes;
   return HOMG_OK;
 }
 
@@ -1289,6 +1360,7 @@ homg_status l1_ready(homg_ctx* h, int slots) {
     if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->l1part), sizeof(double) * l1_partials())) return e;
   if (h->l1cap < slots) {
     (void)hipFree(h->l1out);
+    h->ws_bytes -= sizeof(double) * size_t(h->l1cap);
     h->l1out = nullptr;
     h->l1cap = 0;
     if (homg_status e = dev_alloc(h, reinterpret_cast<void**>(&h->l1out), sizeof(double) * slots)) return e;
@@ -1332,7 +1404,9 @@ homg_status homg_trace_cycle(homg_handle h, const double* f, double* u, const do
   const double* a0 = h->has_coef ? h->a[0] : nullptr;
   LAUNCH(h, launch_residual(h->prec, h->d, h->n, u, h->dl, f, h->dl, a0, a0 ? h->al[0] : none, h->r[0], h->rl[0],
                             h->partials, &pcount, done, s));
-  for (int m = 0; m < h->top_level; ++m)
+  h->rhs_ready = 0;
+  h->rhs_top64 = false;
+  for (int m = 0; !h->incycle && m < h->top_level; ++m)
     if (homg_status e = enqueue_restrict(h, m, done, s)) return e;
   // the schedule one whole-grid iteration at a time (the form in which
   // every iterate exists on the whole grid), the L1 error of u + e after
@@ -1346,6 +1420,7 @@ homg_status homg_trace_cycle(homg_handle h, const double* f, double* u, const do
   const size_t np = h->sched.size() / 2;
   for (size_t p = 0; p < np && st == HOMG_OK; ++p) {
     const int m = h->sched[2 * p], it = h->sched[2 * p + 1];
+    st = prepare_rhs(h, m, done, s);
     for (int t = 0; t < it && st == HOMG_OK; ++t, ++k) {
       const bool first = p == 0 && t == 0, last = p + 1 == np && t + 1 == it;
       st = run_level(h, m, 1, first, last, -1, &cur, u, done, s);

@@ -19,6 +19,7 @@ STATUS_NAMES = {
 LAPLACE_5PT_2D, LAPLACE_7PT_3D, DIFFUSION_5PT_2D = 0, 1, 2
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 GRID_LAYOUTS = {"nested": 0, "pow2": 1}
+RESTRICTIONS = {"pyramid": 0, "in_cycle": 1}
 
 
 class HomgError(RuntimeError):
@@ -32,7 +33,7 @@ class Options(ctypes.Structure):
                 ("max_i", ctypes.c_int), ("max_cycles", ctypes.c_int),
                 ("schedule", ctypes.POINTER(ctypes.c_int)), ("schedule_len", ctypes.c_int),
                 ("precision", ctypes.c_int), ("temporal_block", ctypes.c_int),
-                ("grid_layout", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("grid_layout", ctypes.c_int), ("restriction", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class Info(ctypes.Structure):
@@ -112,6 +113,7 @@ def load_library(path=LIB_PATH):
     L.homg_learn_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, vp, vp]
     L.homg_l1_error.argtypes = [H, dp, dp, ctypes.POINTER(ctypes.c_double), vp]
+    L.homg_workspace_bytes.argtypes = [H, ctypes.POINTER(ctypes.c_size_t)]
     L.homg_trace_cycle.argtypes = [H, dp, dp, dp, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ip, vp]
     L.homg_residual_noalloc.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp,
                                         ctypes.POINTER(ctypes.c_double), vp]
@@ -128,7 +130,7 @@ def load_library(path=LIB_PATH):
                  "homg_smoother_gate", "homg_trainer_create", "homg_trainer_add_problem",
                  "homg_trainer_count", "homg_trainer_train", "homg_trainer_loss", "homg_trainer_destroy",
                  "homg_learn_forward", "homg_learn_grad", "homg_learn_adam", "homg_residual_noalloc",
-                 "homg_l1_error", "homg_trace_cycle"):
+                 "homg_l1_error", "homg_trace_cycle", "homg_workspace_bytes"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -177,7 +179,8 @@ class Solver:
     """One HOMG solver for a d-dimensional grid of side n = 2^k + 1."""
 
     def __init__(self, ndim, n, levels=0, stencil=None, omega=0.0, max_i=4, max_cycles=200,
-                 schedule=None, precision="fp64", temporal_block=2, grid_layout="nested"):
+                 schedule=None, precision="fp64", temporal_block=2, grid_layout="nested",
+                 restriction="pyramid"):
         L = lib()
         if stencil is None:
             stencil = LAPLACE_5PT_2D if ndim == 2 else LAPLACE_7PT_3D
@@ -189,6 +192,7 @@ class Solver:
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         opt.temporal_block = temporal_block
         opt.grid_layout = GRID_LAYOUTS[grid_layout] if isinstance(grid_layout, str) else int(grid_layout)
+        opt.restriction = RESTRICTIONS[restriction] if isinstance(restriction, str) else int(restriction)
         self._sched_buf = None
         if schedule is not None:
             flat = [int(v) for pair in schedule for v in pair]
@@ -294,6 +298,12 @@ class Solver:
         self._check(lib().homg_trace_cycle(self._h, _ptr(f), _ptr(u), _ptr(u_ref), buf, cap, ctypes.byref(cnt),
                                            _stream(stream)))
         return list(buf[:cnt.value])
+
+    def workspace_bytes(self):
+        """Device memory held by the handle (not counting the caller's arrays)."""
+        v = ctypes.c_size_t()
+        self._check(lib().homg_workspace_bytes(self._h, ctypes.byref(v)))
+        return v.value
 
     def schedule(self):
         n = ctypes.c_int()
