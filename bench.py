@@ -7,13 +7,17 @@ restriction pyramid, fused relax+interpolate iterations, update) until the
 relative residual is <= 1e-10:
     2D 4097 x 4097, 5-point, f ~ U[-1, 1] (seed 0)
     3D 257 x 257 x 257, 7-point, f ~ U[-1, 1] (seed 0)
-Inputs are resident in HBM before the timed region.  `value` is grid-node
-updates per second over the whole step (sum over problems of cycles x
-iterations per cycle x nodes, divided by the wall time of the step): the
-paper's whole-grid iterations, counted as such, although the solver
-(default chained execution) materialises only the values later steps read
--- the iterates are the same bit for bit; the level-blocked time (the whole
-grid written after every level) is reported beside it.
+Inputs are resident in HBM before the timed region.  `value` is
+PAPER-EQUIVALENT grid-node updates per second over the whole step: sum over
+problems of cycles x iterations per cycle x nodes (the paper's work units:
+every HOMG iteration is one operation over the entire grid), divided by the
+wall time of the step.  The solver's default chained execution produces the
+same iterates bit for bit but materialises only the values later steps
+read, so `executed` reports what the timed path actually computes and
+moves: relaxations (lattice node-iterations), the kernels' compulsory bytes
+per step and their rate.  The time with one whole-grid launch per iteration
+(the paper's own form) and with the whole grid written after every level
+are reported beside it.
 
 Extra fields: time to 1e-10 per problem, the roofline of the dominant kernel
 (timed per launch with HIP events stamped by the dispatch on its own
@@ -63,6 +67,13 @@ def sweep_bytes(d, n, level, mode, elem=8):
     if mode & 2:
         return reads + 16.0 * N
     return reads + N * elem
+
+
+def relaxations_per_cycle(d, n, schedule):
+    """Node-iterations that relax (damped Jacobi at the interior lattice
+    nodes of each level) in one cycle: what every execution form computes,
+    whatever it writes."""
+    return sum(it * float((n - 1) // (1 << m) - 1) ** d for m, it in schedule)
 
 
 def kernel_symbol(d, kind, level, mode):
@@ -174,18 +185,38 @@ def cpu_baseline():
         total_s += dt
         parts.append("%s: 1 cycle %.1f s" % (name, dt))
         log("cpu oracle %s: one cycle in %.2f s" % (name, dt))
+    # one thread: one cycle of the 3D problem only (bounded CPU time)
+    one = None
+    try:
+        omp = ctypes.CDLL(O._LIB_PATH)
+        omp.omp_set_num_threads(1)
+        name, d, n = PROBLEMS[1]
+        f = W.uniform(d, n, seed=0)
+        k = O.check_side(n)
+        t0 = time.perf_counter()
+        O.solve(d, n, f, fixed_cycles=1)
+        dt = time.perf_counter() - t0
+        one = {"value": sum(it for _, it in O.default_schedule(k, 4)) * float(n) ** d / dt,
+               "cores": 1, "sample": "%s: one MFMG cycle from u = 0, %.1f s" % (name, dt)}
+        log("cpu oracle %s on one thread: one cycle in %.2f s" % (name, dt))
+        omp.omp_set_num_threads(cores)
+    except Exception as exc:  # the thread count cannot be set: report none
+        log("cpu oracle on one thread skipped: %s" % exc)
     del lib
     return {"value": total_updates / total_s, "unit": "node-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": "one MFMG cycle (MaxI 4) of each problem from u = 0: " + "; ".join(parts)}
+            "sample": "one MFMG cycle (MaxI 4) of each problem from u = 0: " + "; ".join(parts),
+            "one_thread": one}
 
 
 def mixed_precision_section(P, W, torch, dev, reps=3):
     """3D 513^3 7-point Poisson, f ~ N(0,1) seed 0: time to 1e-10 (FP64
     relative residual) with FP64, FP32-storage and BF16-storage sweeps under
-    the FP64 residual/update, the speedup over FP64 and the error of u
-    against the FP64 solve, with the rigorous bound (||r_a|| + ||r_b||) /
-    lambda_min that both solutions satisfy."""
+    the FP64 residual/update and an FP64 coarsest level, the speedup over
+    FP64, and the error of u: against the GPU's FP64 solve, and the rigorous
+    bound ||f - A u|| / lambda_min on the distance to the exact discrete
+    solution (A is SPD).  The same solves with the residual recomputed by
+    the CPU oracle are a GPU test (test_mixed_precision_513_cube)."""
     d, n = 3, 513
     f = torch.from_numpy(W.normal(d, n, seed=0)).to(dev)
     h = 1.0 / (n - 1)
@@ -207,12 +238,13 @@ def mixed_precision_section(P, W, torch, dev, reps=3):
         entry = {"status": res["status"], "converged": res["converged"], "cycles": res["cycles"],
                  "time_to_1e-10_s": t if res["converged"] else None,
                  "final_relres_fp64": res["final_relres"]}
+        entry["rel_err_bound_vs_exact"] = (res["final_relres"] * fn / lam_min) / float(torch.linalg.vector_norm(u))
         if prec == "fp64":
             ref = u.clone()
             ref_res = res["final_relres"]
         else:
             diff = float(torch.linalg.vector_norm(u - ref))
-            entry["rel_err_vs_fp64"] = diff / float(torch.linalg.vector_norm(ref))
+            entry["rel_err_vs_gpu_fp64"] = diff / float(torch.linalg.vector_norm(ref))
             entry["abs_err_bound"] = (res["final_relres"] + ref_res) * fn / lam_min
             entry["abs_err"] = diff
             if res["converged"] and out["fp64"]["time_to_1e-10_s"]:
@@ -250,11 +282,14 @@ def batched_section(P, W, torch, dev, count=512, reps=3):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     t = sorted(times[1:])[len(times[1:]) // 2]
-    sweeps = {}
+    sweeps, relax = {}, {}
     for s in set(sides):
         k = (s - 1).bit_length() - 1
-        sweeps[s] = sum(min(2 ** (k - 1 - m + 1), 4) for m in range(k - 1, -1, -1))
+        sched = [(m, min(2 ** (k - 1 - m + 1), 4)) for m in range(k - 1, -1, -1)]
+        sweeps[s] = sum(it for _, it in sched)
+        relax[s] = relaxations_per_cycle(2, s, sched)
     updates = sum(c * sweeps[s] * float(s) ** 2 for c, s in zip(res["cycles"], sides))
+    relaxations = sum(c * relax[s] for c, s in zip(res["cycles"], sides))
     # one problem at a time with the single-problem solver
     solvers = {s: P.Solver(2, s, precision="fp32") for s in set(sides)}
     for u in us:
@@ -270,7 +305,8 @@ def batched_section(P, W, torch, dev, count=512, reps=3):
            "total_nodes": int(sum(s * s for s in sides)), "status": res["status"],
            "all_converged": all(st == 0 for st in res["statuses"]),
            "max_final_relres": max(res["relres"]), "cycles_min_max": [min(res["cycles"]), max(res["cycles"])],
-           "time_to_1e-10_s": t, "node_updates_per_s": updates / t, "tune_s": tune_s,
+           "time_to_1e-10_s": t, "paper_equivalent_node_updates_per_s": updates / t,
+           "relaxations_per_s": relaxations / t, "tune_s": tune_s,
            "one_by_one_single_solver_s": t_seq, "speedup_vs_one_by_one": t_seq / t}
     log("batched: %s" % out)
     bs.close()
@@ -480,7 +516,8 @@ def main():
         u = torch.zeros_like(f)
         s = P.Solver(d, n, max_i=args.max_i)
         sweeps_per_cycle = sum(it for _, it in s.schedule())
-        probs.append({"name": name, "d": d, "n": n, "f": f, "u": u, "s": s, "spc": sweeps_per_cycle})
+        probs.append({"name": name, "d": d, "n": n, "f": f, "u": u, "s": s, "spc": sweeps_per_cycle,
+                      "rpc": relaxations_per_cycle(d, n, s.schedule())})
     torch.cuda.synchronize()
 
     def step(record):
@@ -505,18 +542,20 @@ def main():
     elapsed = time.perf_counter() - t0
 
     updates = 0.0
+    relaxations = 0.0
     per = {}
     for p in probs:
         runs = rec[p["name"]]
         cyc = [r["cycles"] for _, r in runs]
         updates += sum(c * p["spc"] * float(p["n"]) ** p["d"] for c in cyc)
+        relaxations += sum(c * p["rpc"] for c in cyc)
         times = sorted(dt for dt, _ in runs)
         per[p["name"]] = {"time_to_1e-10_s": times[len(times) // 2], "cycles": int(np.median(cyc)),
                           "final_relres": runs[-1][1]["final_relres"],
                           "sweeps_per_cycle": p["spc"], "nodes": int(p["n"] ** p["d"])}
     value = updates / elapsed
 
-    roofline, kernels = None, []
+    roofline, kernels, executed = None, [], None
     if not args.no_profile:
         # the same steps again with every launch stamped by HIP events (the
         # stamping slows dispatch, so the timed steps above run without it)
@@ -529,39 +568,84 @@ def main():
         for p in probs:
             for e in p["s"].profile():
                 sym = kernel_symbol(p["d"], e["kind"], e["level"], e["mode"])
-                k = by_sym.setdefault((p["name"], sym), {"launches": 0, "ms": 0.0, "bytes": 0.0})
+                k = by_sym.setdefault((p["name"], sym), {"launches": 0, "ms": 0.0, "bytes": 0.0, "mode": e["mode"]})
                 k["launches"] += e["launches"]
                 k["ms"] += e["ms"]
                 k["bytes"] += kernel_bytes(p["d"], p["n"], e)
         for (pname, sym), k in sorted(by_sym.items(), key=lambda kv: -kv[1]["ms"]):
-            kernels.append({"problem": pname, "kernel": sym, "launches": k["launches"],
+            kernels.append({"problem": pname, "kernel": sym, "launches": k["launches"], "mode": k["mode"],
                             "avg_us": 1e3 * k["ms"] / max(k["launches"], 1),
                             "total_ms": k["ms"],
                             "alg_GBps": (k["bytes"] / 1e9) / (k["ms"] / 1e3) if k["ms"] > 0 else None})
         dom = kernels[0]
         k = by_sym[(dom["problem"], dom["kernel"])]
-        achieved = (k["bytes"] / k["launches"]) / (k["ms"] / k["launches"] / 1e3) / 1e9
+        dp = next(p for p in probs if p["name"] == dom["problem"])
+        t_launch = k["ms"] / k["launches"] / 1e3
+        compulsory = k["bytes"] / k["launches"]
+        # the per-unit figure of the measurement plan: 24 B (FP64) per level-0
+        # node-update -- read e and r, write e -- times the node-updates one
+        # launch performs (iterations in the pass x nodes); for a pass of
+        # several iterations this counts the bytes the single-sweep form would
+        # move, so it can exceed the HBM peak
+        its = ((dom["mode"] >> 4) & 3) + 1 if dom["mode"] & 8 else 1
+        per_unit = 24.0 * its * float(dp["n"]) ** dp["d"]
+        achieved = per_unit / t_launch / 1e9
+        traffic = measured_traffic(dom["kernel"])
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom["kernel"]),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "achieved_basis": "24 B per level-0 node-update x %d iterations x %d nodes per launch"
+                                      % (its, int(float(dp["n"]) ** dp["d"])),
+                    "frac_compulsory": compulsory / t_launch / 1e9 / HBM_PEAK_GBS,
+                    "compulsory_basis": "bytes the pass itself must move once (read e, r, u; write u)",
+                    "frac_measured_traffic": (traffic / t_launch / 1e9 / HBM_PEAK_GBS) if traffic else None,
                     "kernel": dom["kernel"], "problem": dom["problem"],
-                    "bytes_per_launch": k["bytes"] / k["launches"],
-                    "avg_launch_us": 1e3 * k["ms"] / k["launches"]}
+                    "bytes_per_launch": per_unit, "compulsory_bytes_per_launch": compulsory,
+                    "avg_launch_us": 1e6 * t_launch}
+        exec_bytes = sum(v["bytes"] for v in by_sym.values()) / args.steps
+        executed = {"relaxations_per_step": relaxations / args.steps,
+                    "relaxations_per_s": relaxations / elapsed,
+                    "compulsory_bytes_per_step": exec_bytes,
+                    "compulsory_GBps": exec_bytes / (elapsed / args.steps) / 1e9,
+                    "note": "relaxations: damped-Jacobi node-iterations at interior lattice nodes, as "
+                            "computed by every execution form; bytes: each launched kernel's compulsory "
+                            "traffic (kernels of the profiled rerun of the same steps)"}
 
-    # the same solves on the level-blocked path (bit-identical results; the
-    # whole grid is written after every level instead of only before level 0)
+    # the same solves with one whole-grid launch per iteration (the paper's
+    # form; temporal_block 0) and on the level-blocked path (the whole grid
+    # written after every level): bit-identical results
+    single_sweep = {}
     for p in ([] if args.no_level_blocked else probs):
-        sc = P.Solver(p["d"], p["n"], max_i=args.max_i, temporal_block=1)
-        times = []
-        for _ in range(4):
-            p["u"].zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res = sc.solve(p["f"], p["u"], tol=1e-10)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t0)
-        per[p["name"]]["level_blocked_time_to_1e-10_s"] = sorted(times[1:])[1]
-        per[p["name"]]["level_blocked_cycles"] = res["cycles"]
-        sc.close()
+        for tb, key in ((0, "one_launch_per_iteration"), (1, "level_blocked")):
+            sc = P.Solver(p["d"], p["n"], max_i=args.max_i, temporal_block=tb)
+            times = []
+            for _ in range(4):
+                p["u"].zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = sc.solve(p["f"], p["u"], tol=1e-10)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            per[p["name"]][key + "_time_to_1e-10_s"] = sorted(times[1:])[1]
+            per[p["name"]][key + "_cycles"] = res["cycles"]
+            if tb == 0 and not args.no_profile:
+                # the single-sweep fused S+R kernel, level 0 and coarse levels apart
+                sc.set_profiling(True)
+                p["u"].zero_()
+                sc.solve(p["f"], p["u"], tol=1e-10)
+                agg = {"level0": [0, 0.0, 0.0], "coarse": [0, 0.0, 0.0]}
+                for e in sc.profile():
+                    if e["kind"] != "sweep":
+                        continue
+                    a = agg["level0" if e["level"] == 0 else "coarse"]
+                    a[0] += e["launches"]
+                    a[1] += e["ms"]
+                    a[2] += kernel_bytes(p["d"], p["n"], e)
+                single_sweep[p["name"]] = {
+                    k2: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                         "alg_GBps": v[2] / 1e9 / (v[1] / 1e3) if v[1] > 0 else None,
+                         "frac": (v[2] / 1e9 / (v[1] / 1e3)) / HBM_PEAK_GBS if v[1] > 0 else None}
+                    for k2, v in agg.items()}
+            sc.close()
     for p in probs:
         p["s"].close()
     mixed = None
@@ -596,7 +680,9 @@ def main():
                                   "3D 257^3 7-point, f ~ U[-1,1] seed 0, u0 = 0, zero Dirichlet, "
                                   "MaxI %d, omega 4/5 (2D) 6/7 (3D)" % args.max_i,
                       "problems": per, "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels[:10],
+           "value_kind": "paper-equivalent: cycles x whole-grid iterations per cycle x nodes, per second",
+           "executed": executed, "roofline": roofline, "fused_sr_single_sweep": single_sweep or None,
+           "cpu_baseline": cpu, "kernels": kernels[:10],
            "mixed_precision": mixed, "batched": batched, "learned_smoother": learned,
            "paper_reproduction": paper, "pow2_grid": pow2, "restriction_in_cycle": in_cycle}
     print(json.dumps(out), flush=True)

@@ -358,7 +358,11 @@ homg_status homg_batch_destroy(homg_batch b);
  *   fallback_ratio (<= 0 selects 1.0): a solve that sees a cycle whose
  *   relative residual is not below fallback_ratio times the previous one
  *   switches to damped Jacobi for the rest of that solve (checked at each
- *   host synchronisation; info->smoother_fell_back = 1).  HOMG_ERR_UNSUPPORTED
+ *   host synchronisation; info->smoother_fell_back = 1).  After a
+ *   homg_smoother_gate call the handle also holds a damped-Jacobi reference
+ *   (the worst geometric-mean per-cycle contraction of Jacobi on the gate's
+ *   problems): a learned solve whose geometric-mean contraction over three
+ *   or more cycles is worse than it falls back too.  HOMG_ERR_UNSUPPORTED
  *   for 3D handles.
  * homg_get_smoother_weights: copies the FP32 values of the BF16 weights (576)
  *   to the device array w_out.

@@ -97,6 +97,7 @@ struct homg_ctx {
   int smoother = 0;
   int active_smoother = 0;     // smoother of the solve in progress (after any fallback)
   double fallback_ratio = 1.0; // per-cycle contraction at which a solve falls back to Jacobi
+  double rho_ref = 0.0;        // damped-Jacobi reference contraction from the last gate (0: none)
   uint16_t* wbf = nullptr;     // the 576 weights in BF16
   float* w32 = nullptr;        // their FP32 values (what the kernels read)
   // FP32/BF16 cycles: the coarsest level (top_level) in FP64 -- its
@@ -794,7 +795,9 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
     if (h->h_st->done || enqueued >= limit) break;
     const int c = h->h_st->cycles;
     // learned relaxation: fall back to damped Jacobi for the rest of the solve
-    // once a cycle contracts the residual by less than fallback_ratio
+    // once a cycle contracts the residual by less than fallback_ratio, or --
+    // with a Jacobi reference from the gate -- once the geometric-mean
+    // contraction over three or more cycles is worse than the reference
     if (h->active_smoother == 1) {
       for (int i = 1; i <= c; ++i)
         if (!(h->h_hist[i] < h->fallback_ratio * h->h_hist[i - 1])) {
@@ -802,6 +805,13 @@ homg_status solve_impl(homg_ctx* h, const double* f, double* u, double tol, int 
           fell_back = 1;
           break;
         }
+      if (h->active_smoother == 1 && h->rho_ref > 0.0 && c >= 3 && h->h_hist[0] > 0.0) {
+        const double rho = std::pow(h->h_hist[c] / h->h_hist[0], 1.0 / c);
+        if (!(rho <= h->rho_ref)) {
+          h->active_smoother = 0;
+          fell_back = 1;
+        }
+      }
     }
     // size the next batch from the observed contraction
     double q = 0.5;
@@ -1317,6 +1327,7 @@ homg_status homg_smoother_gate(homg_handle h, int count, const double* const* f,
   const double keep_ratio = h->fallback_ratio;
   homg_status st = HOMG_OK;
   int ok = 1;
+  double rho_max = 0.0;  // the Jacobi reference the runtime fallback compares against
   std::vector<double> hist(cycles + 1);
   for (int i = 0; i < count && st == HOMG_OK; ++i) {
     double rho[2] = {0.0, 0.0};
@@ -1336,6 +1347,7 @@ homg_status homg_smoother_gate(homg_handle h, int count, const double* const* f,
       rho[which] = (hist[0] > 0.0) ? std::pow(hist[cycles] / hist[0], 1.0 / cycles) : 0.0;
     }
     if (st != HOMG_OK) break;
+    rho_max = std::max(rho_max, rho[0]);
     if (rho_jacobi) rho_jacobi[i] = rho[0];
     if (rho_learned) rho_learned[i] = rho[1];
     if (!(rho[1] <= rho[0])) ok = 0;
@@ -1345,8 +1357,10 @@ homg_status homg_smoother_gate(homg_handle h, int count, const double* const* f,
   h->fallback_ratio = keep_ratio;
   (void)hipStreamSynchronize(s);
   (void)hipFree(u);
+  h->ws_bytes -= bytes;
   if (st != HOMG_OK) return st;
   *accepted = ok;
+  h->rho_ref = rho_max;
   return HOMG_OK;
 }
 

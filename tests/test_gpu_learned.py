@@ -333,6 +333,31 @@ def test_fallback_to_jacobi(B, torch_cuda):
     assert s.residual(dev64(torch, f), u) <= 1e-10 * (1 + 1e-6)
 
 
+def test_fallback_against_jacobi_reference(B, torch_cuda):
+    """Weights that converge but more slowly than damped Jacobi (the
+    Jacobi-equivalent network with omega 0.3): without a reference the solve
+    keeps them (every cycle contracts); after the gate, which rejects them
+    and records Jacobi's contraction, the solve falls back to Jacobi and
+    takes fewer cycles."""
+    torch = torch_cuda
+    n = 129
+    a, f = W.grf_problem(n, seed=12)
+    fd = dev64(torch, f)
+    s = B.Solver(2, n, stencil=B.DIFFUSION_5PT_2D)
+    s.set_coefficient(dev64(torch, a))
+    s.set_smoother(B.LEARNED, dev32(torch, LO.jacobi_weights(0.3)))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    slow = s.solve(fd, u, tol=1e-10)
+    assert slow["converged"] and not slow["smoother_fell_back"]
+    gate = s.smoother_gate([fd], 6)
+    assert not gate["accepted"] and gate["rho_learned"][0] > gate["rho_jacobi"][0]
+    u.zero_()
+    res = s.solve(fd, u, tol=1e-10)
+    assert res["smoother_fell_back"] and res["converged"]
+    assert res["cycles"] < slow["cycles"]
+    assert s.residual(fd, u) <= 1e-10 * (1 + 1e-6)
+
+
 def test_learned_smoother_is_2d_only(B, torch_cuda):
     torch = torch_cuda
     s = B.Solver(3, 17)
