@@ -101,6 +101,12 @@ __host__ __device__ inline int tb_waves(int n, int it, int len) {
   const int valid = 64 - 2 * it;
   return ((n - 2 + valid - 1) / valid) * ((n - 2 + len - 1) / len);
 }
+// Workgroups of a pass: each takes one column tile on four consecutive bands
+// (one wave per band), so its four waves write different rows.
+__host__ __device__ inline int tb_blocks(int n, int it, int len) {
+  const int valid = 64 - 2 * it;
+  return ((n - 2 + valid - 1) / valid) * ((n - 2 + 4 * len - 1) / (4 * len));
+}
 int tb_band(int n, int it);
 // A coarse level's final compact state (layout cl, side (n-1)/2+1 for a
 // pass over side n): x_it in cur and x_{it-1} in prev (unread when

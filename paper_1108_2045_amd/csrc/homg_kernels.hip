@@ -157,7 +157,19 @@ __device__ __forceinline__ double block_sum(double v) {
 
 // ------------------------------------------------------------ launch shapes
 
-constexpr int BX2 = 256;          // 2D: lanes along x per block
+constexpr int BX2 = 256;          // 2D: lanes per block
+// 2D tiles: a block's four waves take TW2 = 64 columns each on four
+// consecutive bands of `len` rows (wave w of block row `by` walks band
+// 4 by + w), so the waves of one block write different rows.  Measured on
+// MI355X with a padded 4097^2 FP64 array: a pure write stream runs at 5.9
+// TB/s this way against 4.2 TB/s with the four waves side by side on the
+// same rows, and a two-read one-write stream with streaming stores at 7.8
+// against 6.9 TB/s.
+constexpr int TW2 = 64;
+__device__ __forceinline__ int t2_x(int bx) { return 1 + bx * TW2 + int(threadIdx.x & 63); }
+__device__ __forceinline__ int t2_y0(int by, int len) { return 1 + (by * 4 + int(threadIdx.x >> 6)) * len; }
+__host__ __device__ inline int t2_gx(int n) { return (n - 2 + TW2 - 1) / TW2; }
+__host__ __device__ inline int t2_gy(int n, int len) { return (n - 2 + 4 * len - 1) / (4 * len); }
 constexpr int BX3 = 64, BY3 = 4;  // 3D: lanes along x and y per block
 
 // Rows (2D) or planes (3D) walked by one block: enough blocks to fill the
@@ -178,7 +190,8 @@ static int walk_len(int d, int n) {
 static dim3 grid_of(int d, int n, int len) {
   const int inner = n - 2;
   const int walks = (inner + len - 1) / len;
-  if (d == 2) return dim3((inner + BX2 - 1) / BX2, walks, 1);
+  (void)walks;
+  if (d == 2) return dim3(t2_gx(n), t2_gy(n, len), 1);
   return dim3((inner + BX3 - 1) / BX3, (inner + BY3 - 1) / BY3, walks);
 }
 
@@ -257,8 +270,8 @@ __device__ __forceinline__ unsigned xcd_order(unsigned h, unsigned count) {
 
 __device__ __forceinline__ void tile_norm2_2d(const double* __restrict__ f, int64_t fp, int n,
                                                   int len, double* __restrict__ partials, int bx, int by, int pidx) {
-  const int x = 1 + bx * BX2 + threadIdx.x;
-  const int y0 = 1 + by * len;
+  const int x = t2_x(bx);
+  const int y0 = t2_y0(by, len);
   const int y1 = min(n - 1, y0 + len);
   double s = 0.0;
   if (x <= n - 2)
@@ -303,11 +316,11 @@ __device__ __forceinline__ void tile_residual_2d(
     const double* __restrict__ u, int64_t up, const double* __restrict__ f, int64_t fp,
     const double* __restrict__ a, int64_t ap, T* __restrict__ r, int64_t rp, int n, int len,
     double inv_h2, double* __restrict__ partials, int bx, int by, int pidx) {
-  const int x = 1 + bx * BX2 + threadIdx.x;
-  const int y0 = 1 + by * len;
+  const int x = t2_x(bx);
+  const int y0 = t2_y0(by, len);
   const int y1 = min(n - 1, y0 + len);
   double s = 0.0;
-  if (x <= n - 2) {
+  if (x <= n - 2 && y0 <= n - 2) {
     double ym = u[int64_t(y0 - 1) * up + x];
     double c = u[int64_t(y0) * up + x];
     double aym = 0.0, ac = 0.0;
@@ -435,7 +448,10 @@ __global__ __launch_bounds__(256) void k_residual_restrict_2d(
                                                 int(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int gx = (n - 2 + RR_W - 1) / RR_W;
+  // (the four waves of a workgroup side by side on the same band measured
+  // faster here than on four bands: 87 against 103 us at 4097^2)
   if (wv >= gx * ((n - 2 + len - 1) / len)) return;  // the whole wave
+  const int pidx = wv;
   const int x = (wv % gx) * RR_W + lane;
   const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);  // len even: Y0 odd
   const bool xin = x >= 1 && x <= n - 2;
@@ -470,7 +486,7 @@ __global__ __launch_bounds__(256) void k_residual_restrict_2d(
     c = yp;
   }
   s = wave_sum(s);
-  if (lane == 0) partials[wv] = s;
+  if (lane == 0) partials[pidx] = s;
 }
 
 // ------------------------------------------------------------ finalize
@@ -570,9 +586,9 @@ __device__ __forceinline__ void tile_restrict_2d(const TI* __restrict__ rf, int6
                                                      TO* __restrict__ rc, int64_t cp, int nc,
                                                      int len, int bx, int by) {
   using C = typename Tr<TO>::C;
-  const int I = 1 + bx * BX2 + threadIdx.x;
-  if (I > nc - 2) return;
-  const int J0 = 1 + by * len;
+  const int I = t2_x(bx);
+  const int J0 = t2_y0(by, len);
+  if (I > nc - 2 || J0 > nc - 2) return;
   const int J1 = min(nc - 1, J0 + len);
   const int xi = 2 * I;
   auto rowsum = [&](int yf) {
@@ -696,9 +712,9 @@ __device__ __forceinline__ void tile_sweep_2d_l0(
     int64_t rp, const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up,
     int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2, int bx, int by) {
   using C = typename Tr<T>::C;
-  const int x = 1 + bx * BX2 + threadIdx.x;
-  if (x > n - 2) return;
-  const int y0 = 1 + by * len;
+  const int x = t2_x(bx);
+  const int y0 = t2_y0(by, len);
+  if (x > n - 2 || y0 > n - 2) return;  // (the last block row may hold empty bands)
   const int y1 = min(n - 1, y0 + len);
   C ym = C(0), c = C(0);
   if (!(MODE & SW_ZERO_OLD)) {
@@ -727,7 +743,7 @@ __global__ __launch_bounds__(256) void k_sweep_2d_l0(
   // one-dimensional grid in XCD order: the walks of one XCD form one band of
   // rows, so the rows shared by vertically adjacent walks stay in its L2
   const unsigned lg = xcd_order(blockIdx.x, gridDim.x);
-  const int gx = (n - 2 + BX2 - 1) / BX2;
+  const int gx = t2_gx(n);
   tile_sweep_2d_l0<T, MODE, VAR>(eo, en, ep, r, rp, a, ap, u, up, n, len, w, hl2, int(lg % gx), int(lg / gx));
 }
 
@@ -992,9 +1008,12 @@ __device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict_
   constexpr int VALID = 64 - 2 * IT;
   const int lane = threadIdx.x & 63;
   const int gx = (n - 2 + VALID - 1) / VALID, gy = (n - 2 + len - 1) / len;
-  if (wv >= gx * gy) return;  // the whole wave
-  const int x = 1 + (wv % gx) * VALID - IT + lane;
-  const int Y0 = 1 + (wv / gx) * len, Y1 = min(n - 1, Y0 + len);
+  // wave wv: workgroup wv / 4 takes column tile (wv / 4) % gx on bands
+  // 4 ((wv / 4) / gx) .. + 3, one per wave (tb_blocks)
+  const int q = wv >> 2, band = (q / gx) * 4 + (wv & 3);
+  if (band >= gy) return;  // the whole wave
+  const int x = 1 + (q % gx) * VALID - IT + lane;
+  const int Y0 = 1 + band * len, Y1 = min(n - 1, Y0 + len);
   const bool xin = x >= 1 && x <= n - 2;
   const bool emit = lane >= IT && lane < 64 - IT;
   const int xc = min(max(x, 0), n - 1);  // columns off the grid read the boundary (zero)
@@ -1053,18 +1072,20 @@ __device__ __forceinline__ void tile_sweep_2d_coarse(
     int64_t rp, const double* __restrict__ am, int64_t ap, double* __restrict__ u, int64_t up,
     int n, int len, int m, typename Tr<T>::C w, typename Tr<T>::C hl2, int bx, int by) {
   using C = typename Tr<T>::C;
-  const int x = 1 + bx * BX2 + threadIdx.x;
-  if (x > n - 2) return;
+  const int x = t2_x(bx);
+  const int y0 = t2_y0(by, len);
+  if (x > n - 2 || y0 > n - 2) return;
   const int l = 1 << m;
   const int mask = l - 1;
   const C inv_l = C(1) / C(l);
-  const int y0 = 1 + by * len;
   const int y1 = min(n - 1, y0 + len);
   const int xa = x & ~mask, xb = xa + l;
   const C tx = C(x - xa) * inv_l;
   const bool latc = (x == xa);
   int ya = y0 & ~mask;
-  C t0 = C(0), t1 = C(0), b0 = C(0), b1 = C(0);
+  // corners of the current cell's top (ya) and bottom (ya + l) rows; the
+  // next cell's bottom corners are loaded one cell ahead
+  C t0 = C(0), t1 = C(0), b0 = C(0), b1 = C(0), n0 = C(0), n1 = C(0);
   if (!(MODE & SW_ZERO_OLD)) {
     t0 = ld(eo + int64_t(ya) * ep + xa);
     t1 = ld(eo + int64_t(ya) * ep + xb);
@@ -1072,38 +1093,41 @@ __device__ __forceinline__ void tile_sweep_2d_coarse(
     b1 = ld(eo + int64_t(ya + l) * ep + xb);
   }
   C top = lerp(t0, t1, tx), bot = lerp(b0, b1, tx);
-  for (int y = y0; y < y1; ++y) {
-    if (y - ya == l) {
-      ya += l;
-      t0 = b0;
-      t1 = b1;
-      top = bot;
-      if (!(MODE & SW_ZERO_OLD)) {
-        b0 = ld(eo + int64_t(ya + l) * ep + xa);
-        b1 = ld(eo + int64_t(ya + l) * ep + xb);
-      }
-      bot = lerp(b0, b1, tx);
+  for (int yc = y0; yc < y1; ya += l) {
+    const int ye = min(y1, ya + l);
+    if (!(MODE & SW_ZERO_OLD) && ye < y1) {
+      n0 = ld(eo + int64_t(ya + 2 * l) * ep + xa);
+      n1 = ld(eo + int64_t(ya + 2 * l) * ep + xb);
     }
-    C v;
-    if (latc && y == ya) {
-      const C rv = ld(rm + int64_t(ya >> m) * rp + (xa >> m));
-      C xm = C(0), ym = C(0);
-      if (!(MODE & SW_ZERO_OLD)) {
-        xm = ld(eo + int64_t(ya) * ep + xa - l);
-        ym = ld(eo + int64_t(ya - l) * ep + xa);
-      }
-      if (VAR) {
-        const int I = xa >> m, J = ya >> m;
-        const double* arow = am + int64_t(J) * ap + I;
-        v = relax_var<C>(t0, xm, t1, ym, b0, arow[0], arow[-1], arow[1], arow[-ap], arow[ap], rv,
-                         w, hl2);
+    for (int y = yc; y < ye; ++y) {
+      C v;
+      if (latc && y == ya) {
+        const C rv = ld(rm + int64_t(ya >> m) * rp + (xa >> m));
+        C xm = C(0), ym = C(0);
+        if (!(MODE & SW_ZERO_OLD)) {
+          xm = ld(eo + int64_t(ya) * ep + xa - l);
+          ym = ld(eo + int64_t(ya - l) * ep + xa);
+        }
+        if (VAR) {
+          const int I = xa >> m, J = ya >> m;
+          const double* arow = am + int64_t(J) * ap + I;
+          v = relax_var<C>(t0, xm, t1, ym, b0, arow[0], arow[-1], arow[1], arow[-ap], arow[ap], rv,
+                           w, hl2);
+        } else {
+          v = relax_const<C>(t0, (xm + t1) + (ym + b0), rv, w, hl2, C(4));
+        }
       } else {
-        v = relax_const<C>(t0, (xm + t1) + (ym + b0), rv, w, hl2, C(4));
+        v = lerp(top, bot, C(y - ya) * inv_l);
       }
-    } else {
-      v = lerp(top, bot, C(y - ya) * inv_l);
+      emit_2d<T, MODE, VAR, true>(en, int64_t(y) * ep + x, u, int64_t(y) * up + x, v);
     }
-    emit_2d<T, MODE, VAR, true>(en, int64_t(y) * ep + x, u, int64_t(y) * up + x, v);
+    yc = ye;
+    t0 = b0;
+    t1 = b1;
+    b0 = n0;
+    b1 = n1;
+    top = bot;
+    bot = lerp(b0, b1, tx);
   }
 }
 
@@ -1390,9 +1414,12 @@ __global__ __launch_bounds__(256) void k_sweep_3d_coarse(
   const int64_t c00 = int64_t(ya) * ep + xa, c01 = int64_t(ya) * ep + xb;
   const int64_t c10 = int64_t(yb) * ep + xa, c11 = int64_t(yb) * ep + xb;
   int za = z0 & ~mask;
-  // corners of the top (za) and bottom (za + l) planes of the current cell
+  // corners of the top (za) and bottom (za + l) planes of the current cell;
+  // the next cell's bottom corners (za + 2l) are loaded one cell ahead, so
+  // their latency overlaps the stores of the current cell
   C t00 = C(0), t01 = C(0), t10 = C(0), t11 = C(0);
   C b00 = C(0), b01 = C(0), b10 = C(0), b11 = C(0);
+  C n00 = C(0), n01 = C(0), n10 = C(0), n11 = C(0);
   if (!(MODE & SW_ZERO_OLD)) {
     const T* pt = eo + int64_t(za) * epl;
     const T* pb = pt + int64_t(l) * epl;
@@ -1401,35 +1428,37 @@ __global__ __launch_bounds__(256) void k_sweep_3d_coarse(
   }
   C top = lerp(lerp(t00, t01, tx), lerp(t10, t11, tx), ty);
   C bot = lerp(lerp(b00, b01, tx), lerp(b10, b11, tx), ty);
-  for (int z = z0; z < z1; ++z) {
-    if (z - za == l) {
-      za += l;
-      t00 = b00; t01 = b01; t10 = b10; t11 = b11;
-      top = bot;
-      if (!(MODE & SW_ZERO_OLD)) {
-        const T* pb = eo + int64_t(za + l) * epl;
-        b00 = ld(pb + c00); b01 = ld(pb + c01); b10 = ld(pb + c10); b11 = ld(pb + c11);
-      }
-      bot = lerp(lerp(b00, b01, tx), lerp(b10, b11, tx), ty);
+  for (int zc = z0; zc < z1; za += l) {
+    const int ze = min(z1, za + l);
+    if (!(MODE & SW_ZERO_OLD) && za + 2 * l <= n - 1 && ze < z1) {
+      const T* pn = eo + int64_t(za + 2 * l) * epl;
+      n00 = ld(pn + c00); n01 = ld(pn + c01); n10 = ld(pn + c10); n11 = ld(pn + c11);
     }
-    C v;
-    if (latxy && z == za) {
-      const C rv = ld(rm + int64_t(za >> m) * rpl + int64_t(ya >> m) * rp + (xa >> m));
-      C xm = C(0), ym = C(0), zm = C(0);
-      if (!(MODE & SW_ZERO_OLD)) {
-        const T* p = eo + int64_t(za) * epl + c00;
-        xm = ld(p - l);
-        ym = ld(p - int64_t(l) * ep);
-        zm = ld(p - int64_t(l) * epl);
+    for (int z = zc; z < ze; ++z) {
+      C v;
+      if (latxy && z == za) {
+        const C rv = ld(rm + int64_t(za >> m) * rpl + int64_t(ya >> m) * rp + (xa >> m));
+        C xm = C(0), ym = C(0), zm = C(0);
+        if (!(MODE & SW_ZERO_OLD)) {
+          const T* p = eo + int64_t(za) * epl + c00;
+          xm = ld(p - l);
+          ym = ld(p - int64_t(l) * ep);
+          zm = ld(p - int64_t(l) * epl);
+        }
+        v = relax_const<C>(t00, ((xm + t01) + (ym + t10)) + (zm + b00), rv, w, hl2, C(6));
+      } else {
+        v = lerp(top, bot, C(z - za) * inv_l);
       }
-      v = relax_const<C>(t00, ((xm + t01) + (ym + t10)) + (zm + b00), rv, w, hl2, C(6));
-    } else {
-      v = lerp(top, bot, C(z - za) * inv_l);
+      if (MODE & SW_ACCUM)
+        add_to(u + int64_t(z) * upl + int64_t(y) * up + x, double(v));
+      else
+        st_w(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
     }
-    if (MODE & SW_ACCUM)
-      add_to(u + int64_t(z) * upl + int64_t(y) * up + x, double(v));
-    else
-      st_w(en + int64_t(z) * epl + int64_t(y) * ep + x, v);
+    zc = ze;
+    t00 = b00; t01 = b01; t10 = b10; t11 = b11;
+    b00 = n00; b01 = n01; b10 = n10; b11 = n11;
+    top = bot;
+    bot = lerp(lerp(b00, b01, tx), lerp(b10, b11, tx), ty);
   }
 }
 
@@ -1570,7 +1599,9 @@ __global__ __launch_bounds__(256) void k_level_write_2d(
   if (*done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int l = 1 << m, mask = l - 1;
-  const int X0 = 1 + blockIdx.x * BX2, X1 = min(n - 2, X0 + BX2 - 1);
+  // a tile of TW2 columns and LW_ROWS2 rows; wave w writes rows
+  // Y0 + w LW_ROWS2/4 .. (the four waves on different rows)
+  const int X0 = 1 + blockIdx.x * TW2, X1 = min(n - 2, X0 + TW2 - 1);
   const int Y0 = 1 + blockIdx.y * LW_ROWS2, Y1 = min(n - 2, Y0 + LW_ROWS2 - 1);
   const int I0 = X0 >> m, J0 = Y0 >> m;
   const int CW = (X1 >> m) - I0 + 2, CH = (Y1 >> m) - J0 + 2;
@@ -1583,7 +1614,9 @@ __global__ __launch_bounds__(256) void k_level_write_2d(
     Q[i] = ld(xcur + g);
   }
   __syncthreads();
-  const int x = X0 + threadIdx.x;
+  const int x = X0 + int(threadIdx.x & 63);
+  constexpr int WR = LW_ROWS2 / 4;
+  const int ya = Y0 + int(threadIdx.x >> 6) * WR, yb = min(Y1, ya + WR - 1);
   if (x > X1) return;
   const C inv_l = C(1) / C(l);
   const int xi = (x >> m) - I0;
@@ -1591,7 +1624,7 @@ __global__ __launch_bounds__(256) void k_level_write_2d(
   const bool latc = (x & mask) == 0;
   int band = -1;
   C top = C(0), bot = C(0);
-  for (int y = Y0; y <= Y1; ++y) {
+  for (int y = ya; y <= yb; ++y) {
     const int yj = (y >> m) - J0;
     if (yj != band) {
       band = yj;
@@ -2241,7 +2274,7 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
     if (m == 0) {
       // walks of 8 rows, one-dimensional grid in XCD order
       const int inner = n - 2, len0 = inner < 8 ? inner : 8;
-      const dim3 g1(((inner + BX2 - 1) / BX2) * ((inner + len0 - 1) / len0));
+      const dim3 g1(t2_gx(n) * t2_gy(n, len0));
       if (am)
         HOMG_LAUNCH((k_sweep_2d_l0<T, MODE, true>), g1, dim3(BX2), s, eo, en, el.pitch, rm,
                     rl.pitch, a, al.pitch, uu, ul.pitch, n, len0, w, hl2, done);
@@ -2300,7 +2333,7 @@ static hipError_t tb_t(int n, int it, int len, double omega, const void* eo_, vo
   double* uu = u ? u + ul.off : nullptr;
   const double h = 1.0 / double(n - 1);
   const C w = C(omega / 4.0), hl2 = C(h * h);
-  const dim3 g((tb_waves(n, it, len) + 3) / 4);
+  const dim3 g(tb_blocks(n, it, len));
 #define TB2_ARGS eo, en, el.pitch, rm, rl.pitch, uu, ul.pitch, n, len, w, hl2, done, l1
   switch (it) {
     case 1: HOMG_LAUNCH((k_sweep_2d_l0_tb<T, ZERO, ACCUM, 1, LAT>), g, dim3(256), s, TB2_ARGS);
@@ -2336,7 +2369,7 @@ static hipError_t ltb_t(int nm, int it, int len, double omega, const void* eo_, 
   const T* rm = static_cast<const T*>(rm_) + rl.off;
   const double h = 1.0 / double(nm - 1);
   const C w = C(omega / 4.0), hl2 = C(h * h);
-  const dim3 g((tb_waves(nm, it, len) + 3) / 4);
+  const dim3 g(tb_blocks(nm, it, len));
 #define LTB_ARGS eo, en, epv, cl.pitch, rm, rl.pitch, nm, len, w, hl2, done, l1
   switch (it) {
     case 1: HOMG_LAUNCH((k_lattice_2d_tb<T, ZERO, PREV, 1, LAT>), g, dim3(256), s, LTB_ARGS);
@@ -2771,7 +2804,7 @@ hipError_t launch_level_transfer(int prec, int d, int m, const void* xprev, cons
 size_t level_write_lds(int prec, int d, int n, int m) {
   const size_t cs = prec == PREC_F64 ? 8 : 4;
   if (d == 2) {
-    const size_t cw = size_t(BX2 >> m) + 3, ch = size_t(LW_ROWS2 >> m) + 3;
+    const size_t cw = size_t(TW2 >> m) + 3, ch = size_t(LW_ROWS2 >> m) + 3;
     return 2 * cw * ch * cs;
   }
   const size_t cw = size_t(BX3 >> m) + 3, ch = size_t(BY3 >> m) + 3, cd = size_t(LW_PLANES3 >> m) + 3;
@@ -2790,7 +2823,7 @@ static hipError_t level_write_tm(int d, int n, int m, const void* xprev, const v
   double* uu = u ? u + ul.off : nullptr;
   const int inner = n - 2;
   if (d == 2) {
-    const dim3 g((inner + BX2 - 1) / BX2, (inner + LW_ROWS2 - 1) / LW_ROWS2);
+    const dim3 g((inner + TW2 - 1) / TW2, (inner + LW_ROWS2 - 1) / LW_ROWS2);
     HOMG_LAUNCH_SMEM((k_level_write_2d<T, MODE>), g, dim3(BX2), lds, s, xp, xc, cl.pitch, e,
                      el.pitch, uu, ul.pitch, n, m, done);
   }
@@ -2855,7 +2888,7 @@ __global__ __launch_bounds__(256) void k_p2_sweep(const double* __restrict__ eo,
                                                   double w, double hl2, double* __restrict__ u, int64_t up,
                                                   const int* __restrict__ done) {
   if (*done) return;
-  const int x = 1 + blockIdx.x * 256 + threadIdx.x;
+  const int x = t2_x(blockIdx.x);
   if (x > N - 2) return;
   const int l = 1 << m, half = N >> 1;
   const int sx = p2_side(x, N, m);
@@ -2863,7 +2896,7 @@ __global__ __launch_bounds__(256) void k_p2_sweep(const double* __restrict__ eo,
   const int ax = tx ? N - 1 - x : x, cx = (ax >> m) << m;
   const int gx0 = tx ? N - 1 - cx : cx, gx1 = tx ? N - 1 - (cx + l) : cx + l;
   const double fx = double(ax - cx) / double(l);
-  const int y0 = 1 + blockIdx.y * P2_ROWS, y1 = min(N - 1, y0 + P2_ROWS);
+  const int y0 = t2_y0(blockIdx.y, P2_ROWS), y1 = min(N - 1, y0 + P2_ROWS);
   for (int y = y0; y < y1; ++y) {
     const int sy = p2_side(y, N, m);
     double v;
@@ -2936,7 +2969,7 @@ hipError_t launch_p2_sweep(int N, int m, double omega, const double* eo, double*
                            const int* done, hipStream_t s) {
   if (m < 1 || N < 4 || (N & (N - 1)) || fl.side != (N >> m)) return hipErrorInvalidValue;
   const double hl = double(1 << m) / double(N - 1);
-  const dim3 g((N - 2 + 255) / 256, (N - 2 + P2_ROWS - 1) / P2_ROWS);
+  const dim3 g(t2_gx(N), t2_gy(N, P2_ROWS));
   const double* e = eo + el.off;
   double* o = en + el.off;
   double* uu = u ? u + ul.off : nullptr;
@@ -2970,10 +3003,8 @@ hipError_t launch_p2_sweep(int N, int m, double omega, const double* eo, double*
 // a cycle retires its problem once the relative residual reaches the
 // tolerance.
 
-__device__ __forceinline__ int tiles_of(int side, int len) {
-  const int inner = side - 2;
-  return ((inner + BX2 - 1) / BX2) * ((inner + len - 1) / len);
-}
+// Tiles (workgroups) of a 2D stage: TW2 columns by four bands of len rows.
+__device__ __forceinline__ int tiles_of(int side, int len) { return t2_gx(side) * t2_gy(side, len); }
 
 struct StageInfo {
   int kind;   // BK_* below
@@ -3022,7 +3053,7 @@ __device__ __forceinline__ int stage_tiles(const BatchProblem& p, const StageInf
   switch (si.kind) {
     case BK_STAGE: {
       const int c = si.code;
-      if (bst_kind(c) == BST_L0) return (tb_waves(p.n, bst_count(c), batch_tb_len(p)) + 3) / 4;
+      if (bst_kind(c) == BST_L0) return tb_blocks(p.n, bst_count(c), batch_tb_len(p));
       if (bst_kind(c) == BST_SWEEP) return tiles_of(level_side(p, si.level), p.len[si.level]);
       const int nt = level_side(p, si.level - 1);  // hand-over target
       return nt >= 3 ? ((nt - 2 + BX2 - 1) / BX2) * ((nt - 2 + BATCH_XF_ROWS - 1) / BATCH_XF_ROWS) : 0;
@@ -3045,7 +3076,7 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
                                            const BatchRun& run) {
   using C = typename Tr<T>::C;
   const int n = p.n;
-  const int gx = (n - 2 + BX2 - 1) / BX2;
+  const int gx = t2_gx(n);
   const int bx = t % gx, by = t / gx;
   T* e0 = static_cast<T*>(p.e[0]);
   T* e1 = static_cast<T*>(p.e[1]);
@@ -3091,7 +3122,7 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
     }
     case BK_RESTRICT: {
       const int nc = (n - 1) / (2 << si.level) + 1;
-      const int gxc = (nc - 2 + BX2 - 1) / BX2;
+      const int gxc = t2_gx(nc);
       if (batch_top64<T>(p, si.level + 1))
         tile_restrict_2d<T, double>(static_cast<const T*>(p.r[si.level]), p.rp[si.level], p.r64, p.p64, nc,
                                     p.len[si.level + 1], t % gxc, t / gxc);
@@ -3112,9 +3143,9 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
         double* xn = p.x64[it & 1];
         T* xr = static_cast<T*>(p.x[m][it & 1]);
         const double hl = 1.0 / double(nm - 1), hl2 = hl * hl, w = run.omega / 4.0;
-        const int gxm = (nm - 2 + BX2 - 1) / BX2;
-        const int I = 1 + (t % gxm) * BX2 + threadIdx.x;
-        const int J0 = 1 + (t / gxm) * p.len[m], J1 = min(nm - 1, J0 + p.len[m]);
+        const int gxm = t2_gx(nm);
+        const int I = t2_x(t % gxm);
+        const int J0 = t2_y0(t / gxm, p.len[m]), J1 = min(nm - 1, J0 + p.len[m]);
         if (I <= nm - 2)
           for (int J = J0; J < J1; ++J) {
             const int64_t o = int64_t(J) * p.p64 + I;
@@ -3134,7 +3165,7 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
         T* xn = static_cast<T*>(p.x[m][it & 1]);
         const double hl = 1.0 / double(nm - 1);
         const C hl2 = C(hl * hl), w = C(run.omega / 4.0);
-        const int gxm = (nm - 2 + BX2 - 1) / BX2;
+        const int gxm = t2_gx(nm);
         const T* rm = static_cast<const T*>(p.r[m]);
         if (zero)
           tile_sweep_2d_l0<T, SW_ZERO_OLD, false>(xo, xn, p.rp[m], rm, p.rp[m], nullptr, 0, nullptr, 0, nm,
@@ -3279,10 +3310,7 @@ __global__ __launch_bounds__(256) void k_batch_init(BatchState* bs, int* done, i
 
 int default_walk_len(int d, int n) { return walk_len(d, n); }
 
-int batch_tiles(int side, int len) {
-  const int inner = side - 2;
-  return ((inner + BX2 - 1) / BX2) * ((inner + len - 1) / len);
-}
+int batch_tiles(int side, int len) { return t2_gx(side) * t2_gy(side, len); }
 
 hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds) {
   *lds = size_t(P + 1) * sizeof(int);
