@@ -904,16 +904,23 @@ struct L1Col3 {
     const int j0 = yb >> 1, nm1 = (n - 1) >> 1;  // arithmetic shift: yb may be -1
     const bool odd = (yb & 1) != 0;
     C xv[R];
+    if (zold) {
 #pragma unroll
-    for (int d = 0; d < R; ++d) {
-      if (zold) {
-        xv[d] = lerp(C(0), C(0), tx());
-      } else {
+      for (int d = 0; d < R; ++d) xv[d] = lerp(C(0), C(0), tx());
+    } else {
+      // the uniform test stays outside the row loop, so the rows' loads
+      // are issued together
+      C a0[R], a1[R];
+#pragma unroll
+      for (int d = 0; d < R; ++d) {
         // rows past the lattice only feed rows off the grid
         const int J = min(max(j0 + d, 0), nm1);
         const T* a = p + int64_t(K) * cpl + int64_t(J) * cp + I;
-        xv[d] = lerp(ld(a), ld(a + 1), tx());
+        a0[d] = ld(a);
+        a1[d] = ld(a + 1);
       }
+#pragma unroll
+      for (int d = 0; d < R; ++d) xv[d] = lerp(a0[d], a1[d], tx());
     }
     // row k lies in level-1 row j0 + (k + odd) / 2
     const C h = C(1) / C(2);
@@ -929,6 +936,13 @@ struct L1Col3 {
       return;
     }
     const int K = z >> 1;
+    // x_it at the lane's lattice position of each row, loaded for every
+    // lane (the index is in range for all) and kept only at level-1
+    // lattice nodes: no divergent branch around the loads
+    C lat[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      lat[k] = ld(q + int64_t(K) * cpl + int64_t(min(max((yb + k) >> 1, 0), (n - 1) >> 1)) * cp + I);
     if (K != band) {
       if (K == band + 1) {
 #pragma unroll
@@ -943,11 +957,8 @@ struct L1Col3 {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int y = yb + k;
-      C t;
-      if (xeven && (y & 1) == 0 && (z & 1) == 0)  // a level-1 lattice node
-        t = ld(q + int64_t(K) * cpl + int64_t(min(max(y >> 1, 0), (n - 1) >> 1)) * cp + I);
-      else
-        t = lerp(top[k], bot[k], tz);
+      const bool node = xeven && (y & 1) == 0 && (z & 1) == 0;  // a level-1 lattice node
+      const C t = node ? lat[k] : lerp(top[k], bot[k], tz);
       v[k] = (xin && y >= 1 && y <= n - 2) ? rnd<T>(t) : C(0);
     }
   }
