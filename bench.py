@@ -468,6 +468,50 @@ def in_cycle_section(P, W, torch, dev, reps=3):
     return out
 
 
+def other_forms_section(P, torch, probs, per, max_i, profile):
+    """The bench solves with one whole-grid launch per iteration (the
+    paper's form; temporal_block 0) and on the level-blocked path (the whole
+    grid written after every level): bit-identical results.  Their times
+    and cycles go into `per`; returns the single-sweep fused S+R kernel's
+    rate, level 0 and the coarse levels apart (from a profiled rerun)."""
+    single_sweep = {}
+    for p in probs:
+        for tb, key in ((0, "one_launch_per_iteration"), (1, "level_blocked")):
+            sc = P.Solver(p["d"], p["n"], max_i=max_i, temporal_block=tb)
+            times = []
+            for _ in range(4):
+                p["u"].zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = sc.solve(p["f"], p["u"], tol=1e-10)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            per[p["name"]][key + "_time_to_1e-10_s"] = sorted(times[1:])[1]
+            per[p["name"]][key + "_cycles"] = res["cycles"]
+            if tb == 0 and profile:
+                sc.set_profiling(True)
+                p["u"].zero_()
+                sc.solve(p["f"], p["u"], tol=1e-10)
+                agg = {"level0": [0, 0.0, 0.0], "coarse": [0, 0.0, 0.0]}
+                for e in sc.profile():
+                    if e["kind"] != "sweep":
+                        continue
+                    a = agg["level0" if e["level"] == 0 else "coarse"]
+                    a[0] += e["launches"]
+                    a[1] += e["ms"]
+                    a[2] += kernel_bytes(p["d"], p["n"], e)
+                single_sweep[p["name"]] = {
+                    k2: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                         "alg_GBps": v[2] / 1e9 / (v[1] / 1e3) if v[1] > 0 else None,
+                         "frac": (v[2] / 1e9 / (v[1] / 1e3)) / HBM_PEAK_GBS if v[1] > 0 else None}
+                    for k2, v in agg.items()}
+            sc.close()
+    return single_sweep
+
+
+SECTIONS = ("other_forms", "mixed", "batched", "learned", "paper", "pow2", "in_cycle")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,6 +528,9 @@ def main():
     ap.add_argument("--no-in-cycle", action="store_true", help="skip the in-cycle restriction comparison")
     ap.add_argument("--no-level-blocked", action="store_true",
                     help="skip the level-blocked comparison solves (profiling runs of the default path)")
+    ap.add_argument("--only", choices=SECTIONS,
+                    help="run only this section (no timed steps) and print its JSON: one profiler "
+                         "run per section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -510,6 +557,12 @@ def main():
                           "launches": 5}), flush=True)
         return
 
+    if args.only and args.only != "other_forms":
+        fn = {"mixed": mixed_precision_section, "batched": batched_section, "learned": learned_section,
+              "paper": paper_section, "pow2": pow2_section, "in_cycle": in_cycle_section}[args.only]
+        print(json.dumps({"section": args.only, "result": fn(P, W, torch, dev)}), flush=True)
+        return
+
     probs = []
     for name, d, n in PROBLEMS:
         f = torch.from_numpy(W.uniform(d, n, seed=0)).to(dev)
@@ -519,6 +572,12 @@ def main():
         probs.append({"name": name, "d": d, "n": n, "f": f, "u": u, "s": s, "spc": sweeps_per_cycle,
                       "rpc": relaxations_per_cycle(d, n, s.schedule())})
     torch.cuda.synchronize()
+    if args.only == "other_forms":
+        per = {p["name"]: {} for p in probs}
+        sw = other_forms_section(P, torch, probs, per, args.max_i, not args.no_profile)
+        print(json.dumps({"section": "other_forms", "result": {"problems": per, "fused_sr_single_sweep": sw}}),
+              flush=True)
+        return
 
     def step(record):
         for p in probs:
@@ -610,42 +669,9 @@ def main():
                             "computed by every execution form; bytes: each launched kernel's compulsory "
                             "traffic (kernels of the profiled rerun of the same steps)"}
 
-    # the same solves with one whole-grid launch per iteration (the paper's
-    # form; temporal_block 0) and on the level-blocked path (the whole grid
-    # written after every level): bit-identical results
     single_sweep = {}
-    for p in ([] if args.no_level_blocked else probs):
-        for tb, key in ((0, "one_launch_per_iteration"), (1, "level_blocked")):
-            sc = P.Solver(p["d"], p["n"], max_i=args.max_i, temporal_block=tb)
-            times = []
-            for _ in range(4):
-                p["u"].zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                res = sc.solve(p["f"], p["u"], tol=1e-10)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-            per[p["name"]][key + "_time_to_1e-10_s"] = sorted(times[1:])[1]
-            per[p["name"]][key + "_cycles"] = res["cycles"]
-            if tb == 0 and not args.no_profile:
-                # the single-sweep fused S+R kernel, level 0 and coarse levels apart
-                sc.set_profiling(True)
-                p["u"].zero_()
-                sc.solve(p["f"], p["u"], tol=1e-10)
-                agg = {"level0": [0, 0.0, 0.0], "coarse": [0, 0.0, 0.0]}
-                for e in sc.profile():
-                    if e["kind"] != "sweep":
-                        continue
-                    a = agg["level0" if e["level"] == 0 else "coarse"]
-                    a[0] += e["launches"]
-                    a[1] += e["ms"]
-                    a[2] += kernel_bytes(p["d"], p["n"], e)
-                single_sweep[p["name"]] = {
-                    k2: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
-                         "alg_GBps": v[2] / 1e9 / (v[1] / 1e3) if v[1] > 0 else None,
-                         "frac": (v[2] / 1e9 / (v[1] / 1e3)) / HBM_PEAK_GBS if v[1] > 0 else None}
-                    for k2, v in agg.items()}
-            sc.close()
+    if not args.no_level_blocked:
+        single_sweep = other_forms_section(P, torch, probs, per, args.max_i, not args.no_profile)
     for p in probs:
         p["s"].close()
     mixed = None

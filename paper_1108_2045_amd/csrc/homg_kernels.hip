@@ -383,9 +383,12 @@ __global__ __launch_bounds__(256) void k_residual_2d(
 }
 
 // 3D residual: a lane owns R3Y consecutive y rows (as the level-0 sweep),
-// walks of 8 planes.  The x neighbours come from the neighbour lanes (DPP
-// wave shifts; lanes past the grid hold the boundary column); only lanes 0
-// and 63 load the column just outside the tile.
+// walks of RES3_LEN planes.  The x neighbours come from the neighbour lanes
+// (DPP wave shifts; lanes past the grid hold the boundary column); only
+// lanes 0 and 63 load the column just outside the tile.  The grid is 1D and
+// XCD-ordered (x tiles fastest, then y, then z), so the tiles that share
+// halo rows and cache lines run on the same XCD and its L2.
+constexpr int RES3_LEN = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_residual_3d(
     const double* __restrict__ u, int64_t up, int64_t upl, const double* __restrict__ f,
@@ -393,10 +396,13 @@ __global__ __launch_bounds__(256) void k_residual_3d(
     double inv_h2, double* __restrict__ partials, const int* __restrict__ done) {
   if (*done) return;
   constexpr int R = 4;  // = R3Y (declared with the sweeps below)
+  const int gx = (n - 2 + BX3 - 1) / BX3, gy = (n - 2 + BY3 * R - 1) / (BY3 * R);
+  const int lg = int(xcd_order(blockIdx.x, gridDim.x));
+  const int bx = lg % gx, by = (lg / gx) % gy, bz = lg / (gx * gy);
   const int lane = threadIdx.x;
-  const int x = 1 + blockIdx.x * BX3 + lane;
-  const int yb = 1 + (blockIdx.y * BY3 + __builtin_amdgcn_readfirstlane(int(threadIdx.y))) * R;
-  const int z0 = 1 + blockIdx.z * len;
+  const int x = 1 + bx * BX3 + lane;
+  const int yb = 1 + (by * BY3 + __builtin_amdgcn_readfirstlane(int(threadIdx.y))) * R;
+  const int z0 = 1 + bz * len;
   const int z1 = min(n - 1, z0 + len);
   const bool xin = x <= n - 2;
   const int xc = min(x, n - 1);
@@ -449,8 +455,7 @@ __global__ __launch_bounds__(256) void k_residual_3d(
     }
   }
   s = block_sum<256>(s);
-  if (threadIdx.x == 0 && threadIdx.y == 0)
-    partials[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+  if (threadIdx.x == 0 && threadIdx.y == 0) partials[lg] = s;
 }
 
 // 2D residual with the restriction to level 1 fused in.  Each wave walks a
@@ -2164,9 +2169,9 @@ static hipError_t residual_t(int d, int n, const double* u, const Lay& ul, const
                 fl.pitch, (const double*)nullptr, int64_t(0), r, rl.pitch, n, len, inv_h2,
                 partials, done);
   }
-  const int inner = n - 2, len3 = inner < 8 ? inner : 8;
-  const dim3 g3((inner + BX3 - 1) / BX3, (inner + 4 * BY3 - 1) / (4 * BY3), (inner + len3 - 1) / len3);
-  *count = int(g3.x * g3.y * g3.z);
+  const int inner = n - 2, len3 = inner < RES3_LEN ? inner : RES3_LEN;
+  const dim3 g3(((inner + BX3 - 1) / BX3) * ((inner + 4 * BY3 - 1) / (4 * BY3)) * ((inner + len3 - 1) / len3));
+  *count = int(g3.x);
   HOMG_LAUNCH((k_residual_3d<T>), g3, dim3(BX3, BY3), s, u + ul.off, ul.pitch, ul.plane,
               f + fl.off, fl.pitch, fl.plane, r, rl.pitch, rl.plane, n, len3, inv_h2, partials,
               done);
