@@ -272,6 +272,7 @@ def batched_section(P, W, torch, dev, count=512, reps=3):
     t0 = time.perf_counter()
     bs.tune(fs, us, tol=1e-10)
     tune_s = time.perf_counter() - t0
+    log("batched: tuned in %.2f s" % tune_s)
     times, res = [], None
     for _ in range(reps + 1):
         for u in us:
@@ -281,6 +282,7 @@ def batched_section(P, W, torch, dev, count=512, reps=3):
         res = bs.solve(fs, us, tol=1e-10, raise_on_status=False)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+        log("batched: solve %d in %.3f s" % (len(times), times[-1]))
     t = sorted(times[1:])[len(times[1:]) // 2]
     sweeps, relax = {}, {}
     for s in set(sides):
@@ -296,8 +298,10 @@ def batched_section(P, W, torch, dev, count=512, reps=3):
         u.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for f, u, s in zip(fs, us, sides):
+    for i, (f, u, s) in enumerate(zip(fs, us, sides)):
         solvers[s].solve(f, u, tol=1e-10, raise_on_status=False)
+        if i % 128 == 127:
+            log("batched: one by one, %d problems done" % (i + 1))
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     out = {"workload": "%d 2D Poisson problems, sides uniform from {65,129,257,513,1025} (seed 0), "
@@ -327,11 +331,13 @@ def learned_section(P, W, torch, dev, n=1025, train_seeds=range(100, 164), held_
 
     t0 = time.perf_counter()
     tr = P.Trainer()
-    for seed in train_seeds:
+    for i, seed in enumerate(train_seeds):
         a, f = W.grf_problem(n, seed=seed)
         s = solver(a)
         tr.add_problem(s, torch.from_numpy(f).to(dev), cycles=pair_cycles)
         s.close()
+        if i % 16 == 15:
+            log("learned: pairs of %d problems generated" % (i + 1))
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     # start: damped Jacobi (omega 0.8) plus small seeded noise on every weight,
@@ -344,6 +350,7 @@ def learned_section(P, W, torch, dev, n=1025, train_seeds=range(100, 164), held_
     w, hist = tr.train(w0, steps=steps, batch=batch, lr=lr, seed=1)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    log("learned: trained %d steps in %.2f s" % (steps, train_s))
     loss1 = tr.loss(w)
     samples = tr.count()
     tr.close()
@@ -371,6 +378,8 @@ def learned_section(P, W, torch, dev, n=1025, train_seeds=range(100, 164), held_
                            "final_relres": res["final_relres"], "converged": res["converged"],
                            "fell_back": res["smoother_fell_back"]}
         entry["speedup_learned_vs_jacobi"] = entry["jacobi"]["time_to_1e-10_s"] / entry["learned"]["time_to_1e-10_s"]
+        if not held:
+            entry["learned_kernel"] = learned_kernel_rate(s, fd, n, torch)
         held.append(entry)
         log("learned held-out %d: %s" % (seed, entry))
         s.close()
@@ -384,6 +393,37 @@ def learned_section(P, W, torch, dev, n=1025, train_seeds=range(100, 164), held_
             "gate_accepted": accepted, "held_out": held,
             "geomean_speedup_learned_vs_jacobi": float(np.exp(np.mean(
                 [np.log(h["speedup_learned_vs_jacobi"]) for h in held])))}
+
+
+LEARNED_MACS_PER_NODE = 576       # 3 features x 16 channels x 9 taps + 16 channels x 9 taps
+LEARNED_MFMA_FLOPS_PER_NODE = 5 * 16 * 32 * 2  # five 16x16x32 MFMAs per 16 nodes of the halo-1 region
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def learned_kernel_rate(s, f, n, torch):
+    """The learned relaxation's level-0 iteration in one profiled learned
+    solve: time per launch, useful FLOP rate (the network's 576 MACs per
+    interior node) and the FLOP rate the matrix cores execute (the
+    three-part BF16 split of the activations, the zero-padded K slots and
+    the halo recompute of 16 x 16 regions for 14 x 14 owned nodes), both
+    against the dense BF16 MFMA peak."""
+    u = torch.zeros_like(f)
+    s.set_profiling(True)
+    s.solve(f, u, tol=1e-10, raise_on_status=False)
+    ent = [e for e in s.profile() if e["kind"] == "learned" and e["level"] == 0]
+    s.set_profiling(False)  # (clears the accumulated entries)
+    launches = sum(e["launches"] for e in ent)
+    if not launches:
+        return None
+    t = sum(e["ms"] for e in ent) / 1e3 / launches
+    nodes = float(n - 2) ** 2
+    tiles = ((n - 2 + 13) // 14) ** 2
+    useful = 2.0 * LEARNED_MACS_PER_NODE * nodes / t / 1e12
+    executed = LEARNED_MFMA_FLOPS_PER_NODE * 256.0 * tiles / t / 1e12
+    return {"level0_launches": launches, "level0_avg_us": 1e6 * t,
+            "useful_TFLOPs": useful, "executed_mfma_TFLOPs": executed,
+            "peak_TFLOPs": BF16_MFMA_PEAK_TFLOPS, "useful_frac": useful / BF16_MFMA_PEAK_TFLOPS,
+            "executed_frac": executed / BF16_MFMA_PEAK_TFLOPS}
 
 
 def paper_section(P, W, torch, dev, sizes=(65, 129, 257, 513, 1025)):

@@ -994,10 +994,15 @@ __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict
                                          L1Col2<T>& lc) {
   using C = typename Tr<T>::C;
   C xl[U], rl[U];
+  double uo[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {  // rows past the grid read the boundary row (zero)
     rl[k] = ld(r + int64_t(min(max(ys + k - 1, 0), n - 1)) * rp + xc);
     if (!LAT) xl[k] = ZERO ? C(0) : ld(eo + int64_t(min(ys + k, n - 1)) * ep + xc);
+    // the old value of the u entry emitted at step k (row ys + k - IT),
+    // loaded with the rows; lanes and steps that emit nothing read a row
+    // of the band (clamped), so the load needs no branch
+    if (ACCUM) uo[k] = u[int64_t(min(max(ys + k - IT, Y0), Y1 - 1)) * up + xc];
   }
   if (LAT) {
     if constexpr (U == 4) {
@@ -1029,7 +1034,7 @@ __device__ __forceinline__ void tb_steps(const T* __restrict__ eo, T* __restrict
         win[t][2] = in ? rnd<T>(v) : C(0);
       } else if (emit && in && y >= Y0 && y < Y1) {
         if (ACCUM)
-          add_to(u + int64_t(y) * up + x, double(v));
+          st(u + int64_t(y) * up + x, uo[k] + double(v));
         else
           st(en + int64_t(y) * ep + x, v);
         if (PREV) st(eprev + int64_t(y) * ep + x, c);  // the iterate before the last
@@ -1080,7 +1085,11 @@ __device__ __forceinline__ void tb_body(const T* __restrict__ eo, T* __restrict_
 }
 
 template <typename T, bool ZERO, bool ACCUM, int IT, bool LAT>
-__global__ __launch_bounds__(256) void k_sweep_2d_l0_tb(
+// Five waves per SIMD: the u loads issued with the rows take the pass from
+// 94 to 108 VGPRs, which would leave four waves per SIMD and a second round
+// of waves at 4097^2 (4736 waves, 4096 resident); held at 96 VGPRs (12 bytes
+// spilled) it runs 101 us against 115 us with the dependent reads.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_sweep_2d_l0_tb(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r, int64_t rp,
     double* __restrict__ u, int64_t up, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2,
     const int* __restrict__ done, L1Src<T> l1) {

@@ -21,8 +21,8 @@
 // The work is a dense 576-MAC contraction per node over LDS-resident tiles:
 // a workgroup owns a 14 x 14 block of lattice nodes and stages x and a on
 // its 20 x 20 halo region, the features on 18 x 18 and the hidden layer on
-// 16 x 16 (one node per lane, all 16 channels in registers, weights from
-// scalar loads).
+// 16 x 16; both channel contractions run on the matrix cores (see the
+// inference section below).
 //
 // Training kernels (FP32, dense compact arrays): forward writes z = delta -
 // y; backward recomputes the tile's features and hidden layer, forms
