@@ -2950,12 +2950,19 @@ __global__ __launch_bounds__(256) void k_p2_sweep(const double* __restrict__ eo,
   const int x = t2_x(blockIdx.x);
   if (x > N - 2) return;
   const int l = 1 << m, half = N >> 1;
+  // 1 / l is exact (l a power of two), so the weights below equal the
+  // quotients (ax - cx) / l bit for bit without a division per node
+  const double inv_l = 1.0 / double(l);
   const int sx = p2_side(x, N, m);
   const int tx = x >= half ? 1 : 0;
   const int ax = tx ? N - 1 - x : x, cx = (ax >> m) << m;
   const int gx0 = tx ? N - 1 - cx : cx, gx1 = tx ? N - 1 - (cx + l) : cx + l;
-  const double fx = double(ax - cx) / double(l);
+  const double fx = double(ax - cx) * inv_l;
   const int y0 = t2_y0(blockIdx.y, P2_ROWS), y1 = min(N - 1, y0 + P2_ROWS);
+  // the corners of the lattice cell last interpolated from (the walk
+  // reloads them only when a row lies in another cell)
+  int cell = -1;
+  double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
   for (int y = y0; y < y1; ++y) {
     const int sy = p2_side(y, N, m);
     double v;
@@ -2980,10 +2987,18 @@ __global__ __launch_bounds__(256) void k_p2_sweep(const double* __restrict__ eo,
       const int ty = y >= half ? 1 : 0;
       const int ay = ty ? N - 1 - y : y, cy = (ay >> m) << m;
       const int gy0 = ty ? N - 1 - cy : cy, gy1 = ty ? N - 1 - (cy + l) : cy + l;
-      const double fy = double(ay - cy) / double(l);
-      const double* r0 = eo + int64_t(gy0) * ep;
-      const double* r1 = eo + int64_t(gy1) * ep;
-      v = lerp(lerp(r0[gx0], r0[gx1], fx), lerp(r1[gx0], r1[gx1], fx), fy);
+      const double fy = double(ay - cy) * inv_l;
+      const int key = gy0 * 2 + ty;
+      if (key != cell) {
+        const double* r0 = eo + int64_t(gy0) * ep;
+        const double* r1 = eo + int64_t(gy1) * ep;
+        c00 = r0[gx0];
+        c01 = r0[gx1];
+        c10 = r1[gx0];
+        c11 = r1[gx1];
+        cell = key;
+      }
+      v = lerp(lerp(c00, c01, fx), lerp(c10, c11, fx), fy);
     }
     if (MODE & SW_ACCUM)
       add_to(u + int64_t(y) * up + x, v);
