@@ -139,10 +139,12 @@ hipError_t launch_lattice_2d_tb(int prec, int nm, int it, double omega, const vo
 // store x_{it-1}; l1: the input iterate from the next coarser level's
 // state (not with zero).  A block walks
 // `len` planes (0: tb3_band's choice: the longest of 32, 16, 8 planes that
-// still gives TB3_MIN_BLOCKS blocks, else 4; at 257^3 that is 32 planes in
-// 880 blocks, measured 3-8% faster per pass than 16 planes in 1760).
+// still gives TB3_MIN_BLOCKS blocks, else 4; at 257^3 that is 16 planes in
+// 1760 blocks, measured 5% faster per pass than 32 planes in 880 -- 119
+// against 126 us for the pass that adds into u -- and at 513^3 level 0
+// keeps 32 planes).
 constexpr int TB3_MAX_IT = 2;
-constexpr int TB3_MIN_BLOCKS = 768;
+constexpr int TB3_MIN_BLOCKS = 1536;
 int tb3_blocks(int n, int it, int len);
 int tb3_band(int n, int it);
 hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, void* en, void* eprev,

@@ -582,17 +582,18 @@ def test_mixed_precision_refinement(B, torch_cuda, d, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_3d_reduced_precision_large_bands_bitwise(B, torch_cuda, prec):
-    """3D 257^3 in FP32 / BF16: level 0 and the 129^3 lattice walk 32-plane
-    bands, and the large compact lattices run multi-iteration passes.  One
-    cycle must give the same bits with one launch per iteration, level
-    blocking and chaining."""
+@pytest.mark.parametrize("n", [257, 513])
+def test_3d_reduced_precision_large_bands_bitwise(B, torch_cuda, prec, n):
+    """3D in FP32 / BF16 at full sizes: level 0 walks 16-plane bands at 257^3
+    (1760 blocks) and 32-plane bands at 513^3, the 257^3 lattice of the
+    513^3 grid 16-plane bands, and the large compact lattices run
+    multi-iteration passes.  One cycle must give the same bits with one
+    launch per iteration, level blocking and chaining."""
     torch = torch_cuda
-    n = 257
     f = dev(torch, W.uniform(3, n, seed=22))
     outs = []
     for blocked in (0, 1, 2):
-        say("3D 257^3 %s temporal_block=%d" % (prec, blocked))
+        say("3D %d^3 %s temporal_block=%d" % (n, prec, blocked))
         s = B.Solver(3, n, precision=prec, temporal_block=blocked)
         u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
         s.solve_cycles(f, u, 1)
