@@ -396,17 +396,18 @@ def learned_section(P, W, torch, dev, n=1025, train_seeds=range(100, 164), held_
 
 
 LEARNED_MACS_PER_NODE = 576       # 3 features x 16 channels x 9 taps + 16 channels x 9 taps
-LEARNED_MFMA_FLOPS_PER_NODE = 5 * 16 * 32 * 2  # five 16x16x32 MFMAs per 16 nodes of the halo-1 region
+LEARNED_MFMA_FLOPS_PER_NODE = 8 * 16 * 32 * 2  # eight 16x16x32 MFMAs per 16 nodes of the halo-1 region
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def learned_kernel_rate(s, f, n, torch):
     """The learned relaxation's level-0 iteration in one profiled learned
     solve: time per launch, useful FLOP rate (the network's 576 MACs per
-    interior node) and the FLOP rate the matrix cores execute (the
-    three-part BF16 split of the activations, the zero-padded K slots and
-    the halo recompute of 16 x 16 regions for 14 x 14 owned nodes), both
-    against the dense BF16 MFMA peak."""
+    interior node) and the FLOP rate the matrix cores execute (six
+    first-layer and two second-layer MFMAs per 16-node row: the three-part
+    BF16 split of the activations, the zero-padded K slots and the halo
+    recompute of 16 x 16 regions for 14 x 14 owned nodes), both against the
+    dense BF16 MFMA peak."""
     u = torch.zeros_like(f)
     s.set_profiling(True)
     s.solve(f, u, tol=1e-10, raise_on_status=False)

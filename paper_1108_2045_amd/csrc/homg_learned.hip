@@ -215,9 +215,10 @@ __device__ __forceinline__ float tile_output(const TileLds<C>& L, const float* _
 // arithmetic on the matrix cores.
 //
 // Per 16-node row of the tile's halo-1 region (four rows per wave):
-//   first layer  D1[c][node] = sum_t W1[c][t] F[t][node], t = 3 tap + ci
-//     (27 of 32 K slots; the rest have zero weights), with the features F
-//     read from LDS already split (three MFMAs, one per part);
+//   first layer  D1[c][node] = sum_s W1[c][s] F[s][node] over K slots
+//     s = 12 dy + 4 dx + ci of the 3 x 3 window (27 of 64 slots carry
+//     weights), with the features F read from LDS already split, four BF16
+//     per node (two MFMAs per part, six in all);
 //   H = max(D1, 0) on interior nodes, 0 elsewhere -- the lane holds
 //     channels 4g .. 4g+3 of its node, which is exactly the B operand the
 //     second layer needs, so H never leaves registers;
@@ -226,7 +227,6 @@ __device__ __forceinline__ float tile_output(const TileLds<C>& L, const float* _
 //     and zeros: two MFMAs), written to LDS;
 // and after a barrier the output at a node is y = sum_k Z[k][node + o_k].
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct Parts {  // an FP32 value as three BF16 parts, in the upper halves of FP32 words
@@ -256,38 +256,44 @@ __device__ __forceinline__ uint32_t pair16(uint32_t lo_word, uint32_t hi_word) {
 }
 
 constexpr int ZS = 12;            // Z row stride in floats (taps 0..8, 16-byte rows)
-constexpr int FPART = 3 * FPL;    // one part of the three feature planes, in u16
 
 template <typename C>
 struct InferLds {
   float z[NT * ZS];               // Z[node][tap] on the halo-1 region
   C x[2][R3 * R3];                // x on the halo-3 region, two tiles in flight
   float a[R3 * R3];               // coefficient on the halo-3 region
-  uint16_t fb[3 * FPART];         // features: part, channel plane, node
+  uint64_t fb[3 * FPL];           // features: part, node; four BF16 each (channels 0-2, then 0)
 };
 
-// The lane's operands that do not change from tile to tile.
+// The lane's operands that do not change from tile to tile.  First-layer K
+// slot s (two MFMAs, s in [0, 64)) holds channel s % 4 of feature node
+// (dy, dx) = (s / 12, (s % 12) / 4) of the 3 x 3 window (channel 3 and
+// s >= 36 are zero weights): with the features stored as four BF16 per
+// node, a lane's eight slots of the first MFMA are two whole nodes and
+// those of the second one node (lanes 0-15) or nothing.
 struct LaneConst {
-  bf16x8 w1, w2a, w2b;  // A operands: first layer; second layer, both MFMAs
-  int lb[8];            // feature index of K slot e relative to the row's window
+  bf16x8 w1a, w1b, w2a, w2b;  // A operands: first layer (two MFMAs); second layer (two)
 };
 
 __device__ __forceinline__ LaneConst lane_const(const float* __restrict__ w) {
   const int lane = threadIdx.x & 63;
   const int ii = lane & 15, g = lane >> 4;
-  float v1[8], va[8], vb[8];
+  float va1[8], vb1[8], va[8], vb[8];
   LaneConst k;
+  auto w1 = [&](int s) {  // W1[c = ii][ci][tap] at K slot s
+    const int dy = s / 12, dx = (s % 12) / 4, ci = s % 4;
+    return s < 36 && ci < 3 ? w[ii * 27 + ci * 9 + 3 * dy + dx] : 0.f;
+  };
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const int t = 8 * g + e, tap = t / 3, ci = t % 3;
-    v1[e] = t < 27 ? w[ii * 27 + ci * 9 + tap] : 0.f;               // W1[c = ii][ci][tap]
+    va1[e] = w1(8 * g + e);
+    vb1[e] = w1(32 + 8 * g + e);
     const float w2 = ii < 9 ? w[NW1 + (4 * g + (e & 3)) * 9 + ii] : 0.f;  // W2[c][tap = ii]
     va[e] = w2;
     vb[e] = e < 4 ? w2 : 0.f;
-    // unused slots read a valid feature (their weights are zero)
-    k.lb[e] = t < 27 ? ii + ci * FPL + (tap / 3) * R2 + (tap % 3) : ii + R2 + 1;
   }
-  k.w1 = pack8(v1);
+  k.w1a = pack8(va1);
+  k.w1b = pack8(vb1);
   k.w2a = pack8(va);
   k.w2b = pack8(vb);
   return k;
@@ -369,16 +375,13 @@ __device__ __forceinline__ void put_features(InferLds<C>& L, const C* X, int q, 
     }
   }
   const Parts p0 = split3(f0), p1 = split3(f1), p2 = split3(f2);
-  uint16_t* fb = L.fb + q;
-  fb[0] = uint16_t(p0.hi >> 16);
-  fb[FPL] = uint16_t(p1.hi >> 16);
-  fb[2 * FPL] = uint16_t(p2.hi >> 16);
-  fb[FPART] = uint16_t(p0.mid >> 16);
-  fb[FPART + FPL] = uint16_t(p1.mid >> 16);
-  fb[FPART + 2 * FPL] = uint16_t(p2.mid >> 16);
-  fb[2 * FPART] = uint16_t(p0.lo >> 16);
-  fb[2 * FPART + FPL] = uint16_t(p1.lo >> 16);
-  fb[2 * FPART + 2 * FPL] = uint16_t(p2.lo >> 16);
+  // one 8-byte store per part: channels 0, 1, 2 and a zero
+  auto node = [](uint32_t c0, uint32_t c1, uint32_t c2) {
+    return uint64_t(pair16(c0, c1)) | (uint64_t(c2 >> 16) << 32);
+  };
+  L.fb[q] = node(p0.hi, p1.hi, p2.hi);
+  L.fb[FPL + q] = node(p0.mid, p1.mid, p2.mid);
+  L.fb[2 * FPL + q] = node(p0.lo, p1.lo, p2.lo);
 }
 
 // Both layers for row jj of the halo-1 region (row J of the lattice); Z to LDS.
@@ -387,18 +390,21 @@ __device__ __forceinline__ void row_contract(InferLds<C>& L, const LaneConst& k,
                                              bool col_in) {
   const int lane = threadIdx.x & 63;
   const int ii = lane & 15, g = lane >> 4;
-  const uint16_t* fb = L.fb + jj * R2;
-  u16x8 fh, fm, fl;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    fh[e] = fb[k.lb[e]];
-    fm[e] = fb[k.lb[e] + FPART];
-    fl[e] = fb[k.lb[e] + 2 * FPART];
-  }
+  // the lane's window nodes (see lane_const): first MFMA two nodes, second
+  // MFMA node (2, 2) for lanes 0-15 (read by all lanes, kept by those)
+  const int na = g == 0 ? 0 : g == 1 ? 2 : g == 2 ? R2 + 1 : 2 * R2;
+  const int nb = g == 0 ? 1 : g == 1 ? R2 : g == 2 ? R2 + 2 : 2 * R2 + 1;
+  const uint64_t* fb = L.fb + jj * R2 + ii;
   f32x4 d = {0.f, 0.f, 0.f, 0.f};
-  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1, __builtin_bit_cast(bf16x8, fh), d, 0, 0, 0);
-  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1, __builtin_bit_cast(bf16x8, fm), d, 0, 0, 0);
-  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1, __builtin_bit_cast(bf16x8, fl), d, 0, 0, 0);
+#pragma unroll
+  for (int part = 0; part < 3; ++part) {
+    const uint64_t* fp = fb + part * FPL;
+    const uint64_t b1[2] = {fp[na], fp[nb]};
+    const uint64_t c = fp[2 * R2 + 2];
+    const uint64_t b2[2] = {g == 0 ? c : uint64_t(0), uint64_t(0)};
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1a, __builtin_bit_cast(bf16x8, b1), d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(k.w1b, __builtin_bit_cast(bf16x8, b2), d, 0, 0, 0);
+  }
   const bool in = row_in && col_in;
   Parts h[4];
 #pragma unroll
