@@ -143,6 +143,13 @@ void build_schedule(homg_batch_ctx* b) {
     b->sweep_levels.insert(b->sweep_levels.end(), codes.begin(), codes.end());
     max_cycle_len = std::max(max_cycle_len, q.top + q.sweeps + 2);
   }
+  // each problem's tiles per stage of a cycle, filled on the device
+  // (launch_batch_tile_table) so that a step looks its tile count up
+  for (int i = 0; i < b->count; ++i) {
+    BatchProblem& q = b->h_probs[i];
+    q.tile_off = int(b->sweep_levels.size());
+    b->sweep_levels.insert(b->sweep_levels.end(), size_t(q.top + q.sweeps + 2), 0);
+  }
   b->max_steps = 4 + (b->max_cycles + 1) * max_cycle_len;
 }
 
@@ -175,6 +182,7 @@ homg_status run_once(homg_batch_ctx* b, const double* const* f, double* const* u
     b->graph = g;
     BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
   }
+  BHIP(b, launch_batch_tile_table(b->count, b->d_probs, b->d_sweep_levels, s));
   BHIP(b, launch_batch_init(b->count, b->d_state, b->d_done, b->d_sync, s));
   // replays of 64 steps until a step finds no active problem (or the step
   // bound of max_cycles is reached)
@@ -266,8 +274,9 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     p.part = take(sizeof(double) * size_t(batch_tiles(n, 1)));
     p.hist = take(sizeof(double) * size_t(b->max_cycles + 1));
     // the stage table is sized for one iteration per level-0 pass, the
-    // longest sequence any pass depth gives
-    b->sched_cap += stage_codes(L, b->max_i, 1).size();
+    // longest sequence any pass depth gives: the codes and the row of
+    // tiles per stage (restrictions, codes, residual, finalize)
+    b->sched_cap += 2 * stage_codes(L, b->max_i, 1).size() + size_t(L - 1) + 2;
   }
   homg_status st = HOMG_OK;
   if (hipMalloc(&b->arena, total) != hipSuccess) {

@@ -269,7 +269,8 @@ struct BatchProblem {         // one problem, read by the step kernels
   double* partials;           // per-tile norm sums
   double* history;            // relres after cycles 0..max_cycles
   int n, levels, top, sweeps; // side, levels, coarsest level visited, iteration stages per cycle
-  int sched_off, id, pad0, pad1;
+  int sched_off, id;           // offset of the stage codes in the table; problem index
+  int tile_off, pad1;          // offset of the tiles-per-stage row (one cycle) in the table
 };
 struct BatchState {
   int cycles;
@@ -294,6 +295,10 @@ int default_walk_len(int d, int n);
 int batch_tiles(int side, int len);
 // Reset of the per-solve state (problem states, done flags, step counter).
 hipError_t launch_batch_init(int P, BatchState* bs, int* done, BatchSync* sync, hipStream_t s);
+// Fill every problem's tiles-per-stage row of the table (stages 4 .. of one
+// cycle, at table[tile_off ..]) from its stage codes and tile shapes; run
+// after the table and the problems are uploaded, before the steps.
+hipError_t launch_batch_tile_table(int P, const BatchProblem* probs, int* table, hipStream_t s);
 // Graph of BATCH_STEPS_PER_REPLAY step kernels (steps base .. base + S - 1 of
 // every problem's sequence, each tile of a step one workgroup) and the
 // advance of base.

@@ -3298,7 +3298,8 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
 
 // One step of every active problem's sequence: k = base + j.  Every
 // workgroup builds the same tile map (prefix sums of the active problems'
-// tile counts for their stage at step k) and takes the tiles g = blockIdx.x,
+// tile counts for their stage at step k, looked up in each problem's row
+// of tiles per stage) and takes the tiles g = blockIdx.x,
 // blockIdx.x + gridDim.x, ...  A problem is active in step k unless it
 // retired in an earlier step; the step that retires it is written by its
 // finalize tile while other workgroups may be building this step's map,
@@ -3320,26 +3321,34 @@ __global__ __launch_bounds__(256) void k_batched_step(const BatchProblem* __rest
   for (int i = threadIdx.x; i < P; i += 256) {
     const BatchProblem& p = probs[i];
     const int ret = __hip_atomic_load(&bs[i].retired, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pref[i + 1] = ret < k ? 0 : stage_tiles(p, stage_of(p, levels_of_sweep, k));
+    int tiles = 0;
+    if (ret >= k)  // the row of tiles per stage of a cycle (k_batch_tile_table)
+      tiles = k < 4 ? stage_tiles(p, stage_of(p, levels_of_sweep, k))
+                    : levels_of_sweep[p.tile_off + (k - 4) % (p.top + p.sweeps + 2)];
+    pref[i + 1] = tiles;
   }
   if (threadIdx.x == 0) pref[0] = 0;
   __syncthreads();
-  // serial scan by chunks: each thread scans its chunk, then offsets
+  // scan by chunks: each thread scans its own chunk, the chunk totals are
+  // scanned across the workgroup (within each wave by shuffles, then the
+  // four wave totals), and each thread adds its chunk's offset
   const int chunk = (P + 255) / 256;
   const int lo = threadIdx.x * chunk + 1, hi = min(P, lo + chunk - 1);
   int acc = 0;
   for (int i = lo; i <= hi; ++i) { acc += pref[i]; pref[i] = acc; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int off = 0;
-    for (int c = 0; c < 256; ++c) {
-      const int clo = c * chunk + 1, chi = min(P, clo + chunk - 1);
-      if (clo > P) break;
-      const int last = pref[chi];
-      for (int i = clo; i <= chi; ++i) pref[i] += off;
-      off += last;
-    }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = acc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
   }
+  __shared__ int wave_total[4];
+  if (lane == 63) wave_total[wave] = incl;
+  __syncthreads();
+  int off = incl - acc;
+  for (int q = 0; q < wave; ++q) off += wave_total[q];
+  for (int i = lo; i <= hi; ++i) pref[i] += off;
   __syncthreads();
   const int total = pref[P];
   if (total == 0) {
@@ -3360,6 +3369,12 @@ __global__ __launch_bounds__(256) void k_batched_step(const BatchProblem* __rest
     batch_tile<T>(p, bs, done, si, g - pref[a], run);
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void k_batch_tile_table(const BatchProblem* __restrict__ probs, int* table) {
+  const BatchProblem& p = probs[blockIdx.x];
+  const int L = p.top + p.sweeps + 2;
+  for (int j = threadIdx.x; j < L; j += 256) table[p.tile_off + j] = stage_tiles(p, stage_of(p, table, 4 + j));
 }
 
 __global__ __launch_bounds__(64) void k_batch_advance(BatchSync* sync, int steps) {
@@ -3393,6 +3408,11 @@ hipError_t batch_occupancy(int prec, int P, int* blocks_per_cu, size_t* lds) {
     case PREC_F32: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_step<float>, 256, *lds);
     default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched_step<bf16>, 256, *lds);
   }
+}
+
+hipError_t launch_batch_tile_table(int P, const BatchProblem* probs, int* table, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_tile_table, dim3(P), dim3(256), 0, s, probs, table);
+  return hipGetLastError();
 }
 
 // Reset of a batched solve's per-problem state and step counter (an
