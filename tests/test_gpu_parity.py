@@ -657,3 +657,53 @@ def test_full_size_fp64(B, torch_cuda, d, n):
     fn = np.sqrt(O.norm2_interior(d, n, f))
     assert np.sqrt(s2) / fn <= 1e-10 * (1 + 1e-6) + relres_floor(d, n, ug, f)
     say("  cycles %d final %.3e" % (res["cycles"], res["final_relres"]))
+
+
+@pytest.mark.parametrize("d,n", [(2, 32769), (3, 1025)])
+def test_maximum_sizes_eigenfunction(B, torch_cuda, d, n):
+    """The largest grids the library accepts (8.6 GB per FP64 array, byte
+    offsets far past 2^31): with f the discrete (1, 1, ...) eigenfunction
+    times its eigenvalue, the discrete solution is that eigenfunction, and
+    since it is the smallest eigenvalue's mode the relative error of u is at
+    most the relative residual.  A property of the mathematics, not of the
+    oracle (too slow at this size).  At these sizes 1e-10 lies below the
+    FP64 rounding floor of the residual itself (16 eps || |A| |u| || / ||f||,
+    about 1.4e-15 / h^2 for this mode: 1.5e-6 at 32769^2, 1.5e-9 at
+    1025^3), so the solve runs to 20 times that floor, and the error bound
+    carries the floor of the final residual too."""
+    torch = torch_cuda
+    say("maximum size d=%d n=%d" % (d, n))
+    h = 1.0 / (n - 1)
+    x = torch.linspace(0.0, 1.0, n, dtype=torch.float64, device="cuda")
+    sx = torch.sin(np.pi * x)
+    sx[0] = 0.0
+    sx[-1] = 0.0
+    ue = sx[:, None] * sx[None, :] if d == 2 else sx[:, None, None] * sx[None, :, None] * sx[None, None, :]
+    lam = d * (4.0 / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    f = ue * lam
+    # |A| |u*| on the interior, for the rounding floor of the residual
+    inn = (slice(1, -1),) * d
+    aau = 2 * d * ue[inn].abs()
+    for axis in range(d):
+        for sh in (-1, 1):
+            sl = [slice(1, -1)] * d
+            sl[axis] = slice(1 + sh, n - 1 + sh)
+            aau = aau + ue[tuple(sl)].abs()
+    floor = 16 * EPS * float(torch.linalg.vector_norm(aau)) / (h * h) / float(torch.linalg.vector_norm(f[inn]))
+    del aau
+    tol = max(1e-10, 20 * floor)
+    u = torch.zeros_like(f)
+    s = B.Solver(d, n)
+    res = s.solve(f, u, tol=tol)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.vector_norm(u - ue) / torch.linalg.vector_norm(ue))
+    worst = float(torch.max(torch.abs(u - ue)))
+    say("  floor %.2e tol %.2e cycles %d final relres %.3e rel err %.3e max err %.3e"
+        % (floor, tol, res["cycles"], res["final_relres"], err, worst))
+    assert res["converged"] and res["final_relres"] <= tol
+    assert err <= (res["final_relres"] + 2 * floor) * (1 + 1e-6)
+    # element by element: |e_i| <= ||e||_2 <= relres ||u*||_2
+    assert worst <= (res["final_relres"] + 2 * floor) * float(torch.linalg.vector_norm(ue)) * (1 + 1e-6)
+    s.close()
+    del f, u, ue
+    torch.cuda.empty_cache()
