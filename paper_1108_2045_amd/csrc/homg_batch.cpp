@@ -101,12 +101,18 @@ void free_batch(homg_batch_ctx* b) {
 // the next finer level's lattice (to the whole grid before level 0), then
 // level 0 in passes of up to `depth` (<= TB_MAX_IT) iterations, the last
 // adding into u.
-std::vector<int> stage_codes(int L, int max_i, int depth) {
+std::vector<int> stage_codes(int n, int L, int max_i, int depth) {
   std::vector<int> codes;
   const int M = L - 1;
   auto iters = [&](int m) { return std::min(1 << std::min(M - m + 1, 30), max_i); };
   for (int m = M; m >= 1; --m) {
     const int it = iters(m);
+    if (m < M && it <= TB_MAX_IT && (n - 1) / (1 << m) + 1 >= BATCH_LTB_MIN_SIDE) {
+      // the level's iterations in one pass, then the hand-over from its outputs
+      codes.push_back(bst_code(BST_LTB, m, it, 0, false, false));
+      codes.push_back(bst_code(BST_XFER, m, it, 1, false, false));
+      continue;
+    }
     for (int t = 1; t <= it; ++t) codes.push_back(bst_code(BST_SWEEP, m, 1, t, m == M && t == 1, false));
     codes.push_back(bst_code(BST_XFER, m, it, 0, m == M && it == 1, false));
   }
@@ -137,7 +143,7 @@ void build_schedule(homg_batch_ctx* b) {
   int max_cycle_len = 0;
   for (int i = 0; i < b->count; ++i) {
     BatchProblem& q = b->h_probs[i];
-    const std::vector<int> codes = stage_codes(b->levels[i], b->max_i, depth_for(b, b->sides[i]));
+    const std::vector<int> codes = stage_codes(b->sides[i], b->levels[i], b->max_i, depth_for(b, b->sides[i]));
     q.sched_off = int(b->sweep_levels.size());
     q.sweeps = int(codes.size());
     b->sweep_levels.insert(b->sweep_levels.end(), codes.begin(), codes.end());
@@ -246,7 +252,8 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     return o2;
   };
   struct Plan {
-    size_t e[2], r[BATCH_MAX_LEVELS], x[BATCH_MAX_LEVELS][2], part, hist, r64 = 0, x64[2] = {0, 0};
+    size_t e[2], r[BATCH_MAX_LEVELS], x[BATCH_MAX_LEVELS][2], x3[BATCH_MAX_LEVELS] = {}, part, hist, r64 = 0,
+        x64[2] = {0, 0};
     Lay el, rl[BATCH_MAX_LEVELS], l64;
   };
   std::vector<Plan> plans(count);
@@ -263,6 +270,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
       p.rl[m] = padded_layout(2, (n - 1) / (1 << m) + 1, eb);
       p.r[m] = take(size_t(p.rl[m].alloc) * eb);
       for (int c = 0; c < 2 && m >= 1; ++c) p.x[m][c] = take(size_t(p.rl[m].alloc) * eb);
+      if (m >= 1 && (n - 1) / (1 << m) + 1 >= BATCH_LTB_MIN_SIDE) p.x3[m] = take(size_t(p.rl[m].alloc) * eb);
     }
     if (b->prec != PREC_F64 && L >= 2) {
       // the FP64 coarsest level of reduced-precision cycles
@@ -276,7 +284,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     // the stage table is sized for one iteration per level-0 pass, the
     // longest sequence any pass depth gives: the codes and the row of
     // tiles per stage (restrictions, codes, residual, finalize)
-    b->sched_cap += 2 * stage_codes(L, b->max_i, 1).size() + size_t(L - 1) + 2;
+    b->sched_cap += 2 * stage_codes(n, L, b->max_i, 1).size() + size_t(L - 1) + 2;
   }
   homg_status st = HOMG_OK;
   if (hipMalloc(&b->arena, total) != hipSuccess) {
@@ -312,6 +320,7 @@ homg_status homg_batch_create(homg_batch* out, int count, const int64_t* sides, 
     for (int m = 0; m < L; ++m) {
       q.r[m] = base + p.r[m] + size_t(p.rl[m].off) * eb;
       for (int c = 0; c < 2 && m >= 1; ++c) q.x[m][c] = base + p.x[m][c] + size_t(p.rl[m].off) * eb;
+      if (m >= 1 && (n - 1) / (1 << m) + 1 >= BATCH_LTB_MIN_SIDE) q.x3[m] = base + p.x3[m] + size_t(p.rl[m].off) * eb;
       q.rp[m] = p.rl[m].pitch;
       q.len[m] = default_walk_len(2, (n - 1) / (1 << m) + 1);
     }

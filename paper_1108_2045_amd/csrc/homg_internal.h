@@ -238,9 +238,18 @@ constexpr int BATCH_MAX_LEVELS = 16;
 //              lattice (ping-pong x[m][0] -> x[m][1] -> ...);
 //   BST_XFER:  hand-over of level m after `iterations` iterations to the
 //              compact x_0 of level m - 1 (to the whole grid e[0] if m = 1);
+//              index 1: the iterations ran as one BST_LTB pass (x_it in
+//              x[m][1], x_{it-1} in x3[m]);
 //   BST_L0:    level-0 pass `index` of `iterations` iterations (e[index & 1]
-//              -> e[1 - index & 1]).
-enum { BST_SWEEP = 1, BST_XFER = 2, BST_L0 = 3 };
+//              -> e[1 - index & 1]);
+//   BST_LTB:   all `iterations` (<= TB_MAX_IT) iterations of coarse level m
+//              below the top in one multi-iteration pass on its compact
+//              lattice: x[m][0] -> x_it in x[m][1], x_{it-1} in x3[m].
+enum { BST_SWEEP = 1, BST_XFER = 2, BST_L0 = 3, BST_LTB = 4 };
+// Coarse levels whose lattice side is at least this run as one BST_LTB
+// pass; smaller lattices keep one step per iteration.
+constexpr int BATCH_LTB_MIN_SIDE = 17;
+constexpr int BATCH_LTB_LEN = 16;  // band rows of a BST_LTB tile (wave)
 __host__ __device__ inline int bst_code(int kind, int level, int count, int index, bool zero, bool accum) {
   return kind | (level << 4) | (count << 9) | (index << 13) | (zero ? 1 << 21 : 0) | (accum ? 1 << 22 : 0);
 }
@@ -263,6 +272,7 @@ struct BatchProblem {         // one problem, read by the step kernels
   void* e[2];                 // internal e ping-pong, pointer at node (0,0)
   void* r[BATCH_MAX_LEVELS];  // residual pyramid, pointer at node (0,0) of each level
   void* x[BATCH_MAX_LEVELS][2];  // compact iterate pair of each coarse level (layout of r)
+  void* x3[BATCH_MAX_LEVELS];    // third compact array: x_{it-1} of a BST_LTB pass
   int64_t ep;                 // pitch of e
   int64_t rp[BATCH_MAX_LEVELS];
   int len[BATCH_MAX_LEVELS];  // rows walked per tile on level-m grids (tile shape)

@@ -3128,6 +3128,7 @@ __device__ __forceinline__ int stage_tiles(const BatchProblem& p, const StageInf
     case BK_STAGE: {
       const int c = si.code;
       if (bst_kind(c) == BST_L0) return tb_blocks(p.n, bst_count(c), batch_tb_len(p));
+      if (bst_kind(c) == BST_LTB) return tb_blocks(level_side(p, si.level), bst_count(c), BATCH_LTB_LEN);
       if (bst_kind(c) == BST_SWEEP) return tiles_of(level_side(p, si.level), p.len[si.level]);
       const int nt = level_side(p, si.level - 1);  // hand-over target
       return nt >= 3 ? ((nt - 2 + BX2 - 1) / BX2) * ((nt - 2 + BATCH_XF_ROWS - 1) / BATCH_XF_ROWS) : 0;
@@ -3247,10 +3248,26 @@ __device__ __forceinline__ void batch_tile(const BatchProblem& p, BatchState* __
         else
           tile_sweep_2d_l0<T, 0, false>(xo, xn, p.rp[m], rm, p.rp[m], nullptr, 0, nullptr, 0, nm, p.len[m],
                                         w, hl2, t % gxm, t / gxm);
+      } else if (kind == BST_LTB) {  // all iterations of level m in one pass on its compact lattice
+        const int nm = level_side(p, m), cnt = bst_count(c);
+        const T* xo = static_cast<const T*>(p.x[m][0]);
+        T* xn = static_cast<T*>(p.x[m][1]);
+        T* xq = static_cast<T*>(p.x3[m]);
+        const double hl = 1.0 / double(nm - 1);
+        const C hl2 = C(hl * hl), w = C(run.omega / 4.0);
+        const T* rm = static_cast<const T*>(p.r[m]);
+        const int wv = t * 4 + int(threadIdx.x >> 6);
+        switch (cnt) {
+          case 1: tb_body<T, false, false, true, 1>(xo, xn, xq, p.rp[m], rm, p.rp[m], nullptr, 0, nm, BATCH_LTB_LEN, w, hl2, wv); break;
+          case 2: tb_body<T, false, false, true, 2>(xo, xn, xq, p.rp[m], rm, p.rp[m], nullptr, 0, nm, BATCH_LTB_LEN, w, hl2, wv); break;
+          case 3: tb_body<T, false, false, true, 3>(xo, xn, xq, p.rp[m], rm, p.rp[m], nullptr, 0, nm, BATCH_LTB_LEN, w, hl2, wv); break;
+          default: tb_body<T, false, false, true, 4>(xo, xn, xq, p.rp[m], rm, p.rp[m], nullptr, 0, nm, BATCH_LTB_LEN, w, hl2, wv); break;
+        }
       } else if (kind == BST_XFER) {  // level m's final state to the lattice of level m - 1
         const int it = bst_count(c), mt = m - 1, nt = level_side(p, mt);
-        const T* xc = static_cast<const T*>(p.x[m][it & 1]);
-        const T* xp = static_cast<const T*>(p.x[m][(it - 1) & 1]);
+        const bool ltb = bst_index(c) == 1;  // from one BST_LTB pass
+        const T* xc = static_cast<const T*>(ltb ? p.x[m][1] : p.x[m][it & 1]);
+        const T* xp = static_cast<const T*>(ltb ? p.x3[m] : p.x[m][(it - 1) & 1]);
         T* dst = mt > 0 ? static_cast<T*>(p.x[mt][0]) : e0;
         const int64_t dp = mt > 0 ? p.rp[mt] : p.ep;
         const int gxt = (nt - 2 + BX2 - 1) / BX2;
