@@ -97,10 +97,12 @@ void free_batch(homg_batch_ctx* b) {
 // Tile rows (the walked length of a tile) of the fine-grid stages.
 // The iteration stages of one cycle (levels M .. 0, n_m = min(2^(M-m+1),
 // MaxI) iterations each, chained as in the single-problem solver): each
-// coarse level's iterations on its compact lattice and its hand-over to
-// the next finer level's lattice (to the whole grid before level 0), then
-// level 0 in passes of up to `depth` (<= TB_MAX_IT) iterations, the last
-// adding into u.
+// coarse level's iterations on its compact lattice -- one multi-iteration
+// pass (BST_LTB) below the top when the lattice side is at least
+// BATCH_LTB_MIN_SIDE and n_m <= TB_MAX_IT, else one stage per iteration --
+// and its hand-over to the next finer level's lattice (to the whole grid
+// before level 0), then level 0 in passes of up to `depth` (<= TB_MAX_IT)
+// iterations, the last adding into u.
 std::vector<int> stage_codes(int n, int L, int max_i, int depth) {
   std::vector<int> codes;
   const int M = L - 1;
