@@ -1847,8 +1847,20 @@ __global__ __launch_bounds__(256) void k_level_transfer_3d(
 // rounding points are those of the restriction, small-lattice and transfer
 // kernels, so the result is theirs bit for bit.  Level ms + k has side
 // nk = ((nms - 1) >> k) + 1; LDS holds, per level, r and two iterates.
-struct TailIts {
-  int it[BATCH_MAX_LEVELS];  // iterations of level ms + k
+// Per-level constants of the tail, worked out on the host (the reciprocals
+// and h^2 are the correctly rounded values the device division would give),
+// so that no level of the kernel starts with a division or a walk over the
+// coarser levels' sizes.
+struct TailLevel {
+  int it;        // iterations of level ms + k
+  int off;       // element offset of the level's R, P, Q arrays in LDS
+  float inv_ni;  // 1 / (nk - 2): splits the level's interior nodes
+  float inv_nt;  // 1 / (2 nk - 3): splits the next finer level's interior nodes
+  double hl2;    // h^2 = (1 / (nk - 1))^2
+};
+struct TailPlan {
+  TailLevel lv[BATCH_MAX_LEVELS];
+  float inv_side;  // 1 / nms: splits every node of level ms
 };
 
 template <int D>
@@ -1878,7 +1890,7 @@ __device__ __forceinline__ void tail_split(int i, int s, float inv_s, int& I, in
 template <typename T, int D, bool TOP64>
 __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     const T* __restrict__ rms, int64_t rp, int64_t rpl, T* __restrict__ dst, int64_t dp, int64_t dpl,
-    int nms, int nlev, TailIts its, typename Tr<T>::C w, double w64, const int* __restrict__ done,
+    int nms, int nlev, TailPlan tp, typename Tr<T>::C w, double w64, const int* __restrict__ done,
     T* __restrict__ sprev, T* __restrict__ scur, int64_t sp, int64_t spl) {
   using C = typename Tr<T>::C;
   if (*done) return;
@@ -1886,11 +1898,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
   C* base = reinterpret_cast<C*>(smem);
   auto side = [&](int k) { return ((nms - 1) >> k) + 1; };
   // per level: R (r), P (x_0 and odd-numbered iterates' sources), Q
-  auto lvl = [&](int k, int which) {
-    C* p = base;
-    for (int j = 0; j < k; ++j) p += 3 * tail_count<D>(side(j));
-    return p + which * tail_count<D>(side(k));
-  };
+  auto lvl = [&](int k, int which) { return base + tp.lv[k].off + which * tail_count<D>(side(k)); };
   // FP64 arrays of the coarsest level (TOP64): R, P, Q after all C arrays
   const int ktop = nlev - 1, ctop = tail_count<D>(side(ktop));
   double* top64 = nullptr;
@@ -1899,37 +1907,47 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     top64 = reinterpret_cast<double*>(smem + ((used + 15) & ~size_t(15)));
     for (int i = threadIdx.x; i < 3 * ctop; i += SMALL_NT) top64[i] = 0.0;
   }
-  // the coarser levels' arrays start at 0 (x_0 = 0 on the coarsest level,
-  // and every boundary node); on level ms, r is loaded (0 on the boundary)
-  // and the iterates' interiors are written before they are read (the
-  // hand-over from level ms + 1, the first iteration), so only their
-  // boundary nodes are cleared
-  for (int k = 1; k < nlev; ++k) {
-    const int cnt = tail_count<D>(side(k));
-    C* R = lvl(k, 0);
-    C* P = lvl(k, 1);
-    C* Q = lvl(k, 2);
-    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) R[i] = P[i] = Q[i] = C(0);
-  }
-  {
+  // Level ms: r is loaded (0 on the boundary) and the iterates' boundary
+  // nodes cleared; their interiors are written before they are read (the
+  // hand-over from level ms + 1, the first iteration).  The coarser levels'
+  // arrays start at 0 (x_0 = 0 on the coarsest level, and every boundary
+  // node).  Each thread issues its loads of r (clamped in-range addresses,
+  // the boundary's values dropped) before any LDS write, so the global
+  // latency is paid once per chunk of TAIL_LB nodes, not once per node.
+  constexpr int TAIL_LB = 8;
+  const int cnt0 = tail_count<D>(nms);
+  for (int i0 = 0; i0 < cnt0; i0 += TAIL_LB * SMALL_NT) {
+    C rv[TAIL_LB];
+    bool inner[TAIL_LB];
+#pragma unroll
+    for (int j = 0; j < TAIL_LB; ++j) {
+      const int i = min(i0 + j * SMALL_NT + int(threadIdx.x), cnt0 - 1);
+      int I, J, K;
+      tail_split<D>(i, nms, tp.inv_side, I, J, K);
+      inner[j] = I > 0 && I < nms - 1 && J > 0 && J < nms - 1 && (D == 2 || (K > 0 && K < nms - 1));
+      rv[j] = ld(rms + int64_t(K) * rpl + int64_t(J) * rp + I);
+    }
+    if (i0 == 0) {
+      const int z0 = tp.lv[nlev > 1 ? 1 : 0].off, z1 = tp.lv[ktop].off + 3 * ctop;
+      for (int i = z0 + threadIdx.x; nlev > 1 && i < z1; i += SMALL_NT) base[i] = C(0);
+    }
     C* R = lvl(0, 0);
     C* P = lvl(0, 1);
     C* Q = lvl(0, 2);
-    const int cnt = tail_count<D>(nms);
-    const float inv = 1.0f / float(nms);
-    for (int i = threadIdx.x; i < cnt; i += SMALL_NT) {
-      int I, J, K;
-      tail_split<D>(i, nms, inv, I, J, K);
-      const bool inner = I > 0 && I < nms - 1 && J > 0 && J < nms - 1 && (D == 2 || (K > 0 && K < nms - 1));
-      R[i] = inner ? ld(rms + int64_t(K) * rpl + int64_t(J) * rp + I) : C(0);
-      if (!inner) P[i] = Q[i] = C(0);
+#pragma unroll
+    for (int j = 0; j < TAIL_LB; ++j) {
+      const int i = i0 + j * SMALL_NT + int(threadIdx.x);
+      if (i < cnt0) {
+        R[i] = inner[j] ? rv[j] : C(0);
+        if (!inner[j]) P[i] = Q[i] = C(0);
+      }
     }
   }
   __syncthreads();
   // restriction pyramid (full weighting, as k_restrict_*)
   for (int k = 1; k < nlev; ++k) {
     const int nf = side(k - 1), nc = side(k), ni = nc - 2, cnt = tail_count<D>(ni);
-    const float inv = 1.0f / float(ni);
+    const float inv = tp.lv[k].inv_ni;
     const C* F = lvl(k - 1, 0);
     C* R = lvl(k, 0);  // boundary nodes stay 0
     const int fp = nf, fpl = nf * nf;
@@ -1974,21 +1992,20 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
   // levels from the coarsest down
   for (int k = nlev - 1; k >= 0; --k) {
     const int nk = side(k), pl = nk * nk;
-    const double h = 1.0 / double(nk - 1);
-    const C hl2 = C(h * h);
+    const C hl2 = C(tp.lv[k].hl2);
     const C* R = lvl(k, 0);
     C* xa = lvl(k, 1);
     C* xb = lvl(k, 2);
-    const int it = its.it[k];
+    const int it = tp.lv[k].it;
     const int ni = nk - 2, icnt = tail_count<D>(ni);
-    const float inv = 1.0f / float(ni);
+    const float inv = tp.lv[k].inv_ni;
     if (TOP64 && k == ktop) {
       // FP64 iterations (as the FP64 small-lattice kernel), then the final
       // pair rounded to the storage type into xa (x_{it-1}) and xb (x_it)
       const double* R64 = top64;
       double* ya = top64 + ctop;
       double* yb = top64 + 2 * ctop;
-      const double hl2d = h * h;
+      const double hl2d = tp.lv[k].hl2;
       for (int t = 1; t <= it; ++t) {
         const double* src = (t & 1) ? ya : yb;
         double* dstl = (t & 1) ? yb : ya;
@@ -2040,10 +2057,9 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     if (k == 0 && scur) {
       // level ms's final state (every node) for the next level's first
       // pass, which interpolates it itself
-      const float sinv = 1.0f / float(nk);
       for (int j = threadIdx.x; j < tail_count<D>(nk); j += SMALL_NT) {
         int I, J, K;
-        tail_split<D>(j, nk, sinv, I, J, K);
+        tail_split<D>(j, nk, tp.inv_side, I, J, K);
         const int64_t o = (D == 3 ? int64_t(K) * spl : 0) + int64_t(J) * sp + I;
         st(sprev + o, prv[j]);
         st(scur + o, cur[j]);
@@ -2055,7 +2071,7 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
     const int nt = 2 * nk - 1, ptl = nt * nt, nti = nt - 2;
     C* tgt = k > 0 ? lvl(k - 1, 1) : nullptr;
     const int tcnt = tail_count<D>(nti);
-    const float tinv = 1.0f / float(nti);
+    const float tinv = tp.lv[k].inv_nt;
     for (int j = threadIdx.x; j < tcnt; j += SMALL_NT) {
       int I, J, K;
       tail_split<D>(j, nti, tinv, I, J, K);
@@ -2775,8 +2791,15 @@ static hipError_t tail_t(int d, int nms, int nlev, const int* its, double omega,
                          const Lay& rl, void* dst, const Lay& tl, const int* done, hipStream_t s,
                          void* sprev, void* scur, const Lay& sl) {
   using C = typename Tr<T>::C;
-  TailIts ti{};
-  for (int k = 0; k < nlev; ++k) ti.it[k] = its[k];
+  TailPlan ti{};
+  int off = 0;
+  for (int k = 0; k < nlev; ++k) {
+    const int nk = ((nms - 1) >> k) + 1;
+    const double h = 1.0 / double(nk - 1);
+    ti.lv[k] = TailLevel{its[k], off, 1.0f / float(nk - 2), 1.0f / float(2 * nk - 3), h * h};
+    off += 3 * (d == 2 ? nk * nk : nk * nk * nk);
+  }
+  ti.inv_side = 1.0f / float(nms);
   const size_t lds = coarse_tail_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, nms, nlev, TOP64);
   const T* r = static_cast<const T*>(rms) + rl.off;
   T* o = dst ? static_cast<T*>(dst) + tl.off : nullptr;
