@@ -76,6 +76,14 @@ hipError_t launch_l1(int prec, int d, int n, const double* uref, const double* u
 // One full-weighting restriction: fine level (side nf) -> coarse (side (nf-1)/2+1).
 hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void* rc,
                            const Lay& cl, const int* done, hipStream_t s);
+// P consecutive restrictions r_a -> ... -> r_{a+P} in one launch (r[k],
+// l[k]: the array and layout of level a + k, k = 0 .. P): the same bits as
+// P launch_restrict calls.  Workgroups own blocks of B nodes per axis of
+// level a + P; restrict_multi_lds: the LDS bytes that needs.
+constexpr int MR_MAX = 6;
+size_t restrict_multi_lds(int prec, int d, int P, int B);
+hipError_t launch_restrict_multi(int prec, int d, int P, int B, void* const* r, const Lay* l, const int* done,
+                                 hipStream_t s);
 // One whole-grid relax+interpolate iteration at level m.  eo/en: fine
 // arrays (layout el); rm: compact level-m residual (layout rl); am: compact
 // level-m nodal coefficient (FP64, layout al) or null; mode: SweepMode bits;

@@ -2102,6 +2102,103 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
   }
 }
 
+// ------------------------------------------------------------ multi-level restriction
+// P consecutive full-weighting restrictions of the cycle's chain, r_a ->
+// r_{a+1} -> ... -> r_{a+P}, in one launch: the chain's coarse end, where
+// every launch is latency-bound.  Each level is rounded to the storage type
+// before the next is restricted from it, as the separate launches store and
+// reload it, and the node formula and summation order are those of
+// k_restrict_*, so every level gets the same bits.
+//
+// Workgroup b (per axis) owns the interior nodes B b + 1 .. B (b + 1) of
+// level a + P and, at level a + P - j, the nodes 2^j B b + 1 .. 2^j B (b + 1):
+// a partition of every level's interior.  Those depend on the nodes
+// 2^j B b + 1 .. 2^j B b + S_j of level a + P - j, S_j = 2^j (B + 1) - 1, and
+// tile node t of one level on tile nodes 2t .. 2t + 2 of the next finer one.
+// The workgroup loads its tile of r_a into LDS (each lane issues up to
+// MR_LB loads before it writes any of them), restricts level by level in
+// LDS and writes the nodes it owns.  A tile's nodes past the last interior node are loaded clamped or
+// skipped: interior coarse nodes read interior fine nodes only.
+struct MultiRestrictLevel {
+  void* r;  // the level's array at node (0, 0, 0)
+  int64_t pitch, plane;
+  int side;  // nodes per axis
+  int off;   // LDS offset of the level's tile (elements; level a + P has none)
+};
+struct MultiRestrictPlan {
+  MultiRestrictLevel lv[MR_MAX + 1];  // lv[j]: level a + P - j; lv[P] = r_a
+  int P, B, nb;                       // nb: blocks per axis
+};
+constexpr int MR_NT = 1024;
+constexpr int MR_LB = 8;  // tile loads a lane issues before writing LDS
+
+template <typename T, int D>
+__global__ __launch_bounds__(MR_NT) void k_restrict_multi(MultiRestrictPlan mp, const int* __restrict__ done) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* lds = reinterpret_cast<C*>(smem);
+  const int P = mp.P, B = mp.B, nb = mp.nb;
+  // neighbouring blocks (shared halo loads) on one XCD
+  const int lb = int(xcd_order(blockIdx.x, gridDim.x));
+  const int bx = lb % nb, by = (lb / nb) % nb, bz = D == 3 ? lb / (nb * nb) : 0;
+  auto tside = [&](int j) { return j == 0 ? B : ((B + 1) << j) - 1; };
+  {
+    const MultiRestrictLevel& L = mp.lv[P];
+    const int S = tside(P), cnt = D == 2 ? S * S : S * S * S, o = B << P, hi = L.side - 2;
+    const T* rf = static_cast<const T*>(L.r);
+    const float inv = 1.0f / float(S);
+    for (int i0 = 0; i0 < cnt; i0 += MR_LB * MR_NT) {
+      C v[MR_LB];
+#pragma unroll
+      for (int k = 0; k < MR_LB; ++k) {
+        const int i = min(i0 + k * MR_NT + int(threadIdx.x), cnt - 1);
+        int I, J, K;
+        tail_split<D>(i, S, inv, I, J, K);
+        const int gx = min(o * bx + 1 + I, hi), gy = min(o * by + 1 + J, hi), gz = D == 3 ? min(o * bz + 1 + K, hi) : 0;
+        v[k] = C(ld(rf + int64_t(gz) * L.plane + int64_t(gy) * L.pitch + gx));
+      }
+#pragma unroll
+      for (int k = 0; k < MR_LB; ++k) {
+        const int i = i0 + k * MR_NT + int(threadIdx.x);
+        if (i < cnt) lds[L.off + i] = v[k];
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = P - 1; j >= 0; --j) {
+    const MultiRestrictLevel& L = mp.lv[j];
+    const int Sf = tside(j + 1), Sc = tside(j), own = B << j, hi = L.side - 2;
+    const int cnt = D == 2 ? Sc * Sc : Sc * Sc * Sc, fp = Sf, fpl = Sf * Sf;
+    const C* F = lds + mp.lv[j + 1].off;
+    C* R = lds + L.off;
+    T* out = static_cast<T*>(L.r);
+    const float inv = 1.0f / float(Sc);
+    for (int i = threadIdx.x; i < cnt; i += MR_NT) {
+      int I, J, K;
+      tail_split<D>(i, Sc, inv, I, J, K);
+      const int gx = own * bx + 1 + I, gy = own * by + 1 + J, gz = D == 3 ? own * bz + 1 + K : 0;
+      if (gx > hi || gy > hi || (D == 3 && gz > hi)) continue;
+      auto rs = [&](int q) { return fmac(C(2), F[q], F[q - 1] + F[q + 1]); };
+      C v;
+      if (D == 2) {
+        const int q = (2 * J + 1) * fp + 2 * I + 1;
+        const C top = rs(q - fp), mid = rs(q), bot = rs(q + fp);
+        v = fmac(C(2), mid, top + bot) * C(0.0625);
+      } else {
+        auto ps = [&](int q) { return fmac(C(2), rs(q), rs(q - fp) + rs(q + fp)); };
+        const int q = (2 * K + 1) * fpl + (2 * J + 1) * fp + 2 * I + 1;
+        const C top = ps(q - fpl), mid = ps(q), bot = ps(q + fpl);
+        v = fmac(C(2), mid, top + bot) * C(0.015625);
+      }
+      if (j > 0) R[i] = rnd<T>(v);
+      if (I < own && J < own && (D == 2 || K < own))
+        st(out + int64_t(gz) * L.plane + int64_t(gy) * L.pitch + gx, v);
+    }
+    if (j > 0) __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ pack / unpack
 
 template <typename T>
@@ -2319,6 +2416,54 @@ hipError_t launch_restrict(int prec, int d, const void* rf, const Lay& fl, void*
     case PREC_F64: return restrict_t<double>(d, rf, fl, rc, cl, done, s);
     case PREC_F32: return restrict_t<float>(d, rf, fl, rc, cl, done, s);
     default: return restrict_t<bf16>(d, rf, fl, rc, cl, done, s);
+  }
+}
+
+size_t restrict_multi_lds(int prec, int d, int P, int B) {
+  const size_t cs = prec == PREC_F64 ? 8 : 4;
+  size_t cnt = 0;
+  for (int j = 1; j <= P; ++j) {
+    const size_t S = size_t(((B + 1) << j) - 1);
+    cnt += d == 2 ? S * S : S * S * S;
+  }
+  return cnt * cs;
+}
+
+template <typename T>
+static hipError_t restrict_multi_t(int d, int P, int B, void* const* r, const Lay* l, const int* done,
+                                   hipStream_t s) {
+  MultiRestrictPlan mp{};
+  mp.P = P;
+  mp.B = B;
+  mp.nb = (l[P].side - 1 + B - 1) / B;
+  int off = 0;
+  for (int j = 0; j <= P; ++j) {
+    const Lay& L = l[P - j];
+    mp.lv[j] = MultiRestrictLevel{static_cast<T*>(r[P - j]) + L.off, L.pitch, L.plane, L.side, off};
+    if (j >= 1) {
+      const int S = ((B + 1) << j) - 1;
+      off += d == 2 ? S * S : S * S * S;
+    }
+  }
+  const size_t lds = restrict_multi_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, d, P, B);
+  const unsigned blocks = d == 2 ? unsigned(mp.nb * mp.nb) : unsigned(mp.nb * mp.nb * mp.nb);
+  if (d == 2) {
+    hipError_t a = allow_lds(k_restrict_multi<T, 2>, lds);
+    if (a != hipSuccess) return a;
+    HOMG_LAUNCH_SMEM((k_restrict_multi<T, 2>), dim3(blocks), dim3(MR_NT), lds, s, mp, done);
+  }
+  hipError_t a = allow_lds(k_restrict_multi<T, 3>, lds);
+  if (a != hipSuccess) return a;
+  HOMG_LAUNCH_SMEM((k_restrict_multi<T, 3>), dim3(blocks), dim3(MR_NT), lds, s, mp, done);
+}
+
+hipError_t launch_restrict_multi(int prec, int d, int P, int B, void* const* r, const Lay* l, const int* done,
+                                 hipStream_t s) {
+  if (P < 1 || P > MR_MAX || B < 1 || l[P].side < 3) return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return restrict_multi_t<double>(d, P, B, r, l, done, s);
+    case PREC_F32: return restrict_multi_t<float>(d, P, B, r, l, done, s);
+    default: return restrict_multi_t<bf16>(d, P, B, r, l, done, s);
   }
 }
 

@@ -1,7 +1,10 @@
 """The in-cycle restriction of Sec. 2 (one extra array instead of the
 restriction pyramid): same bits as the pyramid on every execution form and
 precision, with schedules that revisit levels, end on a coarse level, skip
-levels and run the one-workgroup coarse tail; and less device memory."""
+levels and run the one-workgroup coarse tail; and less device memory.  The
+in-cycle form runs one restriction per launch, so the bitwise comparison
+also pins the pyramid's multi-level restriction launch (its coarse end,
+several levels per launch) to the single restrictions."""
 import sys
 
 import numpy as np
@@ -36,9 +39,10 @@ def dev(torch, x):
 
 
 CASES = [
-    (2, 5, None), (2, 65, None), (2, 1025, None), (2, 129, [(6, 2), (5, 2), (6, 1), (5, 2), (4, 2), (2, 3), (3, 1), (1, 2), (0, 2)]),
+    (2, 5, None), (2, 65, None), (2, 1025, None), (2, 2049, None),
+    (2, 129, [(6, 2), (5, 2), (6, 1), (5, 2), (4, 2), (2, 3), (3, 1), (1, 2), (0, 2)]),
     (2, 257, [(3, 2), (7, 2), (1, 1), (0, 3), (5, 2)]),
-    (3, 5, None), (3, 33, None), (3, 129, None), (3, 65, [(5, 2), (4, 1), (5, 1), (3, 2), (1, 2), (2, 1), (0, 3)]),
+    (3, 5, None), (3, 33, None), (3, 129, None), (3, 257, None), (3, 65, [(5, 2), (4, 1), (5, 1), (3, 2), (1, 2), (2, 1), (0, 3)]),
 ]
 
 
