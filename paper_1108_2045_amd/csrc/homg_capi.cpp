@@ -289,7 +289,6 @@ bool lat_target(const homg_ctx* h, int mt) {
   const int nm = (h->n - 1) / (1 << mt) + 1;
   if (nm < 5 || mt + 1 >= h->levels) return false;
   if (mt == 0) return true;
-  if (h->d == 3) return false;
   return lattice_small_lds(h->prec, h->d, nm, false) > h->lds_limit && mt < int(h->xp3.size()) &&
          h->xp3[mt];
 }
@@ -742,8 +741,9 @@ homg_status enqueue_cycle(homg_ctx* h, const double* f, double* acc, int cycle, 
     const bool lat = lat_target(h, ms - 1) && !(next_last && h->prec != PREC_F64);
     if (lat || h->d == 3) {
       // the tail leaves level ms's state; level ms - 1's first pass
-      // interpolates it, or (3D) the multi-workgroup hand-over kernel does:
-      // the tail's own one-workgroup hand-over to 33^3 took 16 of its 37 us
+      // interpolates it, or else (3D) the multi-workgroup hand-over kernel
+      // does: the tail's own one-workgroup hand-over to 33^3 took 16 of its
+      // 37 us
       LAUNCH_K(h, s, K_TAIL, ms, 1,
                launch_coarse_tail(h->prec, h->d, nms, ntail, its, h->omega, h->r[ms], h->rl[ms], nullptr,
                                   Lay(), done, s, h->xc[2 * ms], h->xc[2 * ms + 1], h->rl[ms], top64(h)));
