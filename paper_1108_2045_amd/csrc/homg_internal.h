@@ -134,6 +134,17 @@ hipError_t launch_sweep_2d_l0_tb(int prec, int n, int it, double omega, const vo
                                  const Lay& el, const void* rm, const Lay& rl, double* u,
                                  const Lay& ul, bool zero, bool accum, const int* done, hipStream_t s,
                                  int len = 0, const L1State* l1 = nullptr);
+// 3D compact lattice of side n (Laplacian, damped Jacobi): it (<= LT_MAX_IT)
+// iterations in one launch, blocks of 8^3 owned nodes iterating with a halo
+// of `it` nodes in LDS.  x_0: 0 (zero), the compact array xo, or the next
+// coarser level's state (l1); x_it into xn and x_{it-1} into xprev (layout
+// cl; neither may alias xo).  lattice_3d_tiled_lds: its LDS bytes.
+constexpr int LT_MAX_IT = 4;
+constexpr int LT_MAX_SIDE = 65;  // the solver uses it on lattices up to this side
+size_t lattice_3d_tiled_lds(int prec, int it);
+hipError_t launch_lattice_3d_tiled(int prec, int n, int it, double omega, const void* xo, void* xn, void* xprev,
+                                   const Lay& cl, const void* rm, const Lay& rl, bool zero, const L1State* l1,
+                                   const int* done, hipStream_t s);
 // The same on the compact lattice of a coarse level (side nm): x_it into en
 // and, when eprev is not null, x_{it-1} into eprev (layout cl); l1: x_0
 // from the next coarser level's state.

@@ -2102,6 +2102,152 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
   }
 }
 
+// ------------------------------------------------------------ tiled 3D lattice iterations
+// IT (<= 4) iterations of a small 3D compact lattice in one launch: each
+// workgroup holds a block of LT_B^3 owned nodes with a halo of IT nodes in
+// LDS and iterates there, the region of valid values shrinking by one node
+// per side and iteration, so the halo is recomputed by neighbouring blocks
+// instead of exchanged between launches.  x_0 is 0 (ZERO), the compact array
+// xo, or (LAT) the next coarser level's final state seen on this lattice
+// (its x_it at shared lattice nodes, else the trilinear interpolant of its
+// x_{it-1}); writes x_IT to xn and x_{IT-1} to xp at the owned nodes.  The
+// node formula, summation order, interpolation and rounding are those of
+// k_lattice_3d_tb and k_level_transfer_3d, so the bits are theirs.
+constexpr int LT_B = 8;      // owned nodes per axis of a block
+constexpr int LT_NT = 1024;
+constexpr int LT_LB = 4;     // global loads a lane issues before writing LDS (a 16^3 tile: all of them)
+
+template <int IT>
+__host__ __device__ constexpr int lt_side() { return LT_B + 2 * IT; }
+__host__ __device__ constexpr int lt_cside(int S) { return S / 2 + 2; }
+
+template <typename T, bool ZERO, bool LAT, int IT>
+__global__ __launch_bounds__(LT_NT) void k_lattice_3d_tiled(
+    const T* __restrict__ xo, T* __restrict__ xn, T* __restrict__ xp, int64_t cp, int64_t cpl,
+    const T* __restrict__ r, int64_t rp, int64_t rpl, int n, int nb, typename Tr<T>::C w,
+    typename Tr<T>::C hl2, const int* __restrict__ done, L1Src<T> l1) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  constexpr int S = lt_side<IT>(), S2 = S * S, S3 = S2 * S, SC = lt_cside(S), SC2 = SC * SC, SC3 = SC2 * SC;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* X0 = reinterpret_cast<C*>(smem);
+  C* X1 = X0 + S3;
+  C* R = X1 + S3;
+  C* Pc = R + S3;  // LAT: the coarser level's x_{it-1} and x_it around the block
+  C* Cc = Pc + SC3;
+  const int lb = int(xcd_order(blockIdx.x, gridDim.x));
+  const int bx = lb % nb, by = (lb / nb) % nb, bz = lb / (nb * nb);
+  // tile node (i, j, k) is lattice node (gx0 + i, gy0 + j, gz0 + k)
+  const int gx0 = LT_B * bx + 1 - IT, gy0 = LT_B * by + 1 - IT, gz0 = LT_B * bz + 1 - IT;
+  const int hi = n - 1;
+  auto interior = [&](int gx, int gy, int gz) {
+    return gx >= 1 && gx <= n - 2 && gy >= 1 && gy <= n - 2 && gz >= 1 && gz <= n - 2;
+  };
+  // r and (neither ZERO nor LAT) x_0 on the tile; clamped loads, nodes off
+  // the lattice are never read by an interior node's update
+  for (int i0 = 0; i0 < S3; i0 += LT_LB * LT_NT) {
+    C rv[LT_LB], xv[LT_LB];
+#pragma unroll
+    for (int u = 0; u < LT_LB; ++u) {
+      const int q = min(i0 + u * LT_NT + int(threadIdx.x), S3 - 1);
+      const int k = q / S2, j = (q / S) % S, i = q % S;
+      const int64_t gx = min(max(gx0 + i, 0), hi), gy = min(max(gy0 + j, 0), hi), gz = min(max(gz0 + k, 0), hi);
+      rv[u] = ld(r + gz * rpl + gy * rp + gx);
+      if (!ZERO && !LAT) xv[u] = ld(xo + gz * cpl + gy * cp + gx);
+    }
+#pragma unroll
+    for (int u = 0; u < LT_LB; ++u) {
+      const int q = i0 + u * LT_NT + int(threadIdx.x);
+      if (q < S3) {
+        R[q] = rv[u];
+        if (!ZERO && !LAT) {
+          const int k = q / S2, j = (q / S) % S, i = q % S;
+          X0[q] = interior(gx0 + i, gy0 + j, gz0 + k) ? xv[u] : C(0);
+        }
+      }
+    }
+  }
+  if (ZERO)
+    for (int q = threadIdx.x; q < S3; q += LT_NT) X0[q] = C(0);
+  // LAT: the coarser level's state from coarse node (cx0, cy0, cz0) on
+  const int cx0 = max(gx0, 0) >> 1, cy0 = max(gy0, 0) >> 1, cz0 = max(gz0, 0) >> 1;
+  if (LAT) {
+    const int nc = (n - 1) / 2 + 1;
+    const T* pp = l1.zero_old ? l1.cur : l1.prev;  // (x_{it-1} = 0: loads a valid array, drops it)
+    for (int i0 = 0; i0 < SC3; i0 += (LT_LB / 2) * LT_NT) {
+      C pv[LT_LB / 2], cv[LT_LB / 2];
+#pragma unroll
+      for (int u = 0; u < LT_LB / 2; ++u) {
+        const int q = min(i0 + u * LT_NT + int(threadIdx.x), SC3 - 1);
+        const int k = q / SC2, j = (q / SC) % SC, i = q % SC;
+        const int64_t o = int64_t(min(cz0 + k, nc - 1)) * l1.cpl + int64_t(min(cy0 + j, nc - 1)) * l1.cp +
+                          min(cx0 + i, nc - 1);
+        pv[u] = l1.zero_old ? C(0) : ld(pp + o);
+        cv[u] = ld(l1.cur + o);
+      }
+#pragma unroll
+      for (int u = 0; u < LT_LB / 2; ++u) {
+        const int q = i0 + u * LT_NT + int(threadIdx.x);
+        if (q < SC3) {
+          Pc[q] = pv[u];
+          Cc[q] = cv[u];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (LAT) {
+    for (int q = threadIdx.x; q < S3; q += LT_NT) {
+      const int k = q / S2, j = (q / S) % S, i = q % S;
+      const int gx = gx0 + i, gy = gy0 + j, gz = gz0 + k;
+      C v = C(0);
+      if (interior(gx, gy, gz)) {
+        const int c0 = ((gz >> 1) - cz0) * SC2 + ((gy >> 1) - cy0) * SC + ((gx >> 1) - cx0);
+        if (!(gx & 1) && !(gy & 1) && !(gz & 1)) {
+          v = Cc[c0];
+        } else {
+          const C tx = C(gx & 1) * C(0.5), ty = C(gy & 1) * C(0.5), tz = C(gz & 1) * C(0.5);
+          const C* p = Pc + c0;
+          const C* q2 = p + SC2;
+          const C top = lerp(lerp(p[0], p[1], tx), lerp(p[SC], p[SC + 1], tx), ty);
+          const C bot = lerp(lerp(q2[0], q2[1], tx), lerp(q2[SC], q2[SC + 1], tx), ty);
+          v = lerp(top, bot, tz);
+        }
+        v = rnd<T>(v);
+      }
+      X0[q] = v;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 1; t <= IT; ++t) {
+    const C* __restrict__ src = (t & 1) ? X0 : X1;
+    C* __restrict__ dst = (t & 1) ? X1 : X0;
+    const int V = S - 2 * t, V2 = V * V, V3 = V2 * V;  // valid region after this iteration
+    for (int q = threadIdx.x; q < V3; q += LT_NT) {
+      const int k = q / V2 + t, j = (q / V) % V + t, i = q % V + t;
+      const int c = (k * S + j) * S + i;
+      const int gx = gx0 + i, gy = gy0 + j, gz = gz0 + k;
+      C v = C(0);
+      const bool in = interior(gx, gy, gz);
+      if (in) {
+        v = relax_const<C>(src[c], ((src[c - 1] + src[c + 1]) + (src[c - S] + src[c + S])) + (src[c - S2] + src[c + S2]),
+                           R[c], w, hl2, C(6));
+        dst[c] = rnd<T>(v);
+      } else {
+        dst[c] = C(0);
+      }
+      // the last iteration's region is the owned block: x_{IT-1} (src) and x_IT
+      if (t == IT && in) {
+        const int64_t o = int64_t(gz) * cpl + int64_t(gy) * cp + gx;
+        st(xn + o, v);
+        st(xp + o, src[c]);
+      }
+    }
+    if (t < IT) __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ multi-level restriction
 // P consecutive full-weighting restrictions of the cycle's chain, r_a ->
 // r_{a+1} -> ... -> r_{a+P}, in one launch: the chain's coarse end, where
@@ -2262,6 +2408,14 @@ void current_launch_events(hipEvent_t* start, hipEvent_t* stop) {
 
 #define HOMG_LAUNCH(kernel, grid, block, stream, ...) \
   HOMG_LAUNCH_SMEM(kernel, grid, block, 0, stream, __VA_ARGS__)
+
+// Opt a kernel in to more than 64 KB of dynamic LDS.
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
 
 hipError_t launch_norm2(int d, int n, const double* f, const Lay& fl, double* partials,
                         int* count, hipStream_t s) {
@@ -2703,6 +2857,63 @@ static hipError_t tb3_tz(int n, int it, int len, double omega, const void* eo, v
 #undef TB3_ARGS
 }
 
+size_t lattice_3d_tiled_lds(int prec, int it) {
+  const size_t S = size_t(LT_B + 2 * it), SC = S / 2 + 2;
+  return (3 * S * S * S + 2 * SC * SC * SC) * (prec == PREC_F64 ? 8 : 4);
+}
+
+template <typename T, bool ZERO, bool LAT, int IT>
+static hipError_t lt3_t(int n, double omega, const void* xo_, void* xn_, void* xp_, const Lay& cl,
+                        const void* rm_, const Lay& rl, const L1Src<T>& l1, const int* done, hipStream_t s) {
+  using C = typename Tr<T>::C;
+  const T* xo = xo_ ? static_cast<const T*>(xo_) + cl.off : nullptr;
+  T* xn = static_cast<T*>(xn_) + cl.off;
+  T* xp = static_cast<T*>(xp_) + cl.off;
+  const T* rm = static_cast<const T*>(rm_) + rl.off;
+  const double h = 1.0 / double(n - 1);
+  const C w = C(omega / 6.0), hl2 = C(h * h);
+  const int nb = (n - 2 + LT_B - 1) / LT_B;
+  const size_t lds = lattice_3d_tiled_lds(sizeof(T) == 8 ? PREC_F64 : PREC_F32, IT);
+  hipError_t a = allow_lds(k_lattice_3d_tiled<T, ZERO, LAT, IT>, lds);
+  if (a != hipSuccess) return a;
+  HOMG_LAUNCH_SMEM((k_lattice_3d_tiled<T, ZERO, LAT, IT>), dim3(unsigned(nb) * nb * nb), dim3(LT_NT), lds, s, xo,
+                   xn, xp, cl.pitch, cl.plane, rm, rl.pitch, rl.plane, n, nb, w, hl2, done, l1);
+}
+
+template <typename T, int IT>
+static hipError_t lt3_it(int n, double omega, const void* xo, void* xn, void* xp, const Lay& cl, const void* rm,
+                         const Lay& rl, bool zero, const L1State* l1, const int* done, hipStream_t s) {
+  const L1Src<T> v = l1_src<T>(l1);
+  if (l1) return lt3_t<T, false, true, IT>(n, omega, xo, xn, xp, cl, rm, rl, v, done, s);
+  if (zero) return lt3_t<T, true, false, IT>(n, omega, xo, xn, xp, cl, rm, rl, v, done, s);
+  return lt3_t<T, false, false, IT>(n, omega, xo, xn, xp, cl, rm, rl, v, done, s);
+}
+
+template <typename T>
+static hipError_t lt3_tz(int n, int it, double omega, const void* xo, void* xn, void* xp, const Lay& cl,
+                         const void* rm, const Lay& rl, bool zero, const L1State* l1, const int* done,
+                         hipStream_t s) {
+  switch (it) {
+    case 1: return lt3_it<T, 1>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+    case 2: return lt3_it<T, 2>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+    case 3: return lt3_it<T, 3>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+    default: return lt3_it<T, 4>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+  }
+}
+
+hipError_t launch_lattice_3d_tiled(int prec, int n, int it, double omega, const void* xo, void* xn, void* xprev,
+                                   const Lay& cl, const void* rm, const Lay& rl, bool zero, const L1State* l1,
+                                   const int* done, hipStream_t s) {
+  if (n < 3 || it < 1 || it > LT_MAX_IT || !xn || !xprev || (l1 && zero) || (!l1 && !zero && !xo) ||
+      !l1_ok(l1, 3, n) || xn == xo || xprev == xo || xn == xprev)
+    return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return lt3_tz<double>(n, it, omega, xo, xn, xprev, cl, rm, rl, zero, l1, done, s);
+    case PREC_F32: return lt3_tz<float>(n, it, omega, xo, xn, xprev, cl, rm, rl, zero, l1, done, s);
+    default: return lt3_tz<bf16>(n, it, omega, xo, xn, xprev, cl, rm, rl, zero, l1, done, s);
+  }
+}
+
 hipError_t launch_tb_3d(int prec, int n, int it, double omega, const void* eo, void* en, void* eprev,
                         const Lay& el, const void* rm, const Lay& rl, double* u, const Lay& ul,
                         bool zero, bool accum, bool compact, const int* done, hipStream_t s, int len,
@@ -2876,13 +3087,6 @@ size_t lattice_small_lds(int prec, int d, int nm, bool var) {
   size_t b = 3 * cnt * cs;
   if (var) b = ((b + 15) & ~size_t(15)) + cnt * 8;
   return b;
-}
-
-template <typename K>
-static hipError_t allow_lds(K kernel, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 template <typename T, bool ZERO>
