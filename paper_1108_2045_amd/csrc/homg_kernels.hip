@@ -146,6 +146,12 @@ __device__ __forceinline__ double lane_next_or(double edge, double v) {
   const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(int(e >> 32), int(b >> 32), 0x130, 0xf, 0xf, false));
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
+__device__ __forceinline__ float lane_prev_or(float edge, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_next_or(float edge, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
 
 // ------------------------------------------------------------ reductions
 
@@ -1204,37 +1210,49 @@ __device__ __forceinline__ void tile_sweep_3d_l0(
     const T* __restrict__ r, int64_t rp, int64_t rpl, double* __restrict__ u, int64_t up,
     int64_t upl, int n, int len, typename Tr<T>::C w, typename Tr<T>::C hl2) {
   using C = typename Tr<T>::C;
-  const int x = 1 + blockIdx.x * BX3 + threadIdx.x;
-  const int yb = 1 + (blockIdx.y * BY3 + threadIdx.y) * R3Y;
-  if (x > n - 2 || yb > n - 2) return;
-  const int z0 = 1 + blockIdx.z * len;
+  // one-dimensional grid in XCD order (the tiles that share halo rows and
+  // planes meet in one XCD's L2), walks of len planes, as the 3D residual
+  const int gx = (n - 2 + BX3 - 1) / BX3, gy = (n - 2 + BY3 * R3Y - 1) / (BY3 * R3Y);
+  const int lg = int(xcd_order(blockIdx.x, gridDim.x));
+  const int bx = lg % gx, by = (lg / gx) % gy, bz = lg / (gx * gy);
+  const int lane = threadIdx.x;
+  const int x = 1 + bx * BX3 + lane;
+  const int yb = 1 + (by * BY3 + __builtin_amdgcn_readfirstlane(int(threadIdx.y))) * R3Y;
+  if (yb > n - 2) return;  // the whole wave
+  const int z0 = 1 + bz * len;
   const int z1 = min(n - 1, z0 + len);
+  // lanes past the last interior column keep walking (their values feed the
+  // neighbour lanes' x neighbours) and store nothing; x neighbours come from
+  // the neighbour lanes, the end lanes load their outside column
+  const bool xin = x <= n - 2;
+  const int xc = min(x, n - 1);
+  const bool edge = lane == 0 || lane == BX3 - 1;
+  const int xe = lane == 0 ? x - 1 : min(x + 1, n - 1);
   // rows yb .. yb+R3Y-1; those past n-2 are clamped (computed, not stored)
   C c[R3Y], zm[R3Y];
 #pragma unroll
   for (int k = 0; k < R3Y; ++k) {
-    const int64_t col = int64_t(min(yb + k, n - 2)) * ep + x;
+    const int64_t col = int64_t(min(yb + k, n - 2)) * ep + xc;
     c[k] = zm[k] = C(0);
     if (!(MODE & SW_ZERO_OLD)) {
       zm[k] = ld(eo + int64_t(z0 - 1) * epl + col);
       c[k] = ld(eo + int64_t(z0) * epl + col);
     }
   }
-  const int64_t ylo = int64_t(yb - 1) * ep + x;
-  const int64_t yhi = int64_t(min(yb + R3Y, n - 1)) * ep + x;
+  const int64_t ylo = int64_t(yb - 1) * ep + xc;
+  const int64_t yhi = int64_t(min(yb + R3Y, n - 1)) * ep + xc;
   for (int z = z0; z < z1; ++z) {
-    C zp[R3Y], xm[R3Y], xp[R3Y], rv[R3Y];
+    C zp[R3Y], ev[R3Y], rv[R3Y];
     C below = C(0), above = C(0);
 #pragma unroll
     for (int k = 0; k < R3Y; ++k) {
       const int yk = min(yb + k, n - 2);
-      rv[k] = ld(r + int64_t(z) * rpl + int64_t(yk) * rp + x);
-      zp[k] = xm[k] = xp[k] = C(0);
+      rv[k] = ld(r + int64_t(z) * rpl + int64_t(yk) * rp + xc);
+      zp[k] = ev[k] = C(0);
       if (!(MODE & SW_ZERO_OLD)) {
-        const T* q = eo + int64_t(z) * epl + int64_t(yk) * ep + x;
-        zp[k] = ld(q + epl);
-        xm[k] = ld(q - 1);
-        xp[k] = ld(q + 1);
+        const T* q = eo + int64_t(z) * epl + int64_t(yk) * ep;
+        zp[k] = ld(q + epl + xc);
+        if (edge) ev[k] = ld(q + xe);
       }
     }
     if (!(MODE & SW_ZERO_OLD)) {
@@ -1247,8 +1265,10 @@ __device__ __forceinline__ void tile_sweep_3d_l0(
       // the row above is the next owned row, or the group's upper neighbour
       // (the boundary row, 0, when the group ends at n-2)
       const C yp = k == R3Y - 1 ? above : (yb + k + 1 <= n - 2 ? c[k + 1] : C(0));
-      const C v = relax_const<C>(c[k], ((xm[k] + xp[k]) + (ym + yp)) + (zm[k] + zp[k]), rv[k], w, hl2, C(6));
-      if (yb + k <= n - 2) {
+      const C xm = lane_prev_or(ev[k], c[k]);  // lane 0: ev
+      const C xp = lane_next_or(ev[k], c[k]);  // lane 63: ev
+      const C v = relax_const<C>(c[k], ((xm + xp) + (ym + yp)) + (zm[k] + zp[k]), rv[k], w, hl2, C(6));
+      if (xin && yb + k <= n - 2) {
         if (MODE & SW_ACCUM)
           add_to(u + int64_t(z) * upl + int64_t(yb + k) * up + x, double(v));
         else
@@ -2662,9 +2682,11 @@ static hipError_t sweep_tm(int d, int n, int m, double omega, const void* eo_, v
                 rl.pitch, a, al.pitch, uu, ul.pitch, n, len, m, w, hl2, done);
   }
   const C w = C(omega / 6.0);
-  // level 0: lanes own R3Y rows each, walks of 8 planes
-  const int inner = n - 2, len0 = inner < 8 ? inner : 8;
-  const dim3 g0((inner + BX3 - 1) / BX3, (inner + BY3 * R3Y - 1) / (BY3 * R3Y), (inner + len0 - 1) / len0);
+  // level 0: lanes own R3Y rows each, walks of RES3_LEN planes, one
+  // XCD-ordered dimension
+  const int inner = n - 2, len0 = inner < RES3_LEN ? inner : RES3_LEN;
+  const dim3 g0(unsigned((inner + BX3 - 1) / BX3) * unsigned((inner + BY3 * R3Y - 1) / (BY3 * R3Y)) *
+                unsigned((inner + len0 - 1) / len0));
   if (m == 0 && compact)
     HOMG_LAUNCH((k_lattice_sweep_3d<T, MODE>), g0, dim3(BX3, BY3), s, eo, en, el.pitch, el.plane,
                 rm, rl.pitch, rl.plane, uu, ul.pitch, ul.plane, n, len0, w, hl2, done);
