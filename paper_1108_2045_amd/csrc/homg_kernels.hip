@@ -700,25 +700,33 @@ __device__ __forceinline__ void emit_2d(T* en, int64_t eoff, double* u, int64_t 
 
 // Level 0: every interior node relaxes (plain damped Jacobi).  The walk
 // takes U rows per step and issues all their loads before any arithmetic,
-// so each lane keeps several rows of memory traffic in flight.
+// so each lane keeps several rows of memory traffic in flight.  Constant
+// coefficient: the x neighbours come from the neighbour lanes (DPP wave
+// shifts; the wave is 64 consecutive columns), the end lanes load their
+// outside column; lanes past the last interior column (xc clamped) walk
+// along and store nothing.
 template <typename T, int MODE, bool VAR, int U>
 __device__ __forceinline__ void rows_2d_l0(
     const T* __restrict__ eo, T* __restrict__ en, int64_t ep, const T* __restrict__ r,
     int64_t rp, const double* __restrict__ a, int64_t ap, double* __restrict__ u, int64_t up,
-    int x, int y, typename Tr<T>::C w, typename Tr<T>::C hl2, typename Tr<T>::C& ym,
-    typename Tr<T>::C& c, double& aym, double& ac) {
+    int x, int xc, int xe, bool edge, bool xin, int y, typename Tr<T>::C w, typename Tr<T>::C hl2,
+    typename Tr<T>::C& ym, typename Tr<T>::C& c, double& aym, double& ac) {
   using C = typename Tr<T>::C;
-  C rv[U], xm[U], xp[U], yp[U];
+  C rv[U], xm[U], xp[U], yp[U], ev[U];
   double axm[U], axp[U], ayp[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {
-    rv[k] = ld(r + int64_t(y + k) * rp + x);
-    xm[k] = xp[k] = yp[k] = C(0);
+    rv[k] = ld(r + int64_t(y + k) * rp + xc);
+    xm[k] = xp[k] = yp[k] = ev[k] = C(0);
     if (!(MODE & SW_ZERO_OLD)) {
       const T* row = eo + int64_t(y + k) * ep;
-      yp[k] = ld(row + ep + x);
-      xm[k] = ld(row + x - 1);
-      xp[k] = ld(row + x + 1);
+      yp[k] = ld(row + ep + xc);
+      if (VAR) {
+        xm[k] = ld(row + x - 1);
+        xp[k] = ld(row + x + 1);
+      } else if (edge) {
+        ev[k] = ld(row + xe);
+      }
     }
     if (VAR) {
       const double* arow = a + int64_t(y + k) * ap;
@@ -735,9 +743,10 @@ __device__ __forceinline__ void rows_2d_l0(
       aym = ac;
       ac = ayp[k];
     } else {
-      v = relax_const<C>(c, (xm[k] + xp[k]) + (ym + yp[k]), rv[k], w, hl2, C(4));
+      const C xl = lane_prev_or(ev[k], c), xr = lane_next_or(ev[k], c);  // lane 0 / 63: ev
+      v = relax_const<C>(c, (xl + xr) + (ym + yp[k]), rv[k], w, hl2, C(4));
     }
-    emit_2d<T, MODE, VAR>(en, int64_t(y + k) * ep + x, u, int64_t(y + k) * up + x, v);
+    if (xin) emit_2d<T, MODE, VAR>(en, int64_t(y + k) * ep + x, u, int64_t(y + k) * up + x, v);
     ym = c;
     c = yp[k];
   }
@@ -751,12 +760,19 @@ __device__ __forceinline__ void tile_sweep_2d_l0(
   using C = typename Tr<T>::C;
   const int x = t2_x(bx);
   const int y0 = t2_y0(by, len);
-  if (x > n - 2 || y0 > n - 2) return;  // (the last block row may hold empty bands)
+  // (the last block row may hold empty bands; with a variable coefficient
+  // the lanes past the grid leave too, the x neighbours being loaded)
+  if (y0 > n - 2 || (VAR && x > n - 2)) return;
   const int y1 = min(n - 1, y0 + len);
+  const bool xin = x <= n - 2;
+  const int xc = min(x, n - 1);
+  const int lane = threadIdx.x & 63;
+  const bool edge = lane == 0 || lane == 63;
+  const int xe = lane == 0 ? x - 1 : min(x + 1, n - 1);
   C ym = C(0), c = C(0);
   if (!(MODE & SW_ZERO_OLD)) {
-    ym = ld(eo + int64_t(y0 - 1) * ep + x);
-    c = ld(eo + int64_t(y0) * ep + x);
+    ym = ld(eo + int64_t(y0 - 1) * ep + xc);
+    c = ld(eo + int64_t(y0) * ep + xc);
   }
   double aym = 0.0, ac = 0.0;
   if (VAR) {
@@ -766,9 +782,9 @@ __device__ __forceinline__ void tile_sweep_2d_l0(
   constexpr int U = 4;
   int y = y0;
   for (; y + U <= y1; y += U)
-    rows_2d_l0<T, MODE, VAR, U>(eo, en, ep, r, rp, a, ap, u, up, x, y, w, hl2, ym, c, aym, ac);
+    rows_2d_l0<T, MODE, VAR, U>(eo, en, ep, r, rp, a, ap, u, up, x, xc, xe, edge, xin, y, w, hl2, ym, c, aym, ac);
   for (; y < y1; ++y)
-    rows_2d_l0<T, MODE, VAR, 1>(eo, en, ep, r, rp, a, ap, u, up, x, y, w, hl2, ym, c, aym, ac);
+    rows_2d_l0<T, MODE, VAR, 1>(eo, en, ep, r, rp, a, ap, u, up, x, xc, xe, edge, xin, y, w, hl2, ym, c, aym, ac);
 }
 
 template <typename T, int MODE, bool VAR>
