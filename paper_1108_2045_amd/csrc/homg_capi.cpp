@@ -443,18 +443,21 @@ homg_status run_level(homg_ctx* h, int m, int it, bool first, bool last, int nex
     int src = 0;
     xprev = nullptr;
     const int gmax = h->d == 2 ? TB_MAX_IT : TB3_MAX_IT;
-    const bool tiled = h->d == 3 && nm <= LT_MAX_SIDE &&
-                       lattice_3d_tiled_lds(h->prec, std::min(it, LT_MAX_IT)) <= h->lds_limit;
+    const bool tiled = (h->d == 3 && nm <= LT_MAX_SIDE &&
+                        lattice_3d_tiled_lds(h->prec, std::min(it, LT_MAX_IT)) <= h->lds_limit) ||
+                       (h->d == 2 && nm <= LT2_MAX_SIDE);
     for (int t0 = 0; tiled && t0 < it; t0 += LT_MAX_IT) {
-      // small 3D lattice: up to four iterations per launch on LDS tiles
-      // (x_{it-1} of every launch into the third array; the last one's is kept)
+      // small lattice: up to four iterations per launch on LDS tiles (x_{it-1}
+      // of every launch into the third array; the last one's is kept)
       const int g = std::min(LT_MAX_IT, it - t0);
       const bool zero = first && t0 == 0;
       const L1State* ls = t0 == 0 ? l1 : nullptr;
       LAUNCH_K(h, s, K_LATTICE, m,
                SW_TBLOCK | (zero ? SW_ZERO_OLD : 0) | ((g - 1) << 4) | 64 | (ls ? 128 : 0) | 256,
-               launch_lattice_3d_tiled(h->prec, nm, g, h->omega, (zero || ls) ? nullptr : X[src], X[1 - src],
-                                       h->xp3[m], cl, h->r[m], h->rl[m], zero, ls, done, s));
+               h->d == 3 ? launch_lattice_3d_tiled(h->prec, nm, g, h->omega, (zero || ls) ? nullptr : X[src],
+                                                   X[1 - src], h->xp3[m], cl, h->r[m], h->rl[m], zero, ls, done, s)
+                         : launch_lattice_2d_tiled(h->prec, nm, g, h->omega, (zero || ls) ? nullptr : X[src],
+                                                   X[1 - src], h->xp3[m], cl, h->r[m], h->rl[m], zero, ls, done, s));
       xprev = h->xp3[m];
       src = 1 - src;
     }

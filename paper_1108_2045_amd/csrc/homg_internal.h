@@ -145,6 +145,11 @@ size_t lattice_3d_tiled_lds(int prec, int it);
 hipError_t launch_lattice_3d_tiled(int prec, int n, int it, double omega, const void* xo, void* xn, void* xprev,
                                    const Lay& cl, const void* rm, const Lay& rl, bool zero, const L1State* l1,
                                    const int* done, hipStream_t s);
+// The same on a 2D compact lattice (blocks of 24^2 owned nodes).
+constexpr int LT2_MAX_SIDE = 513;  // the solver uses it on lattices up to this side
+hipError_t launch_lattice_2d_tiled(int prec, int n, int it, double omega, const void* xo, void* xn, void* xprev,
+                                   const Lay& cl, const void* rm, const Lay& rl, bool zero, const L1State* l1,
+                                   const int* done, hipStream_t s);
 // The same on the compact lattice of a coarse level (side nm): x_it into en
 // and, when eprev is not null, x_{it-1} into eprev (layout cl); l1: x_0
 // from the next coarser level's state.

@@ -2284,6 +2284,94 @@ __global__ __launch_bounds__(LT_NT) void k_lattice_3d_tiled(
   }
 }
 
+// The same for a 2D compact lattice: blocks of LT2_B^2 owned nodes with a
+// halo of IT nodes, one lane per tile node (1024 lanes for four
+// iterations).  Interpolation, node formula and rounding are those of
+// k_lattice_2d_tb and k_level_transfer_2d.
+constexpr int LT2_B = 24;
+constexpr int LT2_NT = 1024;
+
+template <typename T, bool ZERO, bool LAT, int IT>
+__global__ __launch_bounds__(LT2_NT) void k_lattice_2d_tiled(
+    const T* __restrict__ xo, T* __restrict__ xn, T* __restrict__ xp, int64_t cp, const T* __restrict__ r,
+    int64_t rp, int n, int nb, typename Tr<T>::C w, typename Tr<T>::C hl2, const int* __restrict__ done,
+    L1Src<T> l1) {
+  using C = typename Tr<T>::C;
+  if (*done) return;
+  constexpr int S = LT2_B + 2 * IT, S2 = S * S, SC = S / 2 + 2, SC2 = SC * SC;
+  __shared__ C X0[S2], X1[S2], R[S2], Pc[LAT ? SC2 : 1], Cc[LAT ? SC2 : 1];
+  const int lb = int(xcd_order(blockIdx.x, gridDim.x));
+  const int bx = lb % nb, by = lb / nb;
+  // tile node (i, j) is lattice node (gx0 + i, gy0 + j)
+  const int gx0 = LT2_B * bx + 1 - IT, gy0 = LT2_B * by + 1 - IT;
+  const int hi = n - 1;
+  auto interior = [&](int gx, int gy) { return gx >= 1 && gx <= n - 2 && gy >= 1 && gy <= n - 2; };
+  const int q = threadIdx.x;  // one tile node per lane (S2 <= LT2_NT)
+  const int qi = q % S, qj = q / S;
+  const bool live = q < S2;
+  const int gx = gx0 + qi, gy = gy0 + qj;
+  if (live) {  // r and (neither ZERO nor LAT) x_0: clamped loads
+    const int64_t cx = min(max(gx, 0), hi), cy = min(max(gy, 0), hi);
+    R[q] = ld(r + cy * rp + cx);
+    if (!ZERO && !LAT) {
+      const C v = ld(xo + cy * cp + cx);
+      X0[q] = interior(gx, gy) ? v : C(0);
+    }
+    if (ZERO) X0[q] = C(0);
+  }
+  const int cx0 = max(gx0, 0) >> 1, cy0 = max(gy0, 0) >> 1;
+  if (LAT && q < SC2) {
+    const int nc = (n - 1) / 2 + 1;
+    const T* pp = l1.zero_old ? l1.cur : l1.prev;  // (x_{it-1} = 0: loads a valid array, drops it)
+    const int64_t o = int64_t(min(cy0 + q / SC, nc - 1)) * l1.cp + min(cx0 + q % SC, nc - 1);
+    const C pv = ld(pp + o);
+    Pc[q] = l1.zero_old ? C(0) : pv;
+    Cc[q] = ld(l1.cur + o);
+  }
+  __syncthreads();
+  if (LAT) {
+    if (live) {
+      C v = C(0);
+      if (interior(gx, gy)) {
+        const int c0 = ((gy >> 1) - cy0) * SC + ((gx >> 1) - cx0);
+        if (!(gx & 1) && !(gy & 1)) {
+          v = Cc[c0];
+        } else {
+          const C tx = C(gx & 1) * C(0.5), ty = C(gy & 1) * C(0.5);
+          const C top = lerp(Pc[c0], Pc[c0 + 1], tx), bot = lerp(Pc[c0 + SC], Pc[c0 + SC + 1], tx);
+          v = lerp(top, bot, ty);
+        }
+        v = rnd<T>(v);
+      }
+      X0[q] = v;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 1; t <= IT; ++t) {
+    const C* __restrict__ src = (t & 1) ? X0 : X1;
+    C* __restrict__ dst = (t & 1) ? X1 : X0;
+    // valid region after this iteration: tile nodes t .. S - 1 - t per axis
+    if (live && qi >= t && qi < S - t && qj >= t && qj < S - t) {
+      C v = C(0);
+      const bool in = interior(gx, gy);
+      if (in) {
+        v = relax_const<C>(src[q], (src[q - 1] + src[q + 1]) + (src[q - S] + src[q + S]), R[q], w, hl2, C(4));
+        dst[q] = rnd<T>(v);
+      } else {
+        dst[q] = C(0);
+      }
+      // the last iteration's region is the owned block: x_{IT-1} and x_IT
+      if (t == IT && in) {
+        const int64_t o = int64_t(gy) * cp + gx;
+        st(xn + o, v);
+        st(xp + o, src[q]);
+      }
+    }
+    if (t < IT) __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ multi-level restriction
 // P consecutive full-weighting restrictions of the cycle's chain, r_a ->
 // r_{a+1} -> ... -> r_{a+P}, in one launch: the chain's coarse end, where
@@ -2893,6 +2981,55 @@ static hipError_t tb3_tz(int n, int it, int len, double omega, const void* eo, v
     return zero ? tb3_t<T, true, false, true, false>(TB3_ARGS) : tb3_t<T, false, false, true, false>(TB3_ARGS);
   return zero ? tb3_t<T, true, false, false, false>(TB3_ARGS) : tb3_t<T, false, false, false, false>(TB3_ARGS);
 #undef TB3_ARGS
+}
+
+template <typename T, bool ZERO, bool LAT, int IT>
+static hipError_t lt2_t(int n, double omega, const void* xo_, void* xn_, void* xp_, const Lay& cl,
+                        const void* rm_, const Lay& rl, const L1Src<T>& l1, const int* done, hipStream_t s) {
+  using C = typename Tr<T>::C;
+  const T* xo = xo_ ? static_cast<const T*>(xo_) + cl.off : nullptr;
+  T* xn = static_cast<T*>(xn_) + cl.off;
+  T* xp = static_cast<T*>(xp_) + cl.off;
+  const T* rm = static_cast<const T*>(rm_) + rl.off;
+  const double h = 1.0 / double(n - 1);
+  const C w = C(omega / 4.0), hl2 = C(h * h);
+  const int nb = (n - 2 + LT2_B - 1) / LT2_B;
+  HOMG_LAUNCH((k_lattice_2d_tiled<T, ZERO, LAT, IT>), dim3(unsigned(nb) * nb), dim3(LT2_NT), s, xo, xn, xp,
+              cl.pitch, rm, rl.pitch, n, nb, w, hl2, done, l1);
+}
+
+template <typename T, int IT>
+static hipError_t lt2_it(int n, double omega, const void* xo, void* xn, void* xp, const Lay& cl, const void* rm,
+                         const Lay& rl, bool zero, const L1State* l1, const int* done, hipStream_t s) {
+  const L1Src<T> v = l1_src<T>(l1);
+  if (l1) return lt2_t<T, false, true, IT>(n, omega, xo, xn, xp, cl, rm, rl, v, done, s);
+  if (zero) return lt2_t<T, true, false, IT>(n, omega, xo, xn, xp, cl, rm, rl, v, done, s);
+  return lt2_t<T, false, false, IT>(n, omega, xo, xn, xp, cl, rm, rl, v, done, s);
+}
+
+template <typename T>
+static hipError_t lt2_tz(int n, int it, double omega, const void* xo, void* xn, void* xp, const Lay& cl,
+                         const void* rm, const Lay& rl, bool zero, const L1State* l1, const int* done,
+                         hipStream_t s) {
+  switch (it) {
+    case 1: return lt2_it<T, 1>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+    case 2: return lt2_it<T, 2>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+    case 3: return lt2_it<T, 3>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+    default: return lt2_it<T, 4>(n, omega, xo, xn, xp, cl, rm, rl, zero, l1, done, s);
+  }
+}
+
+hipError_t launch_lattice_2d_tiled(int prec, int n, int it, double omega, const void* xo, void* xn, void* xprev,
+                                   const Lay& cl, const void* rm, const Lay& rl, bool zero, const L1State* l1,
+                                   const int* done, hipStream_t s) {
+  if (n < 3 || it < 1 || it > LT_MAX_IT || !xn || !xprev || (l1 && zero) || (!l1 && !zero && !xo) ||
+      !l1_ok(l1, 2, n) || xn == xo || xprev == xo || xn == xprev)
+    return hipErrorInvalidValue;
+  switch (prec) {
+    case PREC_F64: return lt2_tz<double>(n, it, omega, xo, xn, xprev, cl, rm, rl, zero, l1, done, s);
+    case PREC_F32: return lt2_tz<float>(n, it, omega, xo, xn, xprev, cl, rm, rl, zero, l1, done, s);
+    default: return lt2_tz<bf16>(n, it, omega, xo, xn, xprev, cl, rm, rl, zero, l1, done, s);
+  }
 }
 
 size_t lattice_3d_tiled_lds(int prec, int it) {
