@@ -2148,14 +2148,20 @@ __global__ __launch_bounds__(SMALL_NT) void k_coarse_tail(
 // (its x_it at shared lattice nodes, else the trilinear interpolant of its
 // x_{it-1}); writes x_IT to xn and x_{IT-1} to xp at the owned nodes.  The
 // node formula, summation order, interpolation and rounding are those of
-// k_lattice_3d_tb and k_level_transfer_3d, so the bits are theirs.
-constexpr int LT_B = 8;      // owned nodes per axis of a block
+// k_lattice_3d_tb and k_level_transfer_3d, so the bits are theirs.  Each
+// lane keeps its tile nodes (up to four) for every phase, with r there in
+// registers, and the coarser level's neighbourhood sits in the second
+// iterate's array until the first iteration: 64 KB of LDS in FP64, two
+// workgroups per CU.
+constexpr int LT_B = 8;  // owned nodes per axis of a block
 constexpr int LT_NT = 1024;
-constexpr int LT_LB = 4;     // global loads a lane issues before writing LDS (a 16^3 tile: all of them)
 
 template <int IT>
 __host__ __device__ constexpr int lt_side() { return LT_B + 2 * IT; }
 __host__ __device__ constexpr int lt_cside(int S) { return S / 2 + 2; }
+// tile nodes per lane (a 16^3 tile for four iterations: four)
+template <int IT>
+__host__ __device__ constexpr int lt_per_lane() { return (lt_side<IT>() * lt_side<IT>() * lt_side<IT>() + LT_NT - 1) / LT_NT; }
 
 template <typename T, bool ZERO, bool LAT, int IT>
 __global__ __launch_bounds__(LT_NT) void k_lattice_3d_tiled(
@@ -2165,117 +2171,108 @@ __global__ __launch_bounds__(LT_NT) void k_lattice_3d_tiled(
   using C = typename Tr<T>::C;
   if (*done) return;
   constexpr int S = lt_side<IT>(), S2 = S * S, S3 = S2 * S, SC = lt_cside(S), SC2 = SC * SC, SC3 = SC2 * SC;
+  constexpr int U = lt_per_lane<IT>();
+  static_assert(2 * SC3 <= S3, "the coarser level's neighbourhood fits in the second iterate's array");
   extern __shared__ __align__(16) unsigned char smem[];
   C* X0 = reinterpret_cast<C*>(smem);
   C* X1 = X0 + S3;
-  C* R = X1 + S3;
-  C* Pc = R + S3;  // LAT: the coarser level's x_{it-1} and x_it around the block
-  C* Cc = Pc + SC3;
+  C* Pc = X1;  // LAT: the coarser level's x_{it-1} and x_it around the block,
+  C* Cc = Pc + SC3;  // in the second iterate's array until the first iteration
   const int lb = int(xcd_order(blockIdx.x, gridDim.x));
   const int bx = lb % nb, by = (lb / nb) % nb, bz = lb / (nb * nb);
   // tile node (i, j, k) is lattice node (gx0 + i, gy0 + j, gz0 + k)
   const int gx0 = LT_B * bx + 1 - IT, gy0 = LT_B * by + 1 - IT, gz0 = LT_B * bz + 1 - IT;
   const int hi = n - 1;
-  auto interior = [&](int gx, int gy, int gz) {
-    return gx >= 1 && gx <= n - 2 && gy >= 1 && gy <= n - 2 && gz >= 1 && gz <= n - 2;
-  };
-  // r and (neither ZERO nor LAT) x_0 on the tile; clamped loads, nodes off
-  // the lattice are never read by an interior node's update
-  for (int i0 = 0; i0 < S3; i0 += LT_LB * LT_NT) {
-    C rv[LT_LB], xv[LT_LB];
+  // the lane's tile nodes q = lane + u LT_NT (fixed for every phase), their
+  // coordinates, and r there (in registers: each is read by its own lane)
+  int qi[U], qj[U], qk[U];
+  bool live[U], in[U];
+  C rv[U], xv[U];
 #pragma unroll
-    for (int u = 0; u < LT_LB; ++u) {
-      const int q = min(i0 + u * LT_NT + int(threadIdx.x), S3 - 1);
-      const int k = q / S2, j = (q / S) % S, i = q % S;
-      const int64_t gx = min(max(gx0 + i, 0), hi), gy = min(max(gy0 + j, 0), hi), gz = min(max(gz0 + k, 0), hi);
-      rv[u] = ld(r + gz * rpl + gy * rp + gx);
-      if (!ZERO && !LAT) xv[u] = ld(xo + gz * cpl + gy * cp + gx);
-    }
-#pragma unroll
-    for (int u = 0; u < LT_LB; ++u) {
-      const int q = i0 + u * LT_NT + int(threadIdx.x);
-      if (q < S3) {
-        R[q] = rv[u];
-        if (!ZERO && !LAT) {
-          const int k = q / S2, j = (q / S) % S, i = q % S;
-          X0[q] = interior(gx0 + i, gy0 + j, gz0 + k) ? xv[u] : C(0);
-        }
-      }
-    }
+  for (int u = 0; u < U; ++u) {
+    const int q = int(threadIdx.x) + u * LT_NT;
+    live[u] = q < S3;
+    const int qc = min(q, S3 - 1);
+    qk[u] = qc / S2;
+    qj[u] = (qc / S) % S;
+    qi[u] = qc % S;
+    const int gx = gx0 + qi[u], gy = gy0 + qj[u], gz = gz0 + qk[u];
+    in[u] = live[u] && gx >= 1 && gx <= n - 2 && gy >= 1 && gy <= n - 2 && gz >= 1 && gz <= n - 2;
+    const int64_t cx = min(max(gx, 0), hi), cy = min(max(gy, 0), hi), cz = min(max(gz, 0), hi);
+    rv[u] = ld(r + cz * rpl + cy * rp + cx);
+    xv[u] = C(0);
+    if (!ZERO && !LAT) xv[u] = ld(xo + cz * cpl + cy * cp + cx);
   }
-  if (ZERO)
-    for (int q = threadIdx.x; q < S3; q += LT_NT) X0[q] = C(0);
-  // LAT: the coarser level's state from coarse node (cx0, cy0, cz0) on
   const int cx0 = max(gx0, 0) >> 1, cy0 = max(gy0, 0) >> 1, cz0 = max(gz0, 0) >> 1;
   if (LAT) {
     const int nc = (n - 1) / 2 + 1;
     const T* pp = l1.zero_old ? l1.cur : l1.prev;  // (x_{it-1} = 0: loads a valid array, drops it)
-    for (int i0 = 0; i0 < SC3; i0 += (LT_LB / 2) * LT_NT) {
-      C pv[LT_LB / 2], cv[LT_LB / 2];
+    constexpr int UC = (SC3 + LT_NT - 1) / LT_NT;
+    C pv[UC], cv[UC];
 #pragma unroll
-      for (int u = 0; u < LT_LB / 2; ++u) {
-        const int q = min(i0 + u * LT_NT + int(threadIdx.x), SC3 - 1);
-        const int k = q / SC2, j = (q / SC) % SC, i = q % SC;
-        const int64_t o = int64_t(min(cz0 + k, nc - 1)) * l1.cpl + int64_t(min(cy0 + j, nc - 1)) * l1.cp +
-                          min(cx0 + i, nc - 1);
-        pv[u] = l1.zero_old ? C(0) : ld(pp + o);
-        cv[u] = ld(l1.cur + o);
-      }
-#pragma unroll
-      for (int u = 0; u < LT_LB / 2; ++u) {
-        const int q = i0 + u * LT_NT + int(threadIdx.x);
-        if (q < SC3) {
-          Pc[q] = pv[u];
-          Cc[q] = cv[u];
-        }
-      }
+    for (int u = 0; u < UC; ++u) {
+      const int q = min(int(threadIdx.x) + u * LT_NT, SC3 - 1);
+      const int k = q / SC2, j = (q / SC) % SC, i = q % SC;
+      const int64_t o = int64_t(min(cz0 + k, nc - 1)) * l1.cpl + int64_t(min(cy0 + j, nc - 1)) * l1.cp +
+                        min(cx0 + i, nc - 1);
+      pv[u] = ld(pp + o);
+      cv[u] = ld(l1.cur + o);
     }
-  }
-  __syncthreads();
-  if (LAT) {
-    for (int q = threadIdx.x; q < S3; q += LT_NT) {
-      const int k = q / S2, j = (q / S) % S, i = q % S;
-      const int gx = gx0 + i, gy = gy0 + j, gz = gz0 + k;
-      C v = C(0);
-      if (interior(gx, gy, gz)) {
-        const int c0 = ((gz >> 1) - cz0) * SC2 + ((gy >> 1) - cy0) * SC + ((gx >> 1) - cx0);
-        if (!(gx & 1) && !(gy & 1) && !(gz & 1)) {
-          v = Cc[c0];
-        } else {
-          const C tx = C(gx & 1) * C(0.5), ty = C(gy & 1) * C(0.5), tz = C(gz & 1) * C(0.5);
-          const C* p = Pc + c0;
-          const C* q2 = p + SC2;
-          const C top = lerp(lerp(p[0], p[1], tx), lerp(p[SC], p[SC + 1], tx), ty);
-          const C bot = lerp(lerp(q2[0], q2[1], tx), lerp(q2[SC], q2[SC + 1], tx), ty);
-          v = lerp(top, bot, tz);
-        }
-        v = rnd<T>(v);
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int q = int(threadIdx.x) + u * LT_NT;
+      if (q < SC3) {
+        Pc[q] = l1.zero_old ? C(0) : pv[u];
+        Cc[q] = cv[u];
       }
-      X0[q] = v;
     }
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!in[u]) continue;
+      const int gx = gx0 + qi[u], gy = gy0 + qj[u], gz = gz0 + qk[u];
+      const int c0 = ((gz >> 1) - cz0) * SC2 + ((gy >> 1) - cy0) * SC + ((gx >> 1) - cx0);
+      C v;
+      if (!(gx & 1) && !(gy & 1) && !(gz & 1)) {
+        v = Cc[c0];
+      } else {
+        const C tx = C(gx & 1) * C(0.5), ty = C(gy & 1) * C(0.5), tz = C(gz & 1) * C(0.5);
+        const C* p = Pc + c0;
+        const C* q2 = p + SC2;
+        const C top = lerp(lerp(p[0], p[1], tx), lerp(p[SC], p[SC + 1], tx), ty);
+        const C bot = lerp(lerp(q2[0], q2[1], tx), lerp(q2[SC], q2[SC + 1], tx), ty);
+        v = lerp(top, bot, tz);
+      }
+      xv[u] = rnd<T>(v);
+    }
+    // (Pc and Cc live in X1, which the first iteration writes only after the
+    // barrier that follows the writes of X0 below)
   }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (live[u]) X0[int(threadIdx.x) + u * LT_NT] = in[u] ? xv[u] : C(0);
+  __syncthreads();
 #pragma unroll
   for (int t = 1; t <= IT; ++t) {
     const C* __restrict__ src = (t & 1) ? X0 : X1;
     C* __restrict__ dst = (t & 1) ? X1 : X0;
-    const int V = S - 2 * t, V2 = V * V, V3 = V2 * V;  // valid region after this iteration
-    for (int q = threadIdx.x; q < V3; q += LT_NT) {
-      const int k = q / V2 + t, j = (q / V) % V + t, i = q % V + t;
-      const int c = (k * S + j) * S + i;
-      const int gx = gx0 + i, gy = gy0 + j, gz = gz0 + k;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // the valid region after this iteration: tile nodes t .. S - 1 - t per axis
+      if (!live[u] || qi[u] < t || qi[u] >= S - t || qj[u] < t || qj[u] >= S - t || qk[u] < t || qk[u] >= S - t)
+        continue;
+      const int c = int(threadIdx.x) + u * LT_NT;
       C v = C(0);
-      const bool in = interior(gx, gy, gz);
-      if (in) {
+      if (in[u]) {
         v = relax_const<C>(src[c], ((src[c - 1] + src[c + 1]) + (src[c - S] + src[c + S])) + (src[c - S2] + src[c + S2]),
-                           R[c], w, hl2, C(6));
+                           rv[u], w, hl2, C(6));
         dst[c] = rnd<T>(v);
       } else {
         dst[c] = C(0);
       }
       // the last iteration's region is the owned block: x_{IT-1} (src) and x_IT
-      if (t == IT && in) {
-        const int64_t o = int64_t(gz) * cpl + int64_t(gy) * cp + gx;
+      if (t == IT && in[u]) {
+        const int64_t o = int64_t(gz0 + qk[u]) * cpl + int64_t(gy0 + qj[u]) * cp + (gx0 + qi[u]);
         st(xn + o, v);
         st(xp + o, src[c]);
       }
@@ -3033,8 +3030,8 @@ hipError_t launch_lattice_2d_tiled(int prec, int n, int it, double omega, const 
 }
 
 size_t lattice_3d_tiled_lds(int prec, int it) {
-  const size_t S = size_t(LT_B + 2 * it), SC = S / 2 + 2;
-  return (3 * S * S * S + 2 * SC * SC * SC) * (prec == PREC_F64 ? 8 : 4);
+  const size_t S = size_t(LT_B + 2 * it);
+  return 2 * S * S * S * (prec == PREC_F64 ? 8 : 4);  // the two iterates (r stays in registers)
 }
 
 template <typename T, bool ZERO, bool LAT, int IT>
