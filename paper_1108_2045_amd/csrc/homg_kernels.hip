@@ -46,13 +46,12 @@ __device__ __forceinline__ float ld(const bf16* p) {
 // stream from about 5.2 to 7.5 TB/s).
 __device__ __forceinline__ void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
-// FP32 -> BF16, round to nearest even; NaN stays NaN.
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
+// FP32 -> BF16, round to nearest even; NaN stays NaN (quieted: the upper
+// half of its bits with bit 6 set).  One v_cvt_pk_bf16_f32: on MI355X it
+// gives exactly that result for every one of the 2^32 FP32 bit patterns,
+// where the same rounding done with integer operations took five or six
+// instructions per value.
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, __bf16(f)); }
 __device__ __forceinline__ void st(bf16* p, float v) { __builtin_nontemporal_store(f2bf(v), &p->bits); }
 // Write-only passes (a level's whole-grid write, the coarse-level sweeps)
 // keep ordinary stores: on MI355X a pure write stream runs faster with them

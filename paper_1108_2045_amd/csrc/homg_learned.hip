@@ -53,12 +53,9 @@ struct bf16s {
 __device__ __forceinline__ double ldv(const double* p) { return *p; }
 __device__ __forceinline__ float ldv(const float* p) { return *p; }
 __device__ __forceinline__ float ldv(const bf16s* p) { return __uint_as_float(uint32_t(p->bits) << 16); }
-__device__ __forceinline__ uint16_t to_bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return uint16_t(u >> 16);
-}
+// FP32 -> BF16 bits, round to nearest even, NaN quieted (one
+// v_cvt_pk_bf16_f32, which rounds exactly so on every FP32 bit pattern).
+__device__ __forceinline__ uint16_t to_bf16_bits(float f) { return __builtin_bit_cast(uint16_t, __bf16(f)); }
 __device__ __forceinline__ void stv(double* p, double v) { *p = v; }
 __device__ __forceinline__ void stv(float* p, float v) { *p = v; }
 __device__ __forceinline__ void stv(bf16s* p, float v) { p->bits = to_bf16_bits(v); }
